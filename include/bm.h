@@ -1,0 +1,183 @@
+/*
+ * bm.h - C ABI of the MI355X direct-indirect mixed Burton-Miller solver.
+ *
+ * The library assembles the Nystrom matrix of the direct-indirect mixed
+ * Burton-Miller equation for the 2D Helmholtz transmission problem and solves
+ * it with the identity-pivot block LU of Theorem (thm:LU) in Sec. 4.1 of
+ * Matsumoto & Matsushima, "Efficient LU factorization exploiting
+ * direct-indirect Burton-Miller equation for Helmholtz transmission problems".
+ *
+ * Problem (Sec. 2.1, eq. problem): find u0_sc in the exterior and u1_sc in the
+ * interior of a closed C^2 curve Gamma with
+ *   u := u0_sc + u_in = u1_sc,   q := (1/eps0) d_nu (u0_sc + u_in) = (1/eps1) d_nu u1_sc
+ * on Gamma, nu the normal pointing into the exterior, k_i = omega sqrt(eps_i).
+ *
+ * Discrete system (eq. dis_mixedBM), unknowns x = [u; q; phi] in C^{3N}:
+ *   [ I    0    M13 ] [u  ]   [b1]    M13 = -S_k1
+ *   [ 0    I    M23 ] [q  ] = [b2]    M23 = -(D*_k1 + I/2)/eps1
+ *   [ M31  M32  0   ] [phi]   [b3]    M31 = D_k0 - I/2 + beta N_k0
+ *                                     M32 = -eps0 (S_k0 + beta (D*_k0 + I/2))
+ * with S, D, D*, N the single, double, adjoint double and hypersingular layer
+ * operators (Sec. 2.2) discretised on N = 2n equispaced parameter nodes by
+ * Kress' logarithmic splitting (and the Hilbert-type weights for the
+ * hypersingular part).  For plane-wave incidence b1 = b2 = 0 and
+ * b3 = -u_in - beta d_nu u_in.
+ *
+ * The comparator is the ordinary Burton-Miller system (eq. dis_BM), unknowns
+ * [u; q] in C^{2N}, matrix [[M31, M32], [D_k1 + I/2, -eps1 S_k1]]; its second
+ * row is the interior Green identity with q = (1/eps1) d_nu u1.
+ *
+ * Conventions for every entry point:
+ *   - Complex numbers are two doubles (re, im): the layout of C99 double
+ *     _Complex, std::complex<double> and torch.complex128.
+ *   - Matrices are column-major with a leading dimension >= rows.
+ *   - Every array pointer is a DEVICE pointer on the current HIP device, unless
+ *     the argument says "host".  The library reads or writes it in stream
+ *     order on the stream given to bm_create; the caller keeps ownership and
+ *     must keep it alive until the stream has passed the call.
+ *   - Calls are asynchronous with respect to the host unless stated.
+ *   - Return value: BM_OK (0) or a negative bm_status; bm_strerror() names it.
+ *   - A bm_problem is not thread-safe; distinct problems are independent.
+ */
+#ifndef BM_MI355X_H
+#define BM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bm_problem bm_problem;
+
+enum bm_formulation {
+  BM_MIXED = 0,    /* 3N unknowns, block LU of Theorem (thm:LU)        */
+  BM_ORDINARY = 1  /* 2N unknowns, dense partial-pivot LU (comparator) */
+};
+
+enum bm_status {
+  BM_OK = 0,
+  BM_E_ARG = -1,     /* invalid argument (sizes, parameters, null pointers)    */
+  BM_E_NOMEM = -2,   /* device allocation failed                               */
+  BM_E_HIP = -3,     /* a HIP runtime call failed                              */
+  BM_E_STATE = -4,   /* call out of order (e.g. bm_solve before bm_block_lu)   */
+  BM_E_DEVICE = -5   /* a kernel reported an internal error (e.g. a bounded
+                        wait expired); results of the call are invalid         */
+};
+
+/* Maximum number of right-hand sides handled per internal pass; bm_solve and
+ * bm_far_field accept any nrhs and loop over chunks of this size. */
+#define BM_MAX_NRHS 32
+
+/* Boundary geometry: N nodes x(t_j), t_j = 2 pi j / N, counterclockwise, and the
+ * derivatives with respect to t.  Each pointer is a device array of 2N doubles,
+ * interleaved (x1, x2) per node.  x''' enters the diagonal of the Laplace part
+ * of the hypersingular operator. */
+typedef struct {
+  const double *x;
+  const double *dx;
+  const double *ddx;
+  const double *d3x;
+} bm_geometry;
+
+/* Physical parameters (Sec. 2.1 and 3.1).  k0, k1: exterior and interior
+ * wavenumbers, complex allowed with Re k > 0 and |Im k| <= Re k / 2.
+ * eps0, eps1 > 0: material constants.  beta: Burton-Miller constant,
+ * Im(beta) != 0. */
+typedef struct {
+  double k0_re, k0_im;
+  double k1_re, k1_im;
+  double eps0, eps1;
+  double beta_re, beta_im;
+} bm_params;
+
+/* Create a problem of N nodes (N even, 8 <= N <= 65536) for the given
+ * formulation.  Allocates all device memory the solver needs (mixed: the blocks
+ * Top = [M13; M23] (2N x N) and Bot = [M31 M32] (N x 2N), U33 and its factors;
+ * ordinary: the 2N x 2N matrix and its factors; workspace for BM_MAX_NRHS
+ * right-hand sides).  `hip_stream` is a hipStream_t (NULL = the default stream)
+ * on which every later call is ordered.  *out receives the handle.
+ * Errors: BM_E_ARG, BM_E_NOMEM, BM_E_HIP. */
+int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out);
+
+/* Release the problem and its device memory (after synchronising its stream). */
+void bm_destroy(bm_problem *p);
+
+/* Nystrom assembly (eq. dis_mixedBM / eq. dis_BM; kernels of Sec. 2.2 with
+ * G = (i/4) H0^(1)(k|x-y|)).  Mixed: fills Top and Bot.  Ordinary: fills the
+ * 2N x 2N matrix.  Geometry and parameters are read in stream order; the
+ * geometry arrays may be freed once the stream has passed the call.
+ * Errors: BM_E_ARG (null pointers, eps <= 0, Im beta == 0, k outside the
+ * supported sector). */
+int bm_assemble(bm_problem *p, const bm_geometry *geometry, const bm_params *params);
+
+/* Factorisation.  Mixed (Theorem thm:LU): U33 = -M31 M13 - M32 M23 = -Bot * Top
+ * (one complex GEMM, m = n = N, k = 2N), then partial-pivot LU of U33;
+ * the identity blocks are the pivots of the first 2N columns and the L31, L32,
+ * U13, U23 factors are the stored blocks themselves.  Ordinary: partial-pivot LU
+ * of the 2N x 2N matrix.  Pivoting: largest |Re| + |Im| in the column.
+ * If `info` is NULL the call is asynchronous.  Otherwise (host pointer) it
+ * synchronises the stream and stores the LAPACK-style info: 0, or j > 0 when
+ * the pivot of column j (1-based) of the factored matrix is exactly zero.
+ * Errors: BM_E_STATE before bm_assemble, BM_E_DEVICE. */
+int bm_block_lu(bm_problem *p, int32_t *info);
+
+/* Solve for `nrhs` right-hand sides (Corollary lem:for_ssm_RHS for the mixed
+ * form):  z3 = U33^{-1} (b3 - M31 b1 - M32 b2),  x1 = b1 - M13 z3,
+ * x2 = b2 - M23 z3,  x3 = z3.  B and X are (3N | 2N) x nrhs, column-major,
+ * leading dimensions ldb, ldx >= rows.  B is not modified; X may not alias B.
+ * Errors: BM_E_STATE before bm_block_lu, BM_E_ARG. */
+int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, int64_t ldx);
+
+/* Right-hand sides for incident plane waves u_in = exp(i k0 (cos th, sin th).x):
+ * b3 = -u_in - beta d_nu u_in, b1 = b2 = 0 (mixed) or [b3; 0] (ordinary).
+ * theta_inc: device array of nrhs angles.  B as in bm_solve. */
+int bm_rhs_plane_wave(bm_problem *p, int32_t nrhs, const double *theta_inc, void *B, int64_t ldb);
+
+/* Far field of the scattered exterior field from the boundary traces u and q
+ * (rows 0..N-1 and N..2N-1 of each column of X, either formulation):
+ *   u_inf(xh) = int_Gamma [-i k0 (nu(y).xh) u(y) - eps0 q(y)] exp(-i k0 xh.y) ds(y)
+ * with u_sc(x) ~ e^{i pi/4}/sqrt(8 pi k0 |x|) e^{i k0 |x|} u_inf(x/|x|), by the
+ * trapezoid rule.  theta: device array of nang observation angles;
+ * F: nang x nrhs column-major, ldf >= nang. */
+int bm_far_field(bm_problem *p, int32_t nrhs, const void *X, int64_t ldx, int32_t nang,
+                 const double *theta, void *F, int64_t ldf);
+
+/* Copy the assembled blocks out (for checks): mixed: Top (2N x N) to `a`,
+ * Bot (N x 2N) to `b`; ordinary: the 2N x 2N matrix to `a` (`b` ignored).
+ * Must be called after bm_assemble and before bm_block_lu (which keeps the
+ * blocks intact; only the factor storage is overwritten). */
+int bm_copy_blocks(bm_problem *p, void *a, int64_t lda, void *b, int64_t ldb);
+
+/* Copy the factors out (after bm_block_lu): the packed L\U of U33 (mixed,
+ * N x N) or of the 2N x 2N matrix (ordinary) and the pivots (device int32,
+ * 0-based: row i was swapped with ipiv[i] at step i). */
+int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv);
+
+/* Per-phase timing with HIP events on the problem's stream.  enable != 0 turns
+ * recording on.  bm_phase_times synchronises the stream and writes the
+ * durations in milliseconds of the most recent call of each phase:
+ * [0] assemble, [1] Schur-complement GEMM (mixed only), [2] LU, [3] solve,
+ * [4] far field.  n_phase <= 5. */
+int bm_set_profiling(bm_problem *p, int32_t enable);
+int bm_phase_times(bm_problem *p, double *ms_host, int32_t n_phase);
+
+/* Building blocks on caller memory, ordered on `hip_stream`.
+ * bm_zgemm: C = alpha A B + beta C; A m x k, B k x n, C m x n, column-major;
+ *   alpha, beta: host pointers to two doubles each.  m, n, k >= 0.
+ * bm_zgetrf: partial-pivot LU of the n x n matrix A in place; ipiv (device,
+ *   int32, 0-based); info (host, may be NULL for asynchronous operation) as
+ *   in bm_block_lu. */
+int bm_zgemm(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha,
+             const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
+             void *C, int64_t ldc);
+int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info);
+
+/* Text for a status code. */
+const char *bm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BM_MI355X_H */
