@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed Burton-Miller hot path on one MI355X.
+
+One step is one pass of the whole path over one batch of synthetic input:
+bm_assemble (Nystrom matrix of the mixed system) -> bm_block_lu (Schur complement
+U33 = -[M31 M32][M13; M23] and LU of U33, Theorem thm:LU) -> bm_rhs_plane_wave ->
+bm_solve (8 right-hand sides, Corollary lem:for_ssm_RHS) -> bm_far_field (64 angles).
+Inputs (geometry, angles) are resident in HBM before the timed region starts.
+
+value = complete solves per second (one solve = the 8-right-hand-side system,
+assembled, factored and solved, with its far field).  The ordinary 2N x 2N
+formulation runs through the same kernels (same LU) as the comparator.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_zgemm_star2048_traffic.json")
+ZGEMM_SRC = os.path.join(ROOT, "paper_2512_14193_amd", "csrc", "bm_zgemm.hip")
+
+
+def kernel_hash(path=ZGEMM_SRC):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_record():
+    """HBM bytes per Schur-GEMM launch from rocprofv3 counters, if they were taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_formulation(form, w, steps, warmup):
+    import torch
+    from paper_2512_14193_amd import binding as B
+
+    N = w.boundary.n_nodes
+    R = len(w.theta_inc)
+    dev = torch.device("cuda")
+    geo = [torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+           for a in (w.boundary.x, w.boundary.dx, w.boundary.ddx, w.boundary.d3x)]
+    theta_inc = torch.as_tensor(w.theta_inc, dtype=torch.float64, device=dev)
+    theta_obs = torch.as_tensor(w.theta_obs, dtype=torch.float64, device=dev)
+    P = B.Problem(N, form)
+    Bm = B.fortran_empty(P.rows, R)
+    X = B.fortran_empty(P.rows, R)
+    F = B.fortran_empty(len(w.theta_obs), R)
+
+    def step():
+        P.assemble_device(geo, w.physics)
+        P.block_lu(sync=False)
+        P.rhs_plane_wave(theta_inc, Bm)
+        P.solve(Bm, X)
+        P.far_field(X, theta_obs, F)
+
+    for _ in range(warmup):
+        step()
+    P.sync()
+    torch.cuda.synchronize()
+    P.set_profiling(True)
+    P.phase_times()  # reset the per-phase accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, cnt = P.phase_times()
+    P.set_profiling(False)
+    P.sync()  # raises if a kernel reported a device-side error
+    info = P.block_lu(sync=True)
+    if info != 0:
+        raise RuntimeError(f"{form}: singular factor, info = {info}")
+    phases = {name: (ms[i] / cnt[i] if cnt[i] else None)
+              for i, name in enumerate(["assemble", "schur_gemm", "lu", "solve", "far_field"])}
+    out = {"seconds": t1 - t0, "phase_ms": phases, "X": X.cpu().numpy(), "F": F.cpu().numpy()}
+    P.close()
+    return out
+
+
+def cpu_baseline(w):
+    """The oracle as it stands on the host cores: explicit 3N x 3N matrix, dense
+    partial-pivot LU, 8-RHS solve and far field for the same workload."""
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    O.lib()  # build/load outside the timed region
+    t0 = time.perf_counter()
+    A = O.build_mixed(w.boundary, w.physics)
+    Bm = O.rhs_plane_wave(w.boundary, w.physics, w.theta_inc)
+    X = O.zgesv(A, Bm)
+    N = w.boundary.n_nodes
+    O.far_field(w.boundary, w.physics, X[:N], X[N:2 * N], w.theta_obs)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full pass of {w.name} (assembly of the explicit {3 * N}x{3 * N} matrix, "
+                      f"dense LU, {len(w.theta_inc)}-RHS solve, far field) on the host; {t:.1f} s"}
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="star2048")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (traffic-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    from paper_2512_14193_amd import inputs as I
+
+    w = I.workload(args.workload)
+    N = w.boundary.n_nodes
+    R = len(w.theta_inc)
+    mixed = run_formulation("mixed", w, args.steps, args.warmup)
+    sec = mixed["seconds"]
+    value = args.steps / sec
+    ph = mixed["phase_ms"]
+    flops_schur = 16.0 * N ** 3
+    flops_lu = 8.0 / 3.0 * N ** 3
+    schur_tflops = flops_schur / (ph["schur_gemm"] * 1e-3) / 1e12
+    factor_tflops = (flops_schur + flops_lu) / ((ph["schur_gemm"] + ph["lu"]) * 1e-3) / 1e12
+    traffic = traffic_record()
+    rec = {
+        "metric": "block-LU solves/s (mixed Burton-Miller, assemble + factor + 8-RHS solve + far field)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "boundary": w.boundary.name, "n_nodes": N, "unknowns": 3 * N,
+                   "k0": w.physics.k0.real, "k1": w.physics.k1.real, "eps1": w.physics.eps1, "nrhs": R,
+                   "far_field_angles": len(w.theta_obs), "quadrature": "Kress log-split"},
+        "roofline": {"bound": "mfma", "kernel": "zgemm_kernel (Schur complement, m=n=N, k=2N)",
+                     "achieved": schur_tflops, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic},
+        "phase_ms": ph,
+        "factor_tflops": factor_tflops,
+        "factor_mfma_frac": factor_tflops / PEAK_FP64_MFMA_TFLOPS,
+        "rhs_solves_per_s": value * R,
+    }
+    if not args.no_comparator:
+        ordi = run_formulation("ordinary", w, args.steps, args.warmup)
+        v_ord = args.steps / ordi["seconds"]
+        Xm, Xo = mixed["X"], ordi["X"]
+        diff = float(np.max(np.linalg.norm(Xm[:2 * N] - Xo, axis=0) / np.linalg.norm(Xo, axis=0)))
+        rec["comparator"] = {"formulation": "ordinary 2N x 2N Burton-Miller, same kernels",
+                             "value": v_ord, "ms_per_step": 1e3 * ordi["seconds"] / args.steps,
+                             "phase_ms": ordi["phase_ms"], "speedup_mixed_over_ordinary": value / v_ord,
+                             "rel_diff_uq_mixed_vs_ordinary": diff,
+                             "paper_context": "1.38-1.44x on 2x EPYC 9654 (CPU, zeta-corrected quadrature, disk)"}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,13 +154,20 @@ int bm_copy_blocks(bm_problem *p, void *a, int64_t lda, void *b, int64_t ldb);
  * 0-based: row i was swapped with ipiv[i] at step i). */
 int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv);
 
-/* Per-phase timing with HIP events on the problem's stream.  enable != 0 turns
- * recording on.  bm_phase_times synchronises the stream and writes the
- * durations in milliseconds of the most recent call of each phase:
- * [0] assemble, [1] Schur-complement GEMM (mixed only), [2] LU, [3] solve,
- * [4] far field.  n_phase <= 5. */
+/* Synchronise the problem's stream and report device-side errors of the calls
+ * enqueued so far: BM_OK, or BM_E_DEVICE if a kernel raised the error flag (a
+ * bounded wait expired).  The flag stays set for the lifetime of the problem. */
+int bm_sync(bm_problem *p);
+
+/* Per-phase timing with HIP events recorded on the problem's stream around each
+ * call of a phase: [0] bm_assemble, [1] Schur-complement GEMM (mixed only),
+ * [2] LU factorisation, [3] bm_solve, [4] bm_far_field.  enable != 0 turns the
+ * recording on (it does not synchronise).  bm_phase_times synchronises the stream
+ * and writes, for each of the first n_phase (<= 5) phases, the summed duration in
+ * milliseconds (ms, host) and the number of timed calls (count, host) since its
+ * previous call, then resets them; at most the latest 64 calls per phase are kept. */
 int bm_set_profiling(bm_problem *p, int32_t enable);
-int bm_phase_times(bm_problem *p, double *ms_host, int32_t n_phase);
+int bm_phase_times(bm_problem *p, double *ms, int32_t *count, int32_t n_phase);
 
 /* Building blocks on caller memory, ordered on `hip_stream`.
  * bm_zgemm: C = alpha A B + beta C; A m x k, B k x n, C m x n, column-major;

@@ -1,0 +1,240 @@
+"""ctypes binding of libbm_mi355x.so (the C ABI declared in include/bm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+the library.  Matrices cross the boundary as torch.complex128 CUDA tensors in
+column-major (Fortran) layout, i.e. shape (rows, cols) with stride (1, ld).  If
+the library has not been built this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbm_mi355x.so")
+
+BM_MIXED, BM_ORDINARY = 0, 1
+BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE = 0, -1, -2, -3, -4, -5
+BM_MAX_NRHS = 32
+
+EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
+            "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
+            "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror"]
+
+
+class BMGeometry(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("dx", ctypes.c_void_p), ("ddx", ctypes.c_void_p),
+                ("d3x", ctypes.c_void_p)]
+
+
+class BMParams(ctypes.Structure):
+    _fields_ = [("k0_re", ctypes.c_double), ("k0_im", ctypes.c_double),
+                ("k1_re", ctypes.c_double), ("k1_im", ctypes.c_double),
+                ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
+                ("beta_re", ctypes.c_double), ("beta_im", ctypes.c_double)]
+
+
+class BMError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {lib().bm_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2512_14193_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.bm_create.argtypes = [i32, i32, vp, ctypes.POINTER(vp)]
+        L.bm_destroy.argtypes = [vp]
+        L.bm_destroy.restype = None
+        L.bm_assemble.argtypes = [vp, ctypes.POINTER(BMGeometry), ctypes.POINTER(BMParams)]
+        L.bm_block_lu.argtypes = [vp, ctypes.POINTER(i32)]
+        L.bm_solve.argtypes = [vp, i32, vp, i64, vp, i64]
+        L.bm_rhs_plane_wave.argtypes = [vp, i32, vp, vp, i64]
+        L.bm_far_field.argtypes = [vp, i32, vp, i64, i32, vp, vp, i64]
+        L.bm_copy_blocks.argtypes = [vp, vp, i64, vp, i64]
+        L.bm_copy_factors.argtypes = [vp, vp, i64, vp]
+        L.bm_sync.argtypes = [vp]
+        L.bm_set_profiling.argtypes = [vp, i32]
+        L.bm_phase_times.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
+        L.bm_zgemm.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
+        L.bm_zgetrf.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
+        L.bm_strerror.argtypes = [ctypes.c_int]
+        L.bm_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(code, what):
+    if code != BM_OK:
+        raise BMError(code, what)
+
+
+def fortran(t: torch.Tensor) -> torch.Tensor:
+    """Column-major copy of a 2-D tensor (shape kept, stride (1, rows))."""
+    return t.transpose(0, 1).contiguous().transpose(0, 1)
+
+
+def fortran_empty(rows, cols, device="cuda", dtype=torch.complex128) -> torch.Tensor:
+    return torch.empty((cols, rows), dtype=dtype, device=device).transpose(0, 1)
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.dtype != torch.complex128 or not t.is_cuda or (t.shape[0] > 1 and t.stride(0) != 1):
+        raise ValueError("expected a column-major complex128 CUDA matrix")
+    return max(t.stride(1) if t.shape[1] > 1 else t.shape[0], t.shape[0], 1)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Problem:
+    """One discretised transmission problem resident on the device."""
+
+    def __init__(self, n_nodes: int, formulation: str = "mixed", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs on the GPU only")
+        self.n = int(n_nodes)
+        self.formulation = formulation
+        self.form = BM_MIXED if formulation == "mixed" else BM_ORDINARY
+        self.rows = 3 * self.n if self.form == BM_MIXED else 2 * self.n
+        self.stream = stream or torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(lib().bm_create(self.n, self.form, _stream_handle(self.stream), ctypes.byref(h)), "bm_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls of the C ABI -------------------------------------------------
+    def assemble(self, boundary, physics):
+        """bm_assemble with geometry arrays (N, 2) float64 and a Physics record."""
+        dev = torch.device("cuda")
+        geo = [torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+               for a in (boundary.x, boundary.dx, boundary.ddx, boundary.d3x)]
+        g = BMGeometry(*[t.data_ptr() for t in geo])
+        p = BMParams(physics.k0.real, physics.k0.imag, physics.k1.real, physics.k1.imag,
+                     physics.eps0, physics.eps1, physics.beta.real, physics.beta.imag)
+        self._keep = geo  # alive until the stream passes the copy inside bm_assemble
+        check(lib().bm_assemble(self._h, ctypes.byref(g), ctypes.byref(p)), "bm_assemble")
+        self.physics = physics
+
+    def assemble_device(self, geometry, physics):
+        """bm_assemble from geometry already on the device: four contiguous float64
+        CUDA tensors of shape (N, 2) holding x and its first three derivatives."""
+        for t in geometry:
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == (self.n, 2)):
+                raise ValueError("geometry must be contiguous (N, 2) float64 CUDA tensors")
+        g = BMGeometry(*[t.data_ptr() for t in geometry])
+        p = BMParams(physics.k0.real, physics.k0.imag, physics.k1.real, physics.k1.imag,
+                     physics.eps0, physics.eps1, physics.beta.real, physics.beta.imag)
+        check(lib().bm_assemble(self._h, ctypes.byref(g), ctypes.byref(p)), "bm_assemble")
+        self.physics = physics
+
+    def block_lu(self, sync: bool = True):
+        """bm_block_lu; returns info (0 or the 1-based zero-pivot column) when sync."""
+        if sync:
+            info = ctypes.c_int32(0)
+            check(lib().bm_block_lu(self._h, ctypes.byref(info)), "bm_block_lu")
+            return info.value
+        check(lib().bm_block_lu(self._h, None), "bm_block_lu")
+        return None
+
+    def solve(self, B: torch.Tensor, X: torch.Tensor | None = None) -> torch.Tensor:
+        if X is None:
+            X = fortran_empty(B.shape[0], B.shape[1])
+        check(lib().bm_solve(self._h, B.shape[1], _ptr(B), _ld(B), _ptr(X), _ld(X)), "bm_solve")
+        return X
+
+    def rhs_plane_wave(self, theta: torch.Tensor, B: torch.Tensor | None = None) -> torch.Tensor:
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        if B is None:
+            B = fortran_empty(self.rows, theta.shape[0])
+        check(lib().bm_rhs_plane_wave(self._h, theta.shape[0], _ptr(theta), _ptr(B), _ld(B)), "bm_rhs_plane_wave")
+        return B
+
+    def far_field(self, X: torch.Tensor, theta: torch.Tensor, F: torch.Tensor | None = None) -> torch.Tensor:
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        if F is None:
+            F = fortran_empty(theta.shape[0], X.shape[1])
+        check(lib().bm_far_field(self._h, X.shape[1], _ptr(X), _ld(X), theta.shape[0], _ptr(theta), _ptr(F),
+                                 _ld(F)), "bm_far_field")
+        return F
+
+    def copy_blocks(self):
+        N = self.n
+        if self.form == BM_MIXED:
+            top, bot = fortran_empty(2 * N, N), fortran_empty(N, 2 * N)
+            check(lib().bm_copy_blocks(self._h, _ptr(top), _ld(top), _ptr(bot), _ld(bot)), "bm_copy_blocks")
+            return top, bot
+        a = fortran_empty(2 * N, 2 * N)
+        check(lib().bm_copy_blocks(self._h, _ptr(a), _ld(a), None, 0), "bm_copy_blocks")
+        return a
+
+    def copy_factors(self):
+        nf = self.n if self.form == BM_MIXED else 2 * self.n
+        lu = fortran_empty(nf, nf)
+        piv = torch.empty(nf, dtype=torch.int32, device="cuda")
+        check(lib().bm_copy_factors(self._h, _ptr(lu), _ld(lu), _ptr(piv)), "bm_copy_factors")
+        return lu, piv
+
+    def sync(self):
+        check(lib().bm_sync(self._h), "bm_sync")
+
+    def set_profiling(self, on: bool = True):
+        check(lib().bm_set_profiling(self._h, 1 if on else 0), "bm_set_profiling")
+
+    def phase_times(self):
+        """Summed ms and call counts per phase [assemble, schur, lu, solve, far_field]
+        since the previous call (then reset)."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int32 * 5)()
+        check(lib().bm_phase_times(self._h, ms, cnt, 5), "bm_phase_times")
+        return list(ms), list(cnt)
+
+
+def zgemm(alpha, A, B, beta, C, stream=None):
+    """C = alpha A B + beta C on column-major complex128 CUDA matrices."""
+    stream = stream or torch.cuda.current_stream()
+    m, k = A.shape
+    n = B.shape[1]
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    check(lib().bm_zgemm(_stream_handle(stream), m, n, k, al, _ptr(A), _ld(A), _ptr(B), _ld(B), be, _ptr(C), _ld(C)),
+          "bm_zgemm")
+    return C
+
+
+def zgetrf(A, stream=None):
+    """In-place partial-pivot LU of a column-major complex128 CUDA matrix; returns (ipiv, info)."""
+    stream = stream or torch.cuda.current_stream()
+    n = A.shape[0]
+    piv = torch.empty(n, dtype=torch.int32, device="cuda")
+    info = ctypes.c_int32(0)
+    check(lib().bm_zgetrf(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(piv), ctypes.byref(info)), "bm_zgetrf")
+    return piv, info.value

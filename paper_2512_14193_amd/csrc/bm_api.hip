@@ -1,0 +1,332 @@
+// C ABI of the MI355X mixed Burton-Miller solver (declared in include/bm.h).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "bm_internal.h"
+
+extern "C" {
+
+const char *bm_strerror(int code) {
+  switch (code) {
+    case BM_OK: return "ok";
+    case BM_E_ARG: return "invalid argument";
+    case BM_E_NOMEM: return "device allocation failed";
+    case BM_E_HIP: return "HIP runtime error";
+    case BM_E_STATE: return "call out of order";
+    case BM_E_DEVICE: return "device-side error (bounded wait expired)";
+    default: return code > 0 ? "singular factor (info > 0)" : "unknown status";
+  }
+}
+
+static void free_problem(bm_problem *p) {
+  if (!p) return;
+  (void)hipFree(p->geo);
+  (void)hipFree(p->wts);
+  (void)hipFree(p->top);
+  (void)hipFree(p->bot);
+  (void)hipFree(p->lu);
+  (void)hipFree(p->ipiv);
+  (void)hipFree(p->dinv);
+  (void)hipFree(p->dev_err);
+  bm_getrf_ws_destroy(p->gws);
+  for (int i = 0; i < BM_NPHASE; ++i)
+    if (p->ev_created[i])
+      for (int e = 0; e < BM_EV_RING; ++e) {
+        (void)hipEventDestroy(p->ev[i][e][0]);
+        (void)hipEventDestroy(p->ev[i][e][1]);
+      }
+  delete p;
+}
+
+int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out) {
+  if (!out) return BM_E_ARG;
+  *out = nullptr;
+  if (n < 8 || n > 65536 || (n % 2) != 0) return BM_E_ARG;
+  if (formulation != BM_MIXED && formulation != BM_ORDINARY) return BM_E_ARG;
+  bm_problem *p = new (std::nothrow) bm_problem();
+  if (!p) return BM_E_NOMEM;
+  memset((void *)p, 0, sizeof(*p));
+  p->n = n;
+  p->form = formulation;
+  p->nf = (formulation == BM_MIXED) ? n : 2 * n;
+  p->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free_problem(p);
+    return BM_E_HIP;
+  }
+  const size_t N = (size_t)n, nf = (size_t)p->nf;
+  const size_t nblk = (nf + BM_DIAG_NB - 1) / BM_DIAG_NB;
+  bool ok = hipMalloc(&p->geo, sizeof(double) * 8 * N) == hipSuccess;
+  ok = ok && hipMalloc(&p->wts, sizeof(double) * 4 * N) == hipSuccess;
+  if (formulation == BM_MIXED) {
+    ok = ok && hipMalloc(&p->top, sizeof(cplx) * 2 * N * N) == hipSuccess;
+    ok = ok && hipMalloc(&p->bot, sizeof(cplx) * 2 * N * N) == hipSuccess;
+  }
+  ok = ok && hipMalloc(&p->lu, sizeof(cplx) * nf * nf) == hipSuccess;
+  ok = ok && hipMalloc(&p->ipiv, sizeof(int32_t) * nf) == hipSuccess;
+  ok = ok && hipMalloc(&p->dinv, sizeof(cplx) * nblk * 2 * BM_DIAG_NB * BM_DIAG_NB) == hipSuccess;
+  ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 2) == hipSuccess;
+  if (ok) p->gws = bm_getrf_ws_create((int)nf);
+  if (!ok || !p->gws) {
+    free_problem(p);
+    return BM_E_NOMEM;
+  }
+  if (hipMemsetAsync(p->dev_err, 0, 2 * sizeof(int32_t), p->stream) != hipSuccess) {
+    free_problem(p);
+    return BM_E_HIP;
+  }
+  int rc = bm_launch_weights(p->stream, n, p->wts);
+  if (rc) {
+    free_problem(p);
+    return rc;
+  }
+  p->state = BM_ST_CREATED;
+  *out = p;
+  return BM_OK;
+}
+
+void bm_destroy(bm_problem *p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  free_problem(p);
+}
+
+// Phase timing: each call of a phase records an event pair in a ring of
+// BM_EV_RING slots; bm_phase_times sums the pairs recorded since its last call.
+static void phase_begin(bm_problem *p, int ph) {
+  if (!p->profiling) return;
+  if (!p->ev_created[ph]) {
+    for (int e = 0; e < BM_EV_RING; ++e) {
+      (void)hipEventCreate(&p->ev[ph][e][0]);
+      (void)hipEventCreate(&p->ev[ph][e][1]);
+    }
+    p->ev_created[ph] = 1;
+  }
+  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][0], p->stream);
+}
+
+static void phase_end(bm_problem *p, int ph) {
+  if (!p->profiling || !p->ev_created[ph]) return;
+  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][1], p->stream);
+  ++p->ev_count[ph];
+}
+
+int bm_assemble(bm_problem *p, const bm_geometry *g, const bm_params *prm) {
+  if (!p || !g || !prm || !g->x || !g->dx || !g->ddx || !g->d3x) return BM_E_ARG;
+  if (!(prm->eps0 > 0.0) || !(prm->eps1 > 0.0)) return BM_E_ARG;
+  if (prm->beta_im == 0.0 || !isfinite(prm->beta_re) || !isfinite(prm->beta_im)) return BM_E_ARG;
+  const double ks[2][2] = {{prm->k0_re, prm->k0_im}, {prm->k1_re, prm->k1_im}};
+  for (int w = 0; w < 2; ++w)
+    if (!(ks[w][0] > 0.0) || !(fabs(ks[w][1]) <= 0.5 * ks[w][0])) return BM_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  p->phys.k0 = cmk(prm->k0_re, prm->k0_im);
+  p->phys.k1 = cmk(prm->k1_re, prm->k1_im);
+  p->phys.beta = cmk(prm->beta_re, prm->beta_im);
+  p->phys.eps0 = prm->eps0;
+  p->phys.eps1 = prm->eps1;
+  phase_begin(p, BM_PH_ASSEMBLE);
+  const size_t bytes = sizeof(double) * 2 * (size_t)p->n;
+  BM_HIP_TRY(hipMemcpyAsync(p->geo, g->x, bytes, hipMemcpyDeviceToDevice, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 2 * p->n, g->dx, bytes, hipMemcpyDeviceToDevice, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 4 * p->n, g->ddx, bytes, hipMemcpyDeviceToDevice, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 6 * p->n, g->d3x, bytes, hipMemcpyDeviceToDevice, p->stream));
+  bm_geometry gd = {p->geo, p->geo + 2 * p->n, p->geo + 4 * p->n, p->geo + 6 * p->n};
+  int rc = bm_launch_assemble(p, &gd);
+  phase_end(p, BM_PH_ASSEMBLE);
+  if (rc) return rc;
+  p->state = BM_ST_ASSEMBLED;
+  return BM_OK;
+}
+
+static int read_dev_err(bm_problem *p, int32_t *info) {
+  int32_t h[2] = {0, 0};
+  BM_HIP_TRY(hipMemcpyAsync(h, p->dev_err, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  BM_HIP_TRY(hipStreamSynchronize(p->stream));
+  if (info) *info = h[1];
+  return h[0] ? BM_E_DEVICE : BM_OK;
+}
+
+int bm_block_lu(bm_problem *p, int32_t *info) {
+  if (!p) return BM_E_ARG;
+  if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  const int n = p->n, nf = p->nf;
+  int rc = BM_OK;
+  if (p->form == BM_MIXED) {
+    // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
+    phase_begin(p, BM_PH_SCHUR);
+    rc = bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
+    phase_end(p, BM_PH_SCHUR);
+    if (rc) return rc;
+  }
+  phase_begin(p, BM_PH_LU);
+  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws);
+  if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
+  phase_end(p, BM_PH_LU);
+  if (rc) return rc;
+  p->state = BM_ST_FACTORED;
+  if (info) return read_dev_err(p, info);
+  return BM_OK;
+}
+
+int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv, int64_t ldx) {
+  if (!p || nrhs < 0 || (nrhs > 0 && (!Bv || !Xv))) return BM_E_ARG;
+  if (p->state < BM_ST_FACTORED) return BM_E_STATE;
+  const int n = p->n, nf = p->nf;
+  const int rows = (p->form == BM_MIXED) ? 3 * n : 2 * n;
+  if (ldb < rows || ldx < rows) return BM_E_ARG;
+  if (Bv == Xv) return BM_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  const cplx *B = (const cplx *)Bv;
+  cplx *X = (cplx *)Xv;
+  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  phase_begin(p, BM_PH_SOLVE);
+  for (int r0 = 0; r0 < nrhs; r0 += BM_MAX_NRHS) {
+    const int nr = (nrhs - r0 < BM_MAX_NRHS) ? nrhs - r0 : BM_MAX_NRHS;
+    const cplx *Bc = B + (size_t)r0 * ldb;
+    cplx *Xc = X + (size_t)r0 * ldx;
+    BM_HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(cplx) * ldx, Bc, sizeof(cplx) * ldb, sizeof(cplx) * rows, nr,
+                                hipMemcpyDeviceToDevice, p->stream));
+    cplx *X3 = (p->form == BM_MIXED) ? Xc + 2 * n : Xc;
+    int rc;
+    if (p->form == BM_MIXED) {
+      // Corollary lem:for_ssm_RHS: c = b3 - M31 b1 - M32 b2 = b3 - Bot [b1; b2]
+      rc = bm_launch_zgemm(p->stream, n, nr, 2 * n, mone, p->bot, n, Xc, ldx, one, X3, ldx);
+      if (rc) return rc;
+    }
+    rc = bm_launch_rhs_swaps(p->stream, p->gws, nr, X3, ldx);
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, X3, ldx, nr, p->dev_err);
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, X3, ldx, nr, p->dev_err);
+    if (rc) return rc;
+    if (p->form == BM_MIXED) {
+      // x1 = b1 - M13 z3, x2 = b2 - M23 z3:  [x1; x2] = [b1; b2] - Top z3
+      rc = bm_launch_zgemm(p->stream, 2 * n, nr, n, mone, p->top, 2 * n, X3, ldx, one, Xc, ldx);
+      if (rc) return rc;
+    }
+  }
+  phase_end(p, BM_PH_SOLVE);
+  return BM_OK;
+}
+
+int bm_rhs_plane_wave(bm_problem *p, int32_t nrhs, const double *theta_inc, void *B, int64_t ldb) {
+  if (!p || nrhs < 0 || (nrhs > 0 && (!theta_inc || !B))) return BM_E_ARG;
+  if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
+  const int rows = (p->form == BM_MIXED) ? 3 * p->n : 2 * p->n;
+  if (ldb < rows) return BM_E_ARG;
+  if (nrhs == 0) return BM_OK;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  return bm_launch_rhs_plane_wave(p, nrhs, theta_inc, (cplx *)B, ldb);
+}
+
+int bm_far_field(bm_problem *p, int32_t nrhs, const void *X, int64_t ldx, int32_t nang, const double *theta,
+                 void *F, int64_t ldf) {
+  if (!p || nrhs < 0 || nang < 0) return BM_E_ARG;
+  if (nrhs > 0 && nang > 0 && (!X || !theta || !F)) return BM_E_ARG;
+  if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
+  if (ldx < 2 * p->n || ldf < nang) return BM_E_ARG;
+  if (nrhs == 0 || nang == 0) return BM_OK;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  phase_begin(p, BM_PH_FAR);
+  int rc = bm_launch_far_field(p, nrhs, (const cplx *)X, ldx, nang, theta, (cplx *)F, ldf);
+  phase_end(p, BM_PH_FAR);
+  return rc;
+}
+
+int bm_copy_blocks(bm_problem *p, void *a, int64_t lda, void *b, int64_t ldb) {
+  if (!p || !a) return BM_E_ARG;
+  if (p->state != BM_ST_ASSEMBLED && !(p->form == BM_MIXED && p->state == BM_ST_FACTORED)) return BM_E_STATE;
+  const size_t N = (size_t)p->n;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  if (p->form == BM_MIXED) {
+    if (!b || lda < (int64_t)(2 * N) || ldb < (int64_t)N) return BM_E_ARG;
+    BM_HIP_TRY(hipMemcpy2DAsync(a, sizeof(cplx) * lda, p->top, sizeof(cplx) * 2 * N, sizeof(cplx) * 2 * N, N,
+                                hipMemcpyDeviceToDevice, p->stream));
+    BM_HIP_TRY(hipMemcpy2DAsync(b, sizeof(cplx) * ldb, p->bot, sizeof(cplx) * N, sizeof(cplx) * N, 2 * N,
+                                hipMemcpyDeviceToDevice, p->stream));
+  } else {
+    if (lda < (int64_t)(2 * N)) return BM_E_ARG;
+    BM_HIP_TRY(hipMemcpy2DAsync(a, sizeof(cplx) * lda, p->lu, sizeof(cplx) * 2 * N, sizeof(cplx) * 2 * N, 2 * N,
+                                hipMemcpyDeviceToDevice, p->stream));
+  }
+  return BM_OK;
+}
+
+int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv) {
+  if (!p || !lu || !ipiv) return BM_E_ARG;
+  if (p->state < BM_ST_FACTORED) return BM_E_STATE;
+  const size_t nf = (size_t)p->nf;
+  if (ld < (int64_t)nf) return BM_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  BM_HIP_TRY(hipMemcpy2DAsync(lu, sizeof(cplx) * ld, p->lu, sizeof(cplx) * nf, sizeof(cplx) * nf, nf,
+                              hipMemcpyDeviceToDevice, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(ipiv, p->ipiv, sizeof(int32_t) * nf, hipMemcpyDeviceToDevice, p->stream));
+  return BM_OK;
+}
+
+int bm_sync(bm_problem *p) {
+  if (!p) return BM_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  return read_dev_err(p, nullptr);
+}
+
+int bm_set_profiling(bm_problem *p, int32_t enable) {
+  if (!p) return BM_E_ARG;
+  p->profiling = enable ? 1 : 0;
+  return BM_OK;
+}
+
+int bm_phase_times(bm_problem *p, double *ms, int32_t *count, int32_t n_phase) {
+  if (!p || !ms || !count || n_phase < 0 || n_phase > BM_NPHASE) return BM_E_ARG;
+  BM_HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < n_phase; ++i) {
+    const int c = p->ev_count[i] < BM_EV_RING ? p->ev_count[i] : BM_EV_RING;
+    double tot = 0.0;
+    for (int e = 0; e < c; ++e) {
+      float f = 0.0f;
+      if (hipEventElapsedTime(&f, p->ev[i][e][0], p->ev[i][e][1]) == hipSuccess) tot += f;
+    }
+    ms[i] = tot;
+    count[i] = c;
+    p->ev_count[i] = 0;
+  }
+  return BM_OK;
+}
+
+int bm_zgemm(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha, const void *A, int64_t lda,
+             const void *B, int64_t ldb, const double *beta, void *C, int64_t ldc) {
+  if (m < 0 || n < 0 || k < 0 || !alpha || !beta) return BM_E_ARG;
+  if (m == 0 || n == 0) return BM_OK;
+  if (!C || (k > 0 && (!A || !B))) return BM_E_ARG;
+  if (lda < m || ldb < k || ldc < m) return BM_E_ARG;
+  return bm_launch_zgemm((hipStream_t)hip_stream, m, n, k, cmk(alpha[0], alpha[1]), (const cplx *)A, lda,
+                         (const cplx *)B, ldb, cmk(beta[0], beta[1]), (cplx *)C, ldc);
+}
+
+int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info) {
+  if (n < 0 || lda < n || (n > 0 && (!A || !ipiv))) return BM_E_ARG;
+  if (n == 0) {
+    if (info) *info = 0;
+    return BM_OK;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  bm_getrf_ws *w = bm_getrf_ws_create(n);
+  int32_t *dev_err = nullptr;
+  if (!w || hipMalloc(&dev_err, 2 * sizeof(int32_t)) != hipSuccess) {
+    bm_getrf_ws_destroy(w);
+    return BM_E_NOMEM;
+  }
+  int rc = bm_getrf_run(s, n, (cplx *)A, lda, ipiv, dev_err, w);
+  int32_t h[2] = {0, 0};
+  if (hipMemcpyAsync(h, dev_err, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = rc ? rc : BM_E_HIP;
+  (void)hipFree(dev_err);
+  bm_getrf_ws_destroy(w);
+  if (rc) return rc;
+  if (info) *info = h[1];
+  return h[0] ? BM_E_DEVICE : BM_OK;
+}
+
+}  // extern "C"

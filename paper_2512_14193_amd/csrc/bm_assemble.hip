@@ -1,0 +1,407 @@
+// Nystrom assembly of the mixed (and ordinary) Burton-Miller matrices, plane-wave
+// right-hand sides and the far field, for gfx950.
+//
+// Discretisation (the operators of Sec. 2.2 on the N = 2n equispaced nodes of
+// Sec. 4): every kernel K(t, tau) of S, D, D* and of N_k - N_0 is split as
+//   K = K1 ln(4 sin^2((t - tau)/2)) + K2
+// and integrated as  R_|i-j| K1 + (pi/n) K2,  where R are the exact weights of the
+// logarithmic factor for trigonometric polynomials of degree <= n.  The Laplace
+// hypersingular operator is written, after integrating Maue's form by parts, as
+//   N_0 phi(t) = (1/|x'(t)|)[(1/4pi) int cot((tau - t)/2) phi'(tau) dtau + int K0 phi dtau],
+//   K0 = (1/4pi) d_t d_tau ln(|x(t) - x(tau)|^2 / (4 sin^2((t - tau)/2)))  (smooth),
+// with the Hilbert-type weights T_|i-j| for the first term.  The log coefficients
+// are the J-parts of the Hankel functions (Y_n = (2/pi) J_n ln(z/2) + ...), the
+// diagonal limits follow from the small-argument expansions of J and Y.
+//
+// Symmetry: the pair (i, j) and (j, i) share r = |x_i - x_j| and every Hankel value,
+// so each workgroup evaluates one tile of unordered pairs and writes both the (I, J)
+// and the mirrored (J, I) tile of every block.  The mirrored tile goes through LDS so
+// that both global writes are column-major coalesced.
+#include <math.h>
+
+#include "bm_hankel.h"
+#include "bm_internal.h"
+
+__constant__ double bm_hk_g0[BM_HQ + 1];
+__constant__ double bm_hk_g1[BM_HQ + 1];
+__constant__ double bm_hk_s2[BM_HQ + 1];
+
+static int hankel_init_done[64];
+
+static int bm_hankel_init() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BM_E_HIP;
+  if (hankel_init_done[dev]) return BM_OK;
+  double g0[BM_HQ + 1], g1[BM_HQ + 1], s2[BM_HQ + 1];
+  const double rsp = 1.0 / sqrt(BM_PI);
+  for (int q = 0; q <= BM_HQ; ++q) {
+    double s = q * BM_HSTEP, w = (q == 0) ? 0.5 * BM_HSTEP : BM_HSTEP;
+    double e = exp(-s * s);
+    g0[q] = w * e * 2.0 * rsp;
+    g1[q] = w * e * s * s * 4.0 * rsp;
+    s2[q] = s * s;
+  }
+  BM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(bm_hk_g0), g0, sizeof(g0)));
+  BM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(bm_hk_g1), g1, sizeof(g1)));
+  BM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(bm_hk_s2), s2, sizeof(s2)));
+  hankel_init_done[dev] = 1;
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature weights, one workgroup per m = (i - j) mod N:
+//   R_m = -(2pi/n) sum_{p=1}^{n-1} cos(p m pi/n)/p - (pi/n^2)(-1)^m
+//   T_m = -(1/2n) sum_{p=1}^{n-1} p cos(p m pi/n) - (1/4)(-1)^m
+//   L_m = ln(4 sin^2(pi m/N)),  C_m = 1/(2 sin^2(pi m/N))   (m != 0)
+// cos(p m pi/n) is evaluated as cospi(((p m) mod 2n)/n): exact argument reduction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void weights_kernel(int N, double *wts) {
+  const int m = blockIdx.x, n = N / 2;
+  double sr = 0.0, st = 0.0;
+  for (int p = 1 + threadIdx.x; p <= n - 1; p += blockDim.x) {
+    long long q = ((long long)p * m) % N;
+    double c = cospi((double)q / (double)n);
+    sr += c / (double)p;
+    st += (double)p * c;
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = st;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sg = (m & 1) ? -1.0 : 1.0;
+    wts[m] = -(2.0 * BM_PI / n) * red[0][0] - (BM_PI / ((double)n * n)) * sg;
+    wts[N + m] = -red[1][0] / (2.0 * n) - 0.25 * sg;
+    if (m == 0) {
+      wts[2 * N] = 0.0;
+      wts[3 * N] = 0.0;
+    } else {
+      double sn = sinpi((double)m / (double)N);
+      wts[2 * N + m] = log(4.0 * sn * sn);
+      wts[3 * N + m] = 1.0 / (2.0 * sn * sn);
+    }
+  }
+}
+
+int bm_launch_weights(hipStream_t s, int n, double *wts) {
+  hipLaunchKernelGGL(weights_kernel, dim3(n), dim3(256), 0, s, n, wts);
+  BM_HIP_TRY(hipGetLastError());
+  return bm_hankel_init();
+}
+
+// ---------------------------------------------------------------------------
+// Assembly
+// ---------------------------------------------------------------------------
+#define ASM_TB 16  // tile edge: 16 x 16 unordered pairs per workgroup of 256 threads
+
+struct asm_args {
+  int N;
+  double h;  // pi / n
+  bm_phys ph;
+  const double2 *x, *dx, *ddx, *d3x;
+  const double *wts;
+  cplx *top, *bot;  // mixed
+  cplx *ord;        // ordinary
+};
+
+// Per-wavenumber symmetric scalars of an off-diagonal pair:
+//   S_ij = sig s_j,  D_ij = del (n_j . d),  D*_ij = -del (n_i . d) s_j / s_i,
+//   (N_k - N_0)_ij = nu s_j
+struct pair_k {
+  cplx sig, del, nu;
+};
+
+__device__ inline pair_k pair_scalars(cplx k, double r, double rinv, double R, double L, double h, double a,
+                                      double b, bool want_nu) {
+  const bm_hk4 hk = bm_hankel01(cscale(k, r));
+  pair_k o;
+  // S: K = (i/4) H0, K1 = -J0/(4 pi)
+  const cplx aS = cmk(-0.25 * hk.h0.y, 0.25 * hk.h0.x);
+  const cplx lS = cscale(hk.j0, -1.0 / (4.0 * BM_PI));
+  o.sig = cadd(cscale(lS, R), cscale(csub(aS, cscale(lS, L)), h));
+  // D: K = (ik/4) H1 / r, K1 = -(k/4pi) J1 / r  (times n_j . d)
+  const cplx ik4 = cmk(-0.25 * k.y, 0.25 * k.x);
+  const cplx aD = cscale(cmul(ik4, hk.h1), rinv);
+  const cplx lD = cscale(cmul(k, hk.j1), -rinv / (4.0 * BM_PI));
+  o.del = cadd(cscale(lD, R), cscale(csub(aD, cscale(lD, L)), h));
+  if (want_nu) {
+    // N_k - N_0 with a = nu_x.nu_y and b = (nu_x.d)(nu_y.d)/r^2:
+    //   kernel_k = (ik/4)[(H1/r) a + (k H0 - 2 H1/r) b],  kernel_0 = (a/2 - b)/(pi r^2),
+    //   K1 = -(k/4pi)[(J1/r) a + (k J0 - 2 J1/r) b]
+    const cplx hh = cadd(cscale(hk.h1, rinv * a), cscale(csub(cmul(k, hk.h0), cscale(hk.h1, 2.0 * rinv)), b));
+    const cplx jj = cadd(cscale(hk.j1, rinv * a), cscale(csub(cmul(k, hk.j0), cscale(hk.j1, 2.0 * rinv)), b));
+    cplx Kk = cmul(ik4, hh);
+    Kk.x -= (0.5 * a - b) * rinv * rinv / BM_PI;
+    const cplx K1 = cscale(cmul(k, jj), -1.0 / (4.0 * BM_PI));
+    o.nu = cadd(cscale(K1, R), cscale(csub(Kk, cscale(K1, L)), h));
+  } else {
+    o.nu = cmk(0, 0);
+  }
+  return o;
+}
+
+// Output blocks: mixed {M13, M23, M31, M32}; ordinary {M31, M32, D_k1 + I/2, -eps1 S_k1}.
+template <int FORM>
+__device__ inline void store_entry(const asm_args &A, int blk, int row, int col, cplx v) {
+  const long N = A.N;
+  if (FORM == BM_MIXED) {
+    switch (blk) {
+      case 0: A.top[row + col * 2 * N] = v; break;
+      case 1: A.top[N + row + col * 2 * N] = v; break;
+      case 2: A.bot[row + col * N] = v; break;
+      default: A.bot[row + (N + col) * N] = v; break;
+    }
+  } else {
+    switch (blk) {
+      case 0: A.ord[row + col * 2 * N] = v; break;
+      case 1: A.ord[row + (N + col) * 2 * N] = v; break;
+      case 2: A.ord[N + row + col * 2 * N] = v; break;
+      default: A.ord[N + row + (N + col) * 2 * N] = v; break;
+    }
+  }
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
+  // unordered tile pair (I, J), I <= J, from the triangular index
+  const long Lt = blockIdx.x;
+  int J = (int)((sqrt(8.0 * (double)Lt + 1.0) - 1.0) * 0.5);
+  while ((long)J * (J + 1) / 2 > Lt) --J;
+  while ((long)(J + 1) * (J + 2) / 2 <= Lt) ++J;
+  const int I = (int)(Lt - (long)J * (J + 1) / 2);
+
+  __shared__ cplx mirror[4][ASM_TB][ASM_TB + 1];
+
+  const int N = A.N;
+  const int li = threadIdx.x % ASM_TB, lj = threadIdx.x / ASM_TB;
+  const int i = I * ASM_TB + li, j = J * ASM_TB + lj;
+  const bm_phys ph = A.ph;
+  cplx e[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};  // (i, j) entries of the 4 blocks
+  cplx f[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};  // (j, i) entries
+  const bool valid = (i < N) && (j < N);
+  if (valid) {
+    const double2 xi = A.x[i], ai = A.dx[i];
+    const double si = sqrt(ai.x * ai.x + ai.y * ai.y);
+    const double h = A.h;
+    if (i != j) {
+      const double2 xj = A.x[j], aj = A.dx[j];
+      const double sj = sqrt(aj.x * aj.x + aj.y * aj.y);
+      const int m = (i > j) ? i - j : j - i;
+      const double R = A.wts[m], T = A.wts[N + m], L = A.wts[2 * N + m], C = A.wts[3 * N + m];
+      const double d1 = xi.x - xj.x, d2 = xi.y - xj.y;
+      const double r2 = d1 * d1 + d2 * d2, r = sqrt(r2), rinv = 1.0 / r;
+      // unnormalised normals n = (x2', -x1'), |n| = |x'|
+      const double ndj = aj.y * d1 - aj.x * d2;  // n_j . d
+      const double ndi = ai.y * d1 - ai.x * d2;  // n_i . d
+      const double a = (ai.y * aj.y + ai.x * aj.x) / (si * sj);
+      const double b = (ndi / si) * (ndj / sj) * rinv * rinv;
+      // Laplace part: K0 = (1/4pi)[-2 x'_i.x'_j / r^2 + 4 (d.x'_i)(d.x'_j)/r^4 - 1/(2 sin^2)]
+      const double dai = d1 * ai.x + d2 * ai.y, daj = d1 * aj.x + d2 * aj.y;
+      const double aa = ai.x * aj.x + ai.y * aj.y;
+      const double K0 = (-2.0 * aa / r2 + 4.0 * dai * daj / (r2 * r2) - C) / (4.0 * BM_PI);
+      const double kap = T + h * K0;  // N_0,ij = kap / s_i, N_0,ji = kap / s_j
+
+      const pair_k p0 = pair_scalars(ph.k0, r, rinv, R, L, h, a, b, true);
+      const pair_k p1 = pair_scalars(ph.k1, r, rinv, R, L, h, a, b, false);
+      // k0 operators at (i,j) and (j,i)
+      const cplx S0ij = cscale(p0.sig, sj), S0ji = cscale(p0.sig, si);
+      const cplx D0ij = cscale(p0.del, ndj), D0ji = cscale(p0.del, -ndi);
+      const cplx Ds0ij = cscale(p0.del, -ndi * sj / si), Ds0ji = cscale(p0.del, ndj * si / sj);
+      const cplx N0ij = cadd(cmk(kap / si, 0.0), cscale(p0.nu, sj));
+      const cplx N0ji = cadd(cmk(kap / sj, 0.0), cscale(p0.nu, si));
+      // M31 = D0 + beta N0,  M32 = -eps0 (S0 + beta D*0)
+      const cplx M31ij = cadd(D0ij, cmul(ph.beta, N0ij)), M31ji = cadd(D0ji, cmul(ph.beta, N0ji));
+      const cplx M32ij = cscale(cadd(S0ij, cmul(ph.beta, Ds0ij)), -ph.eps0);
+      const cplx M32ji = cscale(cadd(S0ji, cmul(ph.beta, Ds0ji)), -ph.eps0);
+      if (FORM == BM_MIXED) {
+        // M13 = -S1,  M23 = -D*1 / eps1
+        e[0] = cscale(p1.sig, -sj);
+        f[0] = cscale(p1.sig, -si);
+        e[1] = cscale(p1.del, ndi * sj / (si * ph.eps1));
+        f[1] = cscale(p1.del, -ndj * si / (sj * ph.eps1));
+        e[2] = M31ij; f[2] = M31ji;
+        e[3] = M32ij; f[3] = M32ji;
+      } else {
+        e[0] = M31ij; f[0] = M31ji;
+        e[1] = M32ij; f[1] = M32ji;
+        e[2] = cscale(p1.del, ndj);  // D1
+        f[2] = cscale(p1.del, -ndi);
+        e[3] = cscale(p1.sig, -ph.eps1 * sj);  // -eps1 S1
+        f[3] = cscale(p1.sig, -ph.eps1 * si);
+      }
+    } else {
+      // diagonal limits
+      const double2 bi = A.ddx[i], ci = A.d3x[i];
+      const double s2 = si * si;
+      const double R0 = A.wts[0], T0 = A.wts[N];
+      const double kap = (ai.y * bi.x - ai.x * bi.y) / (4.0 * BM_PI * s2);  // D_ii / h
+      const double Dd = h * kap;
+      const double pq = ai.x * bi.x + ai.y * bi.y, B = bi.x * bi.x + bi.y * bi.y, q = ai.x * ci.x + ai.y * ci.y;
+      const double K0d = (-(pq * pq) / (s2 * s2) + (0.5 * B + q / 3.0) / s2 - 1.0 / 6.0) / (4.0 * BM_PI);
+      const double N0d = (T0 + h * K0d) / si;
+      cplx S[2], Nd0;
+      for (int w = 0; w < 2; ++w) {
+        const cplx k = w ? ph.k1 : ph.k0;
+        const cplx lk = clog_d(cscale(k, 0.5 * si));
+        // S_ii = R0 (-s/4pi) + h (i/4 - gamma/2pi - ln(k s/2)/2pi) s
+        cplx K2 = cscale(lk, -1.0 / (2.0 * BM_PI));
+        K2.x -= BM_EULER / (2.0 * BM_PI);
+        K2.y += 0.25;
+        S[w] = cscale(cadd(cmk(-R0 / (4.0 * BM_PI), 0.0), cscale(K2, h)), si);
+        if (w == 0) {
+          // (N_k - N_0)_ii = (R0 (-k^2/8pi) + h (i k^2/8 + (1-2gamma) k^2/8pi - (k^2/4pi) ln(k s/2))) s
+          const cplx k2 = cmul(k, k);
+          cplx t = cscale(k2, (1.0 - 2.0 * BM_EULER) / (8.0 * BM_PI));
+          t = cadd(t, cmk(-0.125 * k2.y, 0.125 * k2.x));
+          t = csub(t, cscale(cmul(k2, lk), 1.0 / (4.0 * BM_PI)));
+          Nd0 = cscale(cadd(cscale(k2, -R0 / (8.0 * BM_PI)), cscale(t, h)), si);
+        }
+      }
+      const cplx Nk0 = cadd(cmk(N0d, 0.0), Nd0);
+      const cplx M31 = cadd(cmk(Dd - 0.5, 0.0), cmul(ph.beta, Nk0));
+      const cplx M32 = cscale(cadd(S[0], cmul(ph.beta, cmk(Dd + 0.5, 0.0))), -ph.eps0);
+      if (FORM == BM_MIXED) {
+        e[0] = cneg(S[1]);
+        e[1] = cmk(-(Dd + 0.5) / ph.eps1, 0.0);
+        e[2] = M31;
+        e[3] = M32;
+      } else {
+        e[0] = M31;
+        e[1] = M32;
+        e[2] = cmk(Dd + 0.5, 0.0);
+        e[3] = cscale(S[1], -ph.eps1);
+      }
+    }
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) store_entry<FORM>(A, blk, i, j, e[blk]);
+  }
+  if (I != J) {
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) mirror[blk][li][lj] = f[blk];
+    __syncthreads();
+    // writer thread: row J*TB + wr, column I*TB + wc of the mirrored tile
+    const int wr = threadIdx.x % ASM_TB, wc = threadIdx.x / ASM_TB;
+    const int row = J * ASM_TB + wr, col = I * ASM_TB + wc;
+    if (row < N && col < N) {
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) store_entry<FORM>(A, blk, row, col, mirror[blk][wc][wr]);
+    }
+  }
+}
+
+int bm_launch_assemble(bm_problem *p, const bm_geometry *g) {
+  asm_args A;
+  A.N = p->n;
+  A.h = BM_PI / (p->n / 2);
+  A.ph = p->phys;
+  A.x = (const double2 *)g->x;
+  A.dx = (const double2 *)g->dx;
+  A.ddx = (const double2 *)g->ddx;
+  A.d3x = (const double2 *)g->d3x;
+  A.wts = p->wts;
+  A.top = p->top;
+  A.bot = p->bot;
+  A.ord = p->lu;
+  const long nt = (p->n + ASM_TB - 1) / ASM_TB;
+  const long ntiles = nt * (nt + 1) / 2;
+  if (p->form == BM_MIXED)
+    hipLaunchKernelGGL(assemble_kernel<BM_MIXED>, dim3((unsigned)ntiles), dim3(256), 0, p->stream, A);
+  else
+    hipLaunchKernelGGL(assemble_kernel<BM_ORDINARY>, dim3((unsigned)ntiles), dim3(256), 0, p->stream, A);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plane-wave right-hand sides: b3 = -u_in - beta d_nu u_in,
+// u_in = exp(i k0 d.x), d_nu u_in = i k0 (d.nu) u_in, d = (cos th, sin th).
+// ---------------------------------------------------------------------------
+__global__ void rhs_kernel(int N, int form, int nrhs, const double2 *x, const double2 *dx, cplx k0, cplx beta,
+                           const double *theta, cplx *B, long ldb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j >= N || r >= nrhs) return;
+  const int rows = (form == BM_MIXED) ? 3 * N : 2 * N;
+  const int off = (form == BM_MIXED) ? 2 * N : 0;
+  cplx *col = B + (long)r * ldb;
+  double s, c;
+  sincos(theta[r], &s, &c);
+  const double2 xj = x[j], aj = dx[j];
+  const double sj = sqrt(aj.x * aj.x + aj.y * aj.y);
+  const double dn = (c * aj.y - s * aj.x) / sj;  // d . nu
+  const double dxv = c * xj.x + s * xj.y;
+  const cplx uin = cexp_d(cmul(cmk(0.0, dxv), k0));  // exp(i k0 d.x)
+  const cplx qin = cmul(cmul(cmk(0.0, dn), k0), uin);
+  const cplx b3 = cneg(cadd(uin, cmul(beta, qin)));
+  for (int t = j; t < rows; t += N) col[t] = (t == off + j) ? b3 : cmk(0, 0);
+}
+
+int bm_launch_rhs_plane_wave(bm_problem *p, int nrhs, const double *theta, cplx *B, int64_t ldb) {
+  dim3 grid((p->n + 255) / 256, nrhs);
+  hipLaunchKernelGGL(rhs_kernel, grid, dim3(256), 0, p->stream, p->n, p->form, nrhs, (const double2 *)p->geo,
+                     (const double2 *)(p->geo + 2 * p->n), p->phys.k0, p->phys.beta, theta, B, (long)ldb);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Far field: F[a, r] = (2pi/N) sum_j [-i k0 (n_j . xh) u_jr - eps0 |x'_j| q_jr] exp(-i k0 xh . x_j)
+// One workgroup per observation angle; deterministic tree reduction.
+// ---------------------------------------------------------------------------
+#define FF_RMAX 8
+__global__ __launch_bounds__(256) void far_field_kernel(int N, int nrhs, const double2 *x, const double2 *dx,
+                                                        cplx k0, double eps0, const cplx *X, long ldx,
+                                                        const double *theta, cplx *F, long ldf) {
+  const int a = blockIdx.x;
+  double s, c;
+  sincos(theta[a], &s, &c);
+  cplx acc[FF_RMAX];
+#pragma unroll
+  for (int r = 0; r < FF_RMAX; ++r) acc[r] = cmk(0, 0);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double2 xj = x[j], aj = dx[j];
+    const double sj = sqrt(aj.x * aj.x + aj.y * aj.y);
+    const double nx = aj.y * c - aj.x * s;  // n_j . xh
+    const cplx e = cexp_d(cmul(cmk(0.0, -(c * xj.x + s * xj.y)), k0));
+    const cplx cu = cmul(cmk(0.0, -nx), k0);  // -i k0 (n.xh)
+#pragma unroll
+    for (int r = 0; r < FF_RMAX; ++r) {
+      if (r < nrhs) {
+        const cplx u = X[j + (long)r * ldx], q = X[N + j + (long)r * ldx];
+        const cplx v = csub(cmul(cu, u), cscale(q, eps0 * sj));
+        acc[r] = cadd(acc[r], cmul(v, e));
+      }
+    }
+  }
+  __shared__ cplx red[256];
+  const double h = 2.0 * BM_PI / N;
+  for (int r = 0; r < nrhs && r < FF_RMAX; ++r) {
+    red[threadIdx.x] = acc[r];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) F[a + (long)r * ldf] = cscale(red[0], h);
+    __syncthreads();
+  }
+}
+
+int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int nang, const double *theta,
+                        cplx *F, int64_t ldf) {
+  for (int r0 = 0; r0 < nrhs; r0 += FF_RMAX) {
+    const int nr = (nrhs - r0 < FF_RMAX) ? nrhs - r0 : FF_RMAX;
+    hipLaunchKernelGGL(far_field_kernel, dim3(nang), dim3(256), 0, p->stream, p->n, nr, (const double2 *)p->geo,
+                       (const double2 *)(p->geo + 2 * p->n), p->phys.k0, p->phys.eps0, X + (long)r0 * ldx,
+                       (long)ldx, theta, F + (long)r0 * ldf, (long)ldf);
+    BM_HIP_TRY(hipGetLastError());
+  }
+  return BM_OK;
+}

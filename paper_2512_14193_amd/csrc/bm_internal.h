@@ -1,0 +1,129 @@
+// Internal declarations of the MI355X mixed Burton-Miller solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bm.h"
+
+typedef double2 cplx;  // (re, im), the layout of torch.complex128
+
+#define BM_PI 3.14159265358979323846
+#define BM_EULER 0.57721566490153286061
+
+// ---------------------------------------------------------------------------
+// complex helpers (host and device)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline cplx cmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx cneg(cplx a) { return make_double2(-a.x, -a.y); }
+__host__ __device__ inline cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * (i * s) for real s
+__host__ __device__ inline cplx cmul_i(cplx a, double s) { return make_double2(-a.y * s, a.x * s); }
+__host__ __device__ inline double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm: no intermediate overflow for any finite b != 0
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.y + b.x * r;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+__host__ __device__ inline cplx crecip(cplx b) { return cdiv(make_double2(1.0, 0.0), b); }
+__device__ inline cplx cexp_d(cplx z) {
+  double e = exp(z.x), s, c;
+  sincos(z.y, &s, &c);
+  return make_double2(e * c, e * s);
+}
+__device__ inline cplx clog_d(cplx z) { return make_double2(log(hypot(z.x, z.y)), atan2(z.y, z.x)); }
+// principal square root (cut along the negative real axis)
+__device__ inline cplx csqrt_d(cplx w) {
+  double r = hypot(w.x, w.y);
+  if (r == 0.0) return make_double2(0.0, 0.0);
+  if (w.x >= 0.0) {
+    double t = sqrt(0.5 * (r + w.x));
+    return make_double2(t, w.y / (2.0 * t));
+  } else {
+    double t = sqrt(0.5 * (r - w.x));
+    return make_double2(fabs(w.y) / (2.0 * t), copysign(t, w.y));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// problem handle
+// ---------------------------------------------------------------------------
+struct bm_phys {
+  cplx k0, k1, beta;
+  double eps0, eps1;
+};
+
+enum { BM_ST_CREATED = 0, BM_ST_ASSEMBLED = 1, BM_ST_FACTORED = 2 };
+#define BM_EV_RING 64
+enum { BM_PH_ASSEMBLE = 0, BM_PH_SCHUR = 1, BM_PH_LU = 2, BM_PH_SOLVE = 3, BM_PH_FAR = 4, BM_NPHASE = 5 };
+
+struct bm_getrf_ws;  // panel-factorisation workspace (bm_getrf.hip)
+
+struct bm_problem {
+  int n;                // nodes N
+  int form;             // BM_MIXED / BM_ORDINARY
+  int nf;               // order of the factored matrix: N (mixed) or 2N (ordinary)
+  int state;
+  int device;
+  hipStream_t stream;
+  bm_phys phys;
+
+  double *geo;          // 8N doubles: x, dx, ddx, d3x (interleaved pairs)
+  double *wts;          // 4N doubles: R_m, T_m, L_m = ln(4 sin^2(pi m/N)), 1/(2 sin^2(pi m/N))
+  cplx *top;            // mixed: [M13; M23], 2N x N, ld 2N
+  cplx *bot;            // mixed: [M31 M32], N x 2N, ld N
+  cplx *lu;             // factor storage: U33 (mixed, N x N) or the ordinary 2N x 2N matrix
+  int32_t *ipiv;        // nf, 0-based LAPACK-style interchanges
+  cplx *dinv;           // inverses of the 64 x 64 diagonal blocks of L and U
+  int32_t *dev_err;     // device-side error flag and getrf info: [0] error, [1] info
+  bm_getrf_ws *gws;
+
+  int profiling;
+  hipEvent_t ev[BM_NPHASE][BM_EV_RING][2];
+  int ev_created[BM_NPHASE];
+  int ev_count[BM_NPHASE];  // event pairs recorded since the last bm_phase_times
+};
+
+// ---------------------------------------------------------------------------
+// internal launchers (all enqueue on `s` and return a bm_status)
+// ---------------------------------------------------------------------------
+int bm_launch_weights(hipStream_t s, int n, double *wts);
+int bm_launch_assemble(bm_problem *p, const bm_geometry *g);
+int bm_launch_rhs_plane_wave(bm_problem *p, int nrhs, const double *theta, cplx *B, int64_t ldb);
+int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int nang, const double *theta,
+                        cplx *F, int64_t ldf);
+int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
+                    const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
+
+// LU
+size_t bm_getrf_ws_bytes(int n);
+bm_getrf_ws *bm_getrf_ws_create(int n);
+void bm_getrf_ws_destroy(bm_getrf_ws *w);
+int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
+                 bm_getrf_ws *w);
+int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);
+
+// solve support: the factorisation's row interchanges applied to right-hand sides,
+// and the blocked triangular solves (lower: unit L, else U) in place on X (n x nrhs)
+int bm_launch_rhs_swaps(hipStream_t s, bm_getrf_ws *w, int nrhs, cplx *X, int64_t ldx);
+int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
+                   cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
+
+#define BM_DIAG_NB 64
+
+#define BM_HIP_TRY(expr)                         \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return BM_E_HIP;       \
+  } while (0)
