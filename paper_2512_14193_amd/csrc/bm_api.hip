@@ -29,6 +29,9 @@ static void free_problem(bm_problem *p) {
   (void)hipFree(p->lu);
   (void)hipFree(p->ipiv);
   (void)hipFree(p->dinv);
+  (void)hipFree(p->perm);
+  (void)hipFree(p->work_g);
+  (void)hipFree(p->work_p);
   (void)hipFree(p->dev_err);
   bm_getrf_ws_destroy(p->gws);
   for (int i = 0; i < BM_NPHASE; ++i)
@@ -67,6 +70,12 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
   ok = ok && hipMalloc(&p->lu, sizeof(cplx) * nf * nf) == hipSuccess;
   ok = ok && hipMalloc(&p->ipiv, sizeof(int32_t) * nf) == hipSuccess;
   ok = ok && hipMalloc(&p->dinv, sizeof(cplx) * nblk * 2 * BM_DIAG_NB * BM_DIAG_NB) == hipSuccess;
+  ok = ok && hipMalloc(&p->perm, sizeof(int32_t) * nf) == hipSuccess;
+  ok = ok && hipMalloc(&p->work_g, sizeof(cplx) * nf * BM_MAX_NRHS) == hipSuccess;
+  if (formulation == BM_MIXED) {
+    size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
+    ok = ok && hipMalloc(&p->work_p, sizeof(cplx) * (wp > w2 ? wp : w2)) == hipSuccess;
+  }
   ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 2) == hipSuccess;
   if (ok) p->gws = bm_getrf_ws_create((int)nf);
   if (!ok || !p->gws) {
@@ -164,6 +173,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   phase_begin(p, BM_PH_LU);
   rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws);
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
+  if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);
   if (rc) return rc;
   p->state = BM_ST_FACTORED;
@@ -181,7 +191,6 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv,
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   const cplx *B = (const cplx *)Bv;
   cplx *X = (cplx *)Xv;
-  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   phase_begin(p, BM_PH_SOLVE);
   for (int r0 = 0; r0 < nrhs; r0 += BM_MAX_NRHS) {
     const int nr = (nrhs - r0 < BM_MAX_NRHS) ? nrhs - r0 : BM_MAX_NRHS;
@@ -190,19 +199,22 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv,
     BM_HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(cplx) * ldx, Bc, sizeof(cplx) * ldb, sizeof(cplx) * rows, nr,
                                 hipMemcpyDeviceToDevice, p->stream));
     cplx *X3 = (p->form == BM_MIXED) ? Xc + 2 * n : Xc;
+    cplx *Y = p->work_g;  // nf x nr, ld nf
     int rc;
     if (p->form == BM_MIXED) {
       // Corollary lem:for_ssm_RHS: c = b3 - M31 b1 - M32 b2 = b3 - Bot [b1; b2]
-      rc = bm_launch_zgemm(p->stream, n, nr, 2 * n, mone, p->bot, n, Xc, ldx, one, X3, ldx);
+      rc = bm_launch_gemv_sub(p->stream, n, 2 * n, nr, p->bot, n, Xc, ldx, X3, ldx, p->work_p);
       if (rc) return rc;
     }
-    rc = bm_launch_rhs_swaps(p->stream, p->gws, nr, X3, ldx);
-    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, X3, ldx, nr, p->dev_err);
-    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, X3, ldx, nr, p->dev_err);
+    rc = bm_launch_gather(p->stream, nf, nr, p->perm, X3, ldx, Y, nf);
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
     if (rc) return rc;
+    BM_HIP_TRY(hipMemcpy2DAsync(X3, sizeof(cplx) * ldx, Y, sizeof(cplx) * nf, sizeof(cplx) * nf, nr,
+                                hipMemcpyDeviceToDevice, p->stream));
     if (p->form == BM_MIXED) {
       // x1 = b1 - M13 z3, x2 = b2 - M23 z3:  [x1; x2] = [b1; b2] - Top z3
-      rc = bm_launch_zgemm(p->stream, 2 * n, nr, n, mone, p->top, 2 * n, X3, ldx, one, Xc, ldx);
+      rc = bm_launch_gemv_sub(p->stream, 2 * n, n, nr, p->top, 2 * n, Y, nf, Xc, ldx, p->work_p);
       if (rc) return rc;
     }
   }

@@ -57,6 +57,46 @@ __device__ inline cplx csqrt_d(cplx w) {
 }
 
 // ---------------------------------------------------------------------------
+// factorisation workspace and cross-workgroup helpers
+// ---------------------------------------------------------------------------
+#define LU_NB 64                   // LU panel width
+#define BM_DIAG_NB 64              // block size of the triangular solves
+#define SWP_STRIDE (1 + 4 * LU_NB) // per panel: count, then (dst, src) row pairs
+#define SPIN_LIMIT (1L << 24)      // bound of every device-side wait
+#define BM_FLAG_STRIDE 32          // int32 words between completion flags (one 128-byte line each)
+
+struct bm_getrf_ws {
+  int n, npanel;
+  cplx *slots;         // 2 buffers of [LU_NB columns][workgroups][LU_NB + 1] exchange records
+  cplx *dslots;        // 2 buffers of [LU_NB columns][LU_NB] diagonal rows
+  int32_t *swp;        // per panel: count, then (dst, src) pairs
+  cplx *linv;          // inverse of the current panel's unit lower 64 x 64 block
+  int32_t *solve_sync; // tickets and flags for the blocked triangular solves
+};
+
+__device__ inline unsigned long long ld_agent(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline cplx ld_cplx_agent(const cplx *p) {
+  const unsigned long long *q = (const unsigned long long *)p;
+  return cmk(__longlong_as_double((long long)ld_agent(q)), __longlong_as_double((long long)ld_agent(q + 1)));
+}
+__device__ inline void st_cplx_agent(cplx *p, cplx v) {
+  unsigned long long *q = (unsigned long long *)p;
+  st_agent(q, (unsigned long long)__double_as_longlong(v.x));
+  st_agent(q + 1, (unsigned long long)__double_as_longlong(v.y));
+}
+__device__ inline double l1abs(cplx v) { return fabs(v.x) + fabs(v.y); }
+// candidate order: larger value wins, then the smaller row
+__device__ inline bool better(double v, long g, double bv, long bg) {
+  return (v > bv) || (v == bv && g >= 0 && (bg < 0 || g < bg));
+}
+
+
+// ---------------------------------------------------------------------------
 // problem handle
 // ---------------------------------------------------------------------------
 struct bm_phys {
@@ -68,7 +108,6 @@ enum { BM_ST_CREATED = 0, BM_ST_ASSEMBLED = 1, BM_ST_FACTORED = 2 };
 #define BM_EV_RING 64
 enum { BM_PH_ASSEMBLE = 0, BM_PH_SCHUR = 1, BM_PH_LU = 2, BM_PH_SOLVE = 3, BM_PH_FAR = 4, BM_NPHASE = 5 };
 
-struct bm_getrf_ws;  // panel-factorisation workspace (bm_getrf.hip)
 
 struct bm_problem {
   int n;                // nodes N
@@ -85,7 +124,10 @@ struct bm_problem {
   cplx *bot;            // mixed: [M31 M32], N x 2N, ld N
   cplx *lu;             // factor storage: U33 (mixed, N x N) or the ordinary 2N x 2N matrix
   int32_t *ipiv;        // nf, 0-based LAPACK-style interchanges
+  int32_t *perm;        // nf: row perm[i] of the factored matrix is row i of P A
   cplx *dinv;           // inverses of the 64 x 64 diagonal blocks of L and U
+  cplx *work_g;         // nf x BM_MAX_NRHS: permuted right-hand sides
+  cplx *work_p;         // split-K partial sums of the skinny GEMMs
   int32_t *dev_err;     // device-side error flag and getrf info: [0] error, [1] info
   bm_getrf_ws *gws;
 
@@ -107,20 +149,23 @@ int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *
                     const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
 
 // LU
-size_t bm_getrf_ws_bytes(int n);
 bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                  bm_getrf_ws *w);
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);
 
-// solve support: the factorisation's row interchanges applied to right-hand sides,
-// and the blocked triangular solves (lower: unit L, else U) in place on X (n x nrhs)
-int bm_launch_rhs_swaps(hipStream_t s, bm_getrf_ws *w, int nrhs, cplx *X, int64_t ldx);
+// solve support (bm_solve.hip): the composed row permutation, gathers, the skinny
+// GEMM C -= A B, and the blocked triangular solves (lower: unit L, else U) on X
+int bm_launch_perm(hipStream_t s, bm_getrf_ws *w, int nf, int32_t *perm);
+int bm_launch_gather(hipStream_t s, int nf, int nrhs, const int32_t *perm, const cplx *X, int64_t ldx, cplx *Y,
+                     int64_t ldy);
+size_t bm_gemv_work_elems(int m, int k);
+int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64_t lda, const cplx *B, int64_t ldb,
+                       cplx *C, int64_t ldc, cplx *work);
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
 
-#define BM_DIAG_NB 64
 
 #define BM_HIP_TRY(expr)                         \
   do {                                           \

@@ -1,0 +1,288 @@
+// Multi-right-hand-side solve with the factors (Corollary lem:for_ssm_RHS):
+//   c  = b3 - [M31 M32][b1; b2]        skinny GEMM (split-K, HBM bound)
+//   z3 = U^{-1} L^{-1} P c             row permutation, blocked triangular solves
+//   [x1; x2] = [b1; b2] - [M13; M23] z3 skinny GEMM
+// All kernels are deterministic: no floating-point atomics, fixed reduction order.
+#include "bm_internal.h"
+
+// ---------------------------------------------------------------------------
+// row permutation of the factorisation: perm[i] = original row at position i of
+// P A, composed panel by panel from each panel's (dst, src) pairs
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void perm_kernel(int nf, int npanel, const int32_t *swp, int32_t *perm,
+                                                     int use_lds) {
+  extern __shared__ int32_t sp[];
+  int32_t *pm = use_lds ? sp : perm;
+  __shared__ int32_t tmp[2 * LU_NB];
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) pm[i] = i;
+  __syncthreads();
+  for (int pn = 0; pn < npanel; ++pn) {
+    const int32_t *s = swp + (size_t)pn * SWP_STRIDE;
+    const int np = s[0];
+    for (int e = threadIdx.x; e < np; e += blockDim.x) tmp[e] = pm[s[2 + 2 * e]];
+    __syncthreads();
+    for (int e = threadIdx.x; e < np; e += blockDim.x) pm[s[1 + 2 * e]] = tmp[e];
+    __syncthreads();
+  }
+  if (use_lds)
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) perm[i] = pm[i];
+}
+
+int bm_launch_perm(hipStream_t s, bm_getrf_ws *w, int nf, int32_t *perm) {
+  const int use_lds = (nf <= 32768) ? 1 : 0;
+  const size_t lds = use_lds ? sizeof(int32_t) * (size_t)nf : 0;
+  hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(1024), lds, s, nf, w->npanel, (const int32_t *)w->swp, perm, use_lds);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+// Y[i, r] = X[perm[i], r]
+__global__ void gather_kernel(int nf, int nrhs, const int32_t *perm, const cplx *X, long ldx, cplx *Y, long ldy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < nf && r < nrhs) Y[i + (long)r * ldy] = X[perm[i] + (long)r * ldx];
+}
+
+int bm_launch_gather(hipStream_t s, int nf, int nrhs, const int32_t *perm, const cplx *X, int64_t ldx, cplx *Y,
+                     int64_t ldy) {
+  hipLaunchKernelGGL(gather_kernel, dim3((nf + 255) / 256, nrhs), dim3(256), 0, s, nf, nrhs, perm, X, (long)ldx, Y,
+                     (long)ldy);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// skinny GEMM  C = C - A B  (A m x k column-major, B k x nr, nr <= BM_MAX_NRHS)
+// stage 1: workgroup (row block, k split) -> partial sums; thread = row, the
+//          k-slice of B staged in LDS and broadcast to the 256 rows
+// stage 2: partials summed in split order and subtracted from C
+// ---------------------------------------------------------------------------
+#define GV_ROWS 256
+#define GV_KC 32
+__global__ __launch_bounds__(256) void gemv_partial_kernel(int m, int k, int nr, int kchunk, const cplx *A, long lda,
+                                                           const cplx *B, long ldb, cplx *part) {
+  __shared__ cplx Bs[GV_KC][BM_MAX_NRHS];
+  const int i = blockIdx.x * GV_ROWS + threadIdx.x;
+  const int ks = blockIdx.y;
+  const int k0 = ks * kchunk, k1 = (k0 + kchunk < k) ? k0 + kchunk : k;
+  cplx acc[BM_MAX_NRHS];
+#pragma unroll
+  for (int r = 0; r < BM_MAX_NRHS; ++r) acc[r] = cmk(0, 0);
+  for (int kb = k0; kb < k1; kb += GV_KC) {
+    const int kn = (k1 - kb < GV_KC) ? k1 - kb : GV_KC;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kn * nr; idx += 256) {
+      const int kk = idx % kn, r = idx / kn;
+      Bs[kk][r] = B[(kb + kk) + (long)r * ldb];
+    }
+    __syncthreads();
+    if (i < m) {
+      for (int kk = 0; kk < kn; ++kk) {
+        const cplx a = A[i + (long)(kb + kk) * lda];
+#pragma unroll
+        for (int r = 0; r < BM_MAX_NRHS; ++r)
+          if (r < nr) acc[r] = cadd(acc[r], cmul(a, Bs[kk][r]));
+      }
+    }
+  }
+  if (i < m) {
+    cplx *pp = part + (size_t)ks * m * nr;
+#pragma unroll
+    for (int r = 0; r < BM_MAX_NRHS; ++r)
+      if (r < nr) pp[i + (size_t)r * m] = acc[r];
+  }
+}
+
+__global__ void gemv_reduce_kernel(int m, int nr, int nsplit, const cplx *part, cplx *C, long ldc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= m || r >= nr) return;
+  cplx s = cmk(0, 0);
+  for (int ks = 0; ks < nsplit; ++ks) s = cadd(s, part[(size_t)ks * m * nr + i + (size_t)r * m]);
+  C[i + (long)r * ldc] = csub(C[i + (long)r * ldc], s);
+}
+
+size_t bm_gemv_work_elems(int m, int k) {
+  const int rb = (m + GV_ROWS - 1) / GV_ROWS;
+  int ns = 1024 / rb;
+  if (ns < 1) ns = 1;
+  const int maxs = (k + GV_KC - 1) / GV_KC;
+  if (ns > maxs) ns = maxs;
+  return (size_t)ns * m * BM_MAX_NRHS;
+}
+
+int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64_t lda, const cplx *B, int64_t ldb,
+                       cplx *C, int64_t ldc, cplx *work) {
+  if (m <= 0 || nr <= 0 || k <= 0) return BM_OK;
+  if (nr > BM_MAX_NRHS) return BM_E_ARG;
+  const int rb = (m + GV_ROWS - 1) / GV_ROWS;
+  int ns = 1024 / rb;
+  if (ns < 1) ns = 1;
+  const int maxs = (k + GV_KC - 1) / GV_KC;
+  if (ns > maxs) ns = maxs;
+  int kchunk = (k + ns - 1) / ns;
+  kchunk = ((kchunk + GV_KC - 1) / GV_KC) * GV_KC;
+  ns = (k + kchunk - 1) / kchunk;
+  hipLaunchKernelGGL(gemv_partial_kernel, dim3(rb, ns), dim3(256), 0, s, m, k, nr, kchunk, A, (long)lda, B, (long)ldb,
+                     work);
+  BM_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3((m + 255) / 256, nr), dim3(256), 0, s, m, nr, ns, (const cplx *)work, C,
+                     (long)ldc);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// blocked triangular solve with the inverted 64 x 64 diagonal blocks
+//   lower (unit):  x_b = Linv_b (c_b - sum_{k<b} L_bk x_k)
+//   upper:         x_b = Uinv_b (c_b - sum_{k>b} U_bk x_k)
+// One workgroup per block.  Blocks take tickets in launch order, so a workgroup
+// only waits for blocks held by workgroups that started before it; the
+// off-diagonal tile of each dependency is fetched into registers before its flag
+// is awaited.
+// ---------------------------------------------------------------------------
+#define TS_NB BM_DIAG_NB
+#define TS_RG (BM_MAX_NRHS / 4)  // right-hand sides per thread
+
+// acc[u] += sign * sum_{s < kn} M[rr][s] Zs[s][rg + 4u]: eight LDS loads of M grouped,
+// two partial sums per output to shorten the dependency chains.
+__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int rr, int rg, int kn,
+                                int nper, cplx *acc, double sign) {
+  cplx p0[TS_RG], p1[TS_RG];
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u) p0[u] = p1[u] = cmk(0, 0);
+  for (int s0 = 0; s0 < kn; s0 += 8) {
+    cplx m[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) m[v] = (s0 + v < kn) ? M[rr][s0 + v] : cmk(0, 0);
+#pragma unroll
+    for (int u = 0; u < TS_RG; ++u) {
+      if (u < nper) {
+#pragma unroll
+        for (int v = 0; v < 8; v += 2) {
+          if (s0 + v < kn) p0[u] = cadd(p0[u], cmul(m[v], Zs[s0 + v][rg + 4 * u]));
+          if (s0 + v + 1 < kn) p1[u] = cadd(p1[u], cmul(m[v + 1], Zs[s0 + v + 1][rg + 4 * u]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u)
+    if (u < nper) acc[u] = cadd(acc[u], cscale(cadd(p0[u], p1[u]), sign));
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long ld, const cplx *dinv, cplx *X, long ldx,
+                                                   int nrhs, int32_t *ticket, int32_t *flags, int32_t *dev_err) {
+  __shared__ int s_t;
+  __shared__ cplx Ls[TS_NB][TS_NB + 1];
+  __shared__ cplx Z[TS_NB][BM_MAX_NRHS + 1];
+  const int nblk = (n + TS_NB - 1) / TS_NB;
+  if (threadIdx.x == 0) s_t = atomicAdd(ticket, 1);
+  __syncthreads();
+  const int t = s_t;
+  const int b = LOWER ? t : nblk - 1 - t;
+  const int o = b * TS_NB;
+  const int nb = (n - o < TS_NB) ? n - o : TS_NB;
+  const int rr = threadIdx.x % TS_NB, rg = threadIdx.x / TS_NB;  // row, right-hand-side group
+  const int nper = (nrhs + 3) / 4;
+  cplx acc[TS_RG];
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u) {
+    const int rs = rg + 4 * u;
+    acc[u] = (u < nper && rr < nb && rs < nrhs) ? X[(o + rr) + (long)rs * ldx] : cmk(0, 0);
+  }
+  // the inverse diagonal block is needed last; fetch it first
+  const cplx *Di = dinv + (size_t)b * 2 * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
+  cplx dv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dv[e] = Di[threadIdx.x + 256 * e];
+  const int ndep = LOWER ? b : nblk - 1 - b;
+  cplx lt[16];  // this thread's 16 elements of the next 64 x 64 tile
+  auto fetch = [&](int k) {
+    const int ko = k * TS_NB;
+    const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      const int r = idx % TS_NB, c = idx / TS_NB;
+      lt[e] = (r < nb && c < kn) ? LU[(o + r) + (long)(ko + c) * ld] : cmk(0, 0);
+    }
+  };
+  if (ndep > 0) fetch(LOWER ? 0 : nblk - 1);
+  for (int d = 0; d < ndep; ++d) {
+    const int k = LOWER ? d : nblk - 1 - d;  // dependencies in the order they are solved
+    const int ko = k * TS_NB;
+    const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      Ls[idx % TS_NB][idx / TS_NB] = lt[e];
+    }
+    if (d + 1 < ndep) fetch(LOWER ? d + 1 : nblk - 2 - d);
+    if (threadIdx.x == 0) {
+      long spins = 0;
+      while (__hip_atomic_load(flags + (size_t)k * BM_FLAG_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if (++spins > SPIN_LIMIT) { atomicOr(dev_err, 1); break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+    {
+      // all loads of the solved block are issued before any is stored to LDS
+      cplx zv[TS_NB * BM_MAX_NRHS / 256];
+#pragma unroll
+      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
+        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
+        if (sr < kn && c < nrhs) zv[e] = ld_cplx_agent(X + (ko + sr) + (long)c * ldx);
+      }
+#pragma unroll
+      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
+        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
+        if (sr < kn && c < nrhs) Z[sr][c] = zv[e];
+      }
+    }
+    __syncthreads();
+    block_mv(Ls, Z, rr, rg, kn, nper, acc, -1.0);
+    __syncthreads();
+  }
+  // diagonal block: x_b = inv(D_b) acc
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = threadIdx.x + 256 * e;
+    Ls[idx % TS_NB][idx / TS_NB] = dv[e];
+  }
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u)
+    if (u < nper && rg + 4 * u < nrhs) Z[rr][rg + 4 * u] = acc[u];
+  __syncthreads();
+  cplx xv[TS_RG];
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u) xv[u] = cmk(0, 0);
+  block_mv(Ls, Z, rr, rg, nb, nper, xv, 1.0);
+#pragma unroll
+  for (int u = 0; u < TS_RG; ++u) {
+    const int rs = rg + 4 * u;
+    if (u < nper && rs < nrhs && rr < nb) X[(o + rr) + (long)rs * ldx] = xv[u];
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)b * BM_FLAG_STRIDE, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
+                   cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
+  if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
+  const int nblk = (n + TS_NB - 1) / TS_NB;
+  int32_t *ticket = w->solve_sync, *flags = w->solve_sync + 8;
+  BM_HIP_TRY(hipMemsetAsync(w->solve_sync, 0, sizeof(int32_t) * (size_t)(BM_FLAG_STRIDE * nblk + 8), s));
+  if (lower)
+    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
+                       ticket, flags, dev_err);
+  else
+    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
+                       ticket, flags, dev_err);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
