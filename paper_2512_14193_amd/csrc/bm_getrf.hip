@@ -445,7 +445,8 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
   ok = ok && hipMalloc(&w->dslots, sizeof(cplx) * 2 * LU_NB * LU_NB) == hipSuccess;
   ok = ok && hipMalloc(&w->swp, sizeof(int32_t) * (size_t)w->npanel * SWP_STRIDE) == hipSuccess;
   ok = ok && hipMalloc(&w->linv, sizeof(cplx) * TI_N * TI_N) == hipSuccess;
-  ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * (size_t)(BM_FLAG_STRIDE * nblk + 8)) == hipSuccess;
+  ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * 8) == hipSuccess;
+  ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS) == hipSuccess;
   if (!ok) {
     bm_getrf_ws_destroy(w);
     return nullptr;
@@ -460,6 +461,7 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   (void)hipFree(w->swp);
   (void)hipFree(w->linv);
   (void)hipFree(w->solve_sync);
+  (void)hipFree(w->zbuf);
   delete w;
 }
 

@@ -63,7 +63,6 @@ __device__ inline cplx csqrt_d(cplx w) {
 #define BM_DIAG_NB 64              // block size of the triangular solves
 #define SWP_STRIDE (1 + 4 * LU_NB) // per panel: count, then (dst, src) row pairs
 #define SPIN_LIMIT (1L << 24)      // bound of every device-side wait
-#define BM_FLAG_STRIDE 32          // int32 words between completion flags (one 128-byte line each)
 
 struct bm_getrf_ws {
   int n, npanel;
@@ -71,7 +70,8 @@ struct bm_getrf_ws {
   cplx *dslots;        // 2 buffers of [LU_NB columns][LU_NB] diagonal rows
   int32_t *swp;        // per panel: count, then (dst, src) pairs
   cplx *linv;          // inverse of the current panel's unit lower 64 x 64 block
-  int32_t *solve_sync; // tickets and flags for the blocked triangular solves
+  int32_t *solve_sync; // ticket counter of the blocked triangular solves
+  cplx *zbuf;          // solved blocks published by the triangular solves
 };
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {

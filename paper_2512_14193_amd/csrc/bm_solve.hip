@@ -137,43 +137,43 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 //   lower (unit):  x_b = Linv_b (c_b - sum_{k<b} L_bk x_k)
 //   upper:         x_b = Uinv_b (c_b - sum_{k>b} U_bk x_k)
 // One workgroup per block.  Blocks take tickets in launch order, so a workgroup
-// only waits for blocks held by workgroups that started before it; the
-// off-diagonal tile of each dependency is fetched into registers before its flag
-// is awaited.
+// only waits for blocks held by workgroups that started before it.  A solved block
+// is published to zbuf (pre-filled with an all-ones pattern) with agent-scope
+// stores and consumers poll its words until none is the pattern: the data is the
+// synchronisation.  The next off-diagonal tile (and, before the last dependency,
+// the inverse diagonal block) is fetched into registers while the current one is
+// consumed.
 // ---------------------------------------------------------------------------
 #define TS_NB BM_DIAG_NB
 #define TS_RG (BM_MAX_NRHS / 4)  // right-hand sides per thread
+#define ZSENT 0xFFFFFFFFFFFFFFFFULL
 
-// acc[u] += sign * sum_{s < kn} M[rr][s] Zs[s][rg + 4u]: eight LDS loads of M grouped,
-// two partial sums per output to shorten the dependency chains.
-__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int rr, int rg, int kn,
-                                int nper, cplx *acc, double sign) {
-  cplx p0[TS_RG], p1[TS_RG];
-#pragma unroll
-  for (int u = 0; u < TS_RG; ++u) p0[u] = p1[u] = cmk(0, 0);
-  for (int s0 = 0; s0 < kn; s0 += 8) {
+// acc[u] += sign * sum_{s < 64} M[rr][s] Zs[s][rg + 4u].  Tiles are zero-padded to
+// 64 x 64, so every loop has a fixed trip count and the LDS loads of a group of
+// eight are issued together.
+__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int rr, int rg,
+                                int nper, cplx (&acc)[TS_RG], double sign) {
+#pragma unroll 2
+  for (int s0 = 0; s0 < TS_NB; s0 += 8) {
     cplx m[8];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) m[v] = (s0 + v < kn) ? M[rr][s0 + v] : cmk(0, 0);
+    for (int v = 0; v < 8; ++v) m[v] = cscale(M[rr][s0 + v], sign);
 #pragma unroll
     for (int u = 0; u < TS_RG; ++u) {
       if (u < nper) {
+        cplx z[8];
 #pragma unroll
-        for (int v = 0; v < 8; v += 2) {
-          if (s0 + v < kn) p0[u] = cadd(p0[u], cmul(m[v], Zs[s0 + v][rg + 4 * u]));
-          if (s0 + v + 1 < kn) p1[u] = cadd(p1[u], cmul(m[v + 1], Zs[s0 + v + 1][rg + 4 * u]));
-        }
+        for (int v = 0; v < 8; ++v) z[v] = Zs[s0 + v][rg + 4 * u];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u] = cadd(acc[u], cmul(m[v], z[v]));
       }
     }
   }
-#pragma unroll
-  for (int u = 0; u < TS_RG; ++u)
-    if (u < nper) acc[u] = cadd(acc[u], cscale(cadd(p0[u], p1[u]), sign));
 }
 
 template <bool LOWER>
 __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long ld, const cplx *dinv, cplx *X, long ldx,
-                                                   int nrhs, int32_t *ticket, int32_t *flags, int32_t *dev_err) {
+                                                   int nrhs, int32_t *ticket, cplx *zbuf, int32_t *dev_err) {
   __shared__ int s_t;
   __shared__ cplx Ls[TS_NB][TS_NB + 1];
   __shared__ cplx Z[TS_NB][BM_MAX_NRHS + 1];
@@ -192,14 +192,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
     const int rs = rg + 4 * u;
     acc[u] = (u < nper && rr < nb && rs < nrhs) ? X[(o + rr) + (long)rs * ldx] : cmk(0, 0);
   }
-  // the inverse diagonal block is needed last; fetch it first
-  const cplx *Di = dinv + (size_t)b * 2 * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
-  cplx dv[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) dv[e] = Di[threadIdx.x + 256 * e];
   const int ndep = LOWER ? b : nblk - 1 - b;
-  cplx lt[16];  // this thread's 16 elements of the next 64 x 64 tile
-  auto fetch = [&](int k) {
+  const cplx *Di = dinv + (size_t)b * 2 * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
+  cplx lt[16];  // this thread's 16 elements of the next 64 x 64 tile (column-major order)
+  auto fetch_tile = [&](int k) {
     const int ko = k * TS_NB;
     const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
 #pragma unroll
@@ -209,80 +205,106 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
       lt[e] = (r < nb && c < kn) ? LU[(o + r) + (long)(ko + c) * ld] : cmk(0, 0);
     }
   };
-  if (ndep > 0) fetch(LOWER ? 0 : nblk - 1);
+  auto fetch_dinv = [&]() {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lt[e] = Di[threadIdx.x + 256 * e];
+  };
+  if (ndep > 0) fetch_tile(LOWER ? 0 : nblk - 1);
+  else fetch_dinv();
+  bool ok = true;
   for (int d = 0; d < ndep; ++d) {
     const int k = LOWER ? d : nblk - 1 - d;  // dependencies in the order they are solved
-    const int ko = k * TS_NB;
-    const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
+    const int kn = (n - k * TS_NB < TS_NB) ? n - k * TS_NB : TS_NB;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int idx = threadIdx.x + 256 * e;
       Ls[idx % TS_NB][idx / TS_NB] = lt[e];
     }
-    if (d + 1 < ndep) fetch(LOWER ? d + 1 : nblk - 2 - d);
-    if (threadIdx.x == 0) {
+    if (d + 1 < ndep) fetch_tile(LOWER ? d + 1 : nblk - 2 - d);
+    else fetch_dinv();
+    {
+      // poll the solved block k: every load of the round is issued before any is checked
+      const unsigned long long *zb = (const unsigned long long *)(zbuf + (size_t)k * TS_NB * BM_MAX_NRHS);
+      unsigned long long zx[TS_NB * BM_MAX_NRHS / 256], zy[TS_NB * BM_MAX_NRHS / 256];
+      bool need[TS_NB * BM_MAX_NRHS / 256];
+#pragma unroll
+      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
+        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
+        need[e] = (sr < kn && c < nrhs);
+        if (need[e]) {
+          zx[e] = ld_agent(zb + 2 * idx);
+          zy[e] = ld_agent(zb + 2 * idx + 1);
+        }
+      }
       long spins = 0;
-      while (__hip_atomic_load(flags + (size_t)k * BM_FLAG_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if (++spins > SPIN_LIMIT) { atomicOr(dev_err, 1); break; }
+      for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
+          if (need[e] && (zx[e] == ZSENT || zy[e] == ZSENT)) {
+            all = false;
+            const int idx = threadIdx.x + 256 * e;
+            zx[e] = ld_agent(zb + 2 * idx);
+            zy[e] = ld_agent(zb + 2 * idx + 1);
+          }
+        }
+        if (all) break;
+        if (++spins > SPIN_LIMIT) {
+          if (ok) atomicOr(dev_err, 1);
+          ok = false;
+          break;
+        }
         __builtin_amdgcn_s_sleep(1);
       }
-      __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    }
-    __syncthreads();
-    {
-      // all loads of the solved block are issued before any is stored to LDS
-      cplx zv[TS_NB * BM_MAX_NRHS / 256];
 #pragma unroll
       for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
         const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
-        if (sr < kn && c < nrhs) zv[e] = ld_cplx_agent(X + (ko + sr) + (long)c * ldx);
-      }
-#pragma unroll
-      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
-        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
-        if (sr < kn && c < nrhs) Z[sr][c] = zv[e];
+        // rows beyond a ragged block are zero so that the fixed-size products stay exact
+        Z[sr][c] = need[e] ? cmk(__longlong_as_double((long long)zx[e]), __longlong_as_double((long long)zy[e]))
+                           : cmk(0, 0);
       }
     }
     __syncthreads();
-    block_mv(Ls, Z, rr, rg, kn, nper, acc, -1.0);
+    block_mv(Ls, Z, rr, rg, nper, acc, -1.0);
     __syncthreads();
   }
-  // diagonal block: x_b = inv(D_b) acc
+  // diagonal block: x_b = inv(D_b) acc (the inverse is in lt)
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int idx = threadIdx.x + 256 * e;
-    Ls[idx % TS_NB][idx / TS_NB] = dv[e];
+    Ls[idx % TS_NB][idx / TS_NB] = lt[e];
   }
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u)
-    if (u < nper && rg + 4 * u < nrhs) Z[rr][rg + 4 * u] = acc[u];
+    if (rg + 4 * u < BM_MAX_NRHS) Z[rr][rg + 4 * u] = (u < nper && rg + 4 * u < nrhs) ? acc[u] : cmk(0, 0);
   __syncthreads();
   cplx xv[TS_RG];
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u) xv[u] = cmk(0, 0);
-  block_mv(Ls, Z, rr, rg, nb, nper, xv, 1.0);
+  block_mv(Ls, Z, rr, rg, nper, xv, 1.0);
+  cplx *zo = zbuf + (size_t)b * TS_NB * BM_MAX_NRHS;
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u) {
     const int rs = rg + 4 * u;
-    if (u < nper && rs < nrhs && rr < nb) X[(o + rr) + (long)rs * ldx] = xv[u];
+    if (u < nper && rs < nrhs && rr < nb) {
+      X[(o + rr) + (long)rs * ldx] = xv[u];
+      st_cplx_agent(zo + rr + rs * TS_NB, xv[u]);
+    }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)b * BM_FLAG_STRIDE, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
   if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
   const int nblk = (n + TS_NB - 1) / TS_NB;
-  int32_t *ticket = w->solve_sync, *flags = w->solve_sync + 8;
-  BM_HIP_TRY(hipMemsetAsync(w->solve_sync, 0, sizeof(int32_t) * (size_t)(BM_FLAG_STRIDE * nblk + 8), s));
+  BM_HIP_TRY(hipMemsetAsync(w->solve_sync, 0, sizeof(int32_t) * 8, s));
+  BM_HIP_TRY(hipMemsetAsync(w->zbuf, 0xFF, sizeof(cplx) * (size_t)nblk * TS_NB * BM_MAX_NRHS, s));
   if (lower)
     hipLaunchKernelGGL(trsv_kernel<true>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
-                       ticket, flags, dev_err);
+                       w->solve_sync, w->zbuf, dev_err);
   else
     hipLaunchKernelGGL(trsv_kernel<false>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
-                       ticket, flags, dev_err);
+                       w->solve_sync, w->zbuf, dev_err);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
