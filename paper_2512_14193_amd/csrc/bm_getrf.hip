@@ -3,19 +3,21 @@
 // Used for U33 = -M31 M13 - M32 M23 (Theorem thm:LU) and, as the comparator, for
 // the 2N x 2N ordinary matrix.  Per panel of jb <= 64 columns starting at column j:
 //
-//  1. panel_kernel (cooperative launch, P workgroups): the (N - j) x jb panel is
-//     distributed over P workgroups by contiguous row ranges and held in LDS for the
-//     whole panel.  For every column: each workgroup finds its local pivot candidate
-//     (largest |Re| + |Im|, smallest row on ties) by a wave64 shuffle reduction and a
-//     cross-wave step in LDS and publishes the candidate value with the candidate's
-//     whole panel row; every workgroup reads all P records, picks the same winner,
-//     exchanges rows in LDS and applies the rank-1 update to its rows.  One
-//     cross-workgroup exchange (a single round trip) per column.
-//  2. swap_kernel: the panel's row interchanges, composed into one permutation of at
-//     most 2 jb rows, applied to every column outside the panel.
-//  3. trsm_kernel: U12 = L11^{-1} A12 (unit lower, jb x jb) for the columns right of
-//     the panel, forward substitution in LDS.
-//  4. trailing update A22 -= L21 U12 with the MFMA GEMM.
+//  1. panel_kernel (P workgroups of 512 threads, all resident at once): the
+//     (n - j) x jb panel lives in registers for the whole panel, one column per lane
+//     and RPT consecutive rows per wavefront (workgroups and wavefronts in row
+//     order).  In the rank-1 update of column c every row takes its multiplier
+//     from lane c by a readlane, so the update touches neither LDS nor memory.  The
+//     pivot search of column c + 1 is a scan of lane c + 1 over its rows, then a
+//     combine of the eight wavefronts in LDS; each workgroup publishes its candidate
+//     (value, row and the whole candidate row) in an exchange record, every
+//     workgroup reads all P records, picks the same winner and exchanges the two rows
+//     in registers.  One cross-workgroup round trip per column.
+//  2. swap_trsm_kernel: the panel's row interchanges, composed into one permutation
+//     of at most 2 jb rows, on every column outside the panel; for the columns right
+//     of the panel also U12 = L11^{-1} A12 by forward substitution, one wavefront per
+//     two columns with lane = row.
+//  3. trailing update A22 -= L21 U12 with the MFMA GEMM.
 //
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
@@ -23,15 +25,12 @@
 #include "bm_internal.h"
 #include "bm_trinv.h"
 
-#define PANEL_PMAX 256    // max workgroups of a panel launch
-#define PANEL_LDS_MAX (152 * 1024)
-
 // ---------------------------------------------------------------------------
 // 1. panel factorisation
 //
 // Exchange protocol: for column c every workgroup g writes one record
 //   slots[c][g] = { (value, row), candidate row (jb complex values) }
-// and the owner of row j + c also writes that row to dslots[c].  Slots are filled
+// and the owner of row j + c also writes that row after the P records.  Slots are filled
 // with an all-ones bit pattern before the panel starts (a NaN the arithmetic
 // never produces), each 8-byte word is written exactly once with an agent-scope
 // store, and readers poll each word with agent-scope loads until it differs from
@@ -39,29 +38,66 @@
 // one round trip per column.  With ONE_ROUND every workgroup receives all P
 // records at once; otherwise it receives the P headers and then the winner's row.
 // ---------------------------------------------------------------------------
-#define SENT 0xFFFFFFFFFFFFFFFFULL
-#define PNT 512   // threads per panel workgroup (8 waves)
+#define PANEL_PMAX 256            // max workgroups of a panel launch
+#define PANEL_ONE_ROUND_PMAX 32   // all records of a column are received at once up to this many workgroups
+#ifndef PANEL_TARGET_P
+#define PANEL_TARGET_P 32         // preferred workgroup count
+#endif
+#define SENT 0xFFFFFFFFFFFFFFFFULL  // empty exchange word (all ones)
+#define PNT 512                   // threads per panel workgroup (8 waves)
 #define PNW (PNT / 64)
-#define PANEL_ONE_ROUND_PMAX 40
-#define RECV_PT ((PANEL_ONE_ROUND_PMAX * (LU_NB + 1) + LU_NB + PNT - 1) / PNT)  // loads per thread per round
+#define PT_LD 65                  // leading dimension of the LDS transpose tile
+#define PANEL_REC_ELEMS (PANEL_ONE_ROUND_PMAX * (LU_NB + 1) > PANEL_PMAX ? PANEL_ONE_ROUND_PMAX * (LU_NB + 1) : PANEL_PMAX)
+#define PANEL_LDS_ELEMS (PANEL_REC_ELEMS > LU_NB * PT_LD ? PANEL_REC_ELEMS : LU_NB * PT_LD)
+#define PANEL_LDS ((size_t)PANEL_LDS_ELEMS * sizeof(cplx))  // records of a column, or the transpose tile
+#define RECV_PT ((PANEL_REC_ELEMS + LU_NB + PNT - 1) / PNT)  // loads per thread per round
 
-__device__ inline cplx poll_cplx(const cplx *p, int32_t *dev_err, bool &ok) {
-  const unsigned long long *q = (const unsigned long long *)p;
-  unsigned long long x = ld_agent(q), y = ld_agent(q + 1);
-  long spins = 0;
-  while (x == SENT || y == SENT) {
-    if (++spins > SPIN_LIMIT) {
+// Records of one column sit REC_STRIDE complex values (4 KiB) apart so that the
+// reads of a column spread over many memory channels instead of queueing on a few.
+#ifndef BM_REC_SPREAD
+#define BM_REC_SPREAD 0
+#endif
+#define REC_STRIDE 256
+#define SLOT_ELEMS ((size_t)LU_NB * (PANEL_PMAX + 1) * REC_STRIDE)  // complex values per slot buffer
+
+// 16-byte agent-coherent loads and stores of the exchange records: buffer
+// instructions with the sc1 cache-policy bit (agent scope on gfx94x / gfx950).
+// A record word reads as empty while either 8-byte half still holds the pattern.
+typedef int bm_v4i __attribute__((ext_vector_type(4)));
+#define BM_BUF_DW3 0x00020000  // buffer descriptor word 3 for raw (untyped) access on gfx9
+#define BM_CPOL_SC1 16
+__device__ inline __amdgpu_buffer_rsrc_t rec_rsrc(const cplx *slots) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)slots, 0, (int)(SLOT_ELEMS * sizeof(cplx)), BM_BUF_DW3);
+}
+__device__ inline bm_v4i rec_load(__amdgpu_buffer_rsrc_t r, int elem) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, elem * (int)sizeof(cplx), 0, BM_CPOL_SC1);
+}
+__device__ inline void rec_store(__amdgpu_buffer_rsrc_t r, int elem, cplx v) {
+  bm_v4i x;
+  x[0] = __double2loint(v.x);
+  x[1] = __double2hiint(v.x);
+  x[2] = __double2loint(v.y);
+  x[3] = __double2hiint(v.y);
+  __builtin_amdgcn_raw_buffer_store_b128(x, r, elem * (int)sizeof(cplx), 0, BM_CPOL_SC1);
+}
+__device__ inline bool rec_empty(bm_v4i v) { return (v[0] & v[1]) == -1 || (v[2] & v[3]) == -1; }
+__device__ inline cplx rec_value(bm_v4i v) { return cmk(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2])); }
+
+// one record value, polled until written (bounded)
+__device__ inline cplx rec_poll(__amdgpu_buffer_rsrc_t r, int elem, int32_t *dev_err, bool &ok) {
+  bm_v4i v = rec_load(r, elem);
+  const unsigned long long t0 = wall_clock64();
+  while (rec_empty(v)) {
+    if (!ok || wait_expired(t0)) {
       if (ok) atomicOr(dev_err, 1);
       ok = false;
       break;
     }
     __builtin_amdgcn_s_sleep(1);
-    if (x == SENT) x = ld_agent(q);
-    if (y == SENT) y = ld_agent(q + 1);
+    v = rec_load(r, elem);
   }
-  return cmk(__longlong_as_double((long long)x), __longlong_as_double((long long)y));
+  return rec_value(v);
 }
-
 
 // Wave-wide maximum of a double by DPP row operations (a few ALU cycles per step,
 // no LDS round trip); NaN entries are ignored.  Must be called with all 64 lanes
@@ -102,143 +138,176 @@ __device__ inline int wave_min_int(int x) {
   return x;
 }
 
-// Panel factorisation with a one-column lookahead.  Per column c:
-//   receive the records of column c, select the pivot, exchange rows gc and p,
-//   scale column c and update only column c + 1, find and publish the candidates
-//   of column c + 1 (the published rows are completed on the fly), and only then
-//   apply the rank-1 update of pivot c to columns c + 2 .. jb - 1, which overlaps
-//   the next exchange.  Invariant before the receive of column c: LDS rows hold all
-//   updates of pivots < c, except that rows awaiting the update of pivot c - 1 on
-//   columns > c get it in the deferred step at the top of the iteration.
-template <bool ONE_ROUND>
-__global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int rpw, int P,
-                                                    int32_t *ipiv, int32_t *dev_err, cplx *slots, cplx *dslots,
-                                                    cplx *next_slots, cplx *next_dslots, int next_words,
-                                                    int32_t *swp) {
-  extern __shared__ cplx smem[];
-  cplx *pan = smem;                      // jb x rpw, column-major: pan[c * rpw + r]
-  cplx *recv = smem + (size_t)jb * rpw;  // ONE_ROUND: P x (jb + 1); else P headers
-  __shared__ cplx drow[LU_NB], wrow[LU_NB], prow[LU_NB];
-  __shared__ double wv[PNW];
-  __shared__ int wr[PNW];
-  __shared__ int s_piv[LU_NB];
-  __shared__ int s_key[2 * LU_NB], s_val[2 * LU_NB];
+// value of lane l (wave-uniform l) in every lane
+__device__ inline double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline cplx readlane_c(cplx v, int l) { return cmk(readlane_f64(v.x, l), readlane_f64(v.y, l)); }
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = blockIdx.x;
+// component-wise select (keeps register arrays out of memory)
+__device__ inline cplx csel(bool c, cplx a, cplx b) { return cmk(c ? a.x : b.x, c ? a.y : b.y); }
+
+// 1/u for the pivot: the larger component is scaled to [0.5, 1) by an exact power
+// of two, then conj(u) / |u|^2 with a Newton-refined hardware reciprocal
+__device__ inline cplx pivot_recip(cplx u) {
+  int e = 0;
+  (void)frexp(fmax(fabs(u.x), fabs(u.y)), &e);
+  const cplx us = cmk(ldexp(u.x, -e), ldexp(u.y, -e));
+  const double d = fma(us.x, us.x, us.y * us.y);
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = ldexp(r, -e);
+  return cmk(us.x * r, -us.y * r);
+}
+
+// Panel factorisation, lane = column.  Wavefront w of workgroup g holds RPT
+// consecutive rows r0 + w RPT + i (i < RPT) of the panel, lane c holding column c,
+// in registers for the whole panel.  Per column c:
+//   receive the records of column c; every wavefront selects the same winner p;
+//   rows j + c and p exchange (the two wavefronts holding them copy the records);
+//   every row below j + c takes its multiplier l = a_c / u_c (computed in lane c,
+//   broadcast by readlane) and subtracts l times the pivot row from its columns
+//   > c; lane c + 1 scans the updated column for the candidates of column c + 1,
+//   the wavefronts combine in LDS and the workgroup publishes its record.
+// Exchange layout per column c (rs = record stride, cstride = complex values per column):
+//   slots[c * cstride + g * rs]  record of workgroup g: (value, row), then the row
+//   slots[c * cstride + P * rs]  the diagonal row j + c, by its owner
+// The P workgroups are blockIdx.x = xs g, g = 0 .. P - 1; the launch has xs P
+// workgroups and the others return at once (xs = 8 puts all P on one XCD).
+template <int RPT, bool ONE_ROUND>
+__global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
+                                                    int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
+                                                    int next_jb, int xs, int32_t *swp) {
+  constexpr int RPW = PNW * RPT;           // rows per workgroup
+  constexpr int CH = RPW < 64 ? RPW : 64;  // rows per transpose chunk
+  extern __shared__ cplx smem[];           // the records of one column, or the transpose tile
+  __shared__ cplx drow[LU_NB];
+  __shared__ cplx s_cand[PNW];             // per wavefront: (value, local row)
+
+  if ((int)blockIdx.x % xs) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = (int)blockIdx.x / xs;
   const int rec = jb + 1;
-  const long r0 = (long)j + (long)g * rpw;
-  const long r1 = (r0 + rpw < N) ? r0 + rpw : N;
-  const int nrows = (r1 > r0) ? (int)(r1 - r0) : 0;
-  // deferred update work split: threads t -> row t % rstride, column group t / rstride
-  const int rstride = (rpw <= 64) ? 64 : (rpw <= 128 ? 128 : 256);
-  const int ngrp = PNT / rstride;
+  const int rstr = BM_REC_SPREAD ? REC_STRIDE : rec;
+  const int cstride = BM_REC_SPREAD ? (P + 1) * REC_STRIDE : P * rec + jb;
+  const __amdgpu_buffer_rsrc_t rs = rec_rsrc(slots);
+  const long r0 = (long)j + (long)g * RPW;  // first row of the workgroup
+  const long wr0 = r0 + (long)wave * RPT;   // first row of the wavefront
+  const long wrem = (long)N - wr0;
+  const int wn = wrem <= 0 ? 0 : (wrem < RPT ? (int)wrem : RPT);  // rows of the wavefront inside the matrix
+  const bool col_ok = lane < jb;
   bool ok = true;
+  cplx a[RPT];
 
-  for (int idx = tid; idx < nrows * jb; idx += PNT) {
-    const int r = idx % nrows, c = idx / nrows;
-    pan[c * rpw + r] = A[(r0 + r) + (long)(j + c) * lda];
-  }
-  __syncthreads();
-
-  // local candidate of column `col` among local rows > `after` (global); writes wv/wr
-  auto local_candidate = [&](double v) {
-    double vm;
-    const int fl = wave_argmax_first(v, vm);
-    if (lane == 0) {
-      wv[wave] = (fl >= 0) ? vm : -1.0;
-      wr[wave] = (fl >= 0) ? wave * 64 + fl : -1;
+  // load: coalesced column reads into the LDS tile, then each wavefront takes its rows
+  for (int ch = 0; ch < RPW; ch += CH) {
+    for (int idx = tid; idx < CH * jb; idx += PNT) {
+      const int r = idx % CH, c = idx / CH;
+      const long gr = r0 + ch + r;
+      smem[c * PT_LD + r] = (gr < N) ? A[gr + (long)(j + c) * lda] : cmk(0, 0);
     }
-  };
-  // wave 0: publish the records of column c; row values of columns >= c + 1 still
-  // owe the update of pivot c - 1, applied here with the multiplier l of that row
-  auto publish = [&](int c) {
-    if (wave != 0) return;
-    const long gc = (long)j + c;
-    cplx *sc = slots + (size_t)c * P * rec;
-    double v = wv[0];
-    int lr = wr[0];
-    for (int w = 1; w < PNW; ++w)
-      if (wv[w] > v) { v = wv[w]; lr = wr[w]; }
-    const long gg = (lr >= 0) ? r0 + lr : -1;
-    const int rr = (lr >= 0) ? lr : 0;  // every record is filled, also without a candidate
-    const bool owns_diag = (gc >= r0 && gc < r1);
-    if (lane < jb) {
-      cplx x = pan[lane * rpw + rr];
-      if (c > 0 && lane > c) x = csub(x, cmul(pan[(c - 1) * rpw + rr], prow[lane]));
-      st_cplx_agent(sc + (size_t)g * rec + 1 + lane, x);
-      if (owns_diag) {
-        const int rd = (int)(gc - r0);
-        cplx y = pan[lane * rpw + rd];
-        if (c > 0 && lane > c) y = csub(y, cmul(pan[(c - 1) * rpw + rd], prow[lane]));
-        st_cplx_agent(dslots + (size_t)c * jb + lane, y);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int lr = wave * RPT + i - ch;
+      if (lr >= 0 && lr < CH) a[i] = csel(col_ok, smem[lane * PT_LD + (lr & (CH - 1))], cmk(0, 0));
+    }
+    __syncthreads();
+  }
+
+  // wavefront candidate of column cc among its rows > after: lane cc scans its rows
+  auto wave_candidate = [&](int cc, long after) __attribute__((always_inline)) {
+    double best = -1.0;
+    int bi = -1;
+    if (wr0 > after && wn == RPT) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const double v = l1abs(a[i]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const double v = (i < wn && wr0 + i > after) ? l1abs(a[i]) : -1.0;
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
       }
     }
-    if (lane == 0) st_cplx_agent(sc + (size_t)g * rec, cmk(v, (double)gg));
+    best = readlane_f64(best, cc);
+    bi = __builtin_amdgcn_readlane(bi, cc);
+    if (lane == 0) s_cand[wave] = cmk(best, (bi >= 0) ? (double)(wave * RPT + bi) : -1.0);
+  };
+  // records of column cc: the workgroup's best candidate with its whole row (every
+  // record is filled, also without a candidate), and the diagonal row by its owner
+  auto publish = [&](int cc) __attribute__((always_inline)) {
+    const cplx cw = (lane < PNW) ? s_cand[lane] : cmk(-1.0, -1.0);
+    double v;
+    const int fw = wave_argmax_first(cw.x, v);  // waves in row order: ties go to the smaller row
+    const int lr = (fw >= 0) ? (int)readlane_f64(cw.y, fw) : -1;
+    const int base = cc * cstride;
+    if (wave == ((lr >= 0) ? lr / RPT : 0)) {
+      const int ic = (lr >= 0) ? lr % RPT : -1;
+      cplx x = cmk(0, 0);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) x = csel(i == ic, a[i], x);
+      const int sc = base + g * rstr;
+      if (col_ok) rec_store(rs, sc + 1 + lane, x);
+      if (lane == 0) rec_store(rs, sc, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
+    }
+    const long id = (long)j + cc - wr0;
+    if (id >= 0 && id < wn) {
+      cplx y = cmk(0, 0);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) y = csel(i == (int)id, a[i], y);
+      if (col_ok) rec_store(rs, base + P * rstr + lane, y);
+    }
   };
 
-  // column 0: candidates over all rows, nothing pending
-  local_candidate((tid < nrows) ? l1abs(pan[tid]) : -1.0);
+  wave_candidate(0, (long)j - 1);
   __syncthreads();
   publish(0);
 
+  // interchange bookkeeping (wave 0 of workgroup 0): lane l holds the source row of
+  // panel position j + l, and of the l-th further row touched by the interchanges
+  int pcont = j + lane, epos = -1, econt = 0, nextra = 0;
+
   for (int c = 0; c < jb; ++c) {
     const long gc = (long)j + c;
-    cplx *sc = slots + (size_t)c * P * rec;
-    // deferred rank-1 update of pivot c - 1 on columns c + 1 .. jb - 1 (rows > gc - 1)
-    if (c > 0) {
-      const int r = tid % rstride, grp = tid / rstride;
-      if (r < nrows && r0 + r >= gc) {
-        const cplx l = pan[(c - 1) * rpw + r];
-        for (int cc0 = c + 1 + grp; cc0 < jb; cc0 += 8 * ngrp) {
-          cplx pv[8], av[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int cc = cc0 + u * ngrp;
-            if (cc < jb) {
-              pv[u] = prow[cc];
-              av[u] = pan[cc * rpw + r];
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int cc = cc0 + u * ngrp;
-            if (cc < jb) pan[cc * rpw + r] = csub(av[u], cmul(l, pv[u]));
-          }
-        }
-      }
-    }
+    const int base = c * cstride;
     // receive: every load of the round is issued before any is checked
     {
-      const int total = ONE_ROUND ? P * rec + jb : P + jb;
       const int hdr = ONE_ROUND ? P * rec : P;
-      unsigned long long vx[RECV_PT], vy[RECV_PT];
-      const unsigned long long *src[RECV_PT];
+      const int total = hdr + jb;
+      int ei[RECV_PT];
+      bm_v4i v[RECV_PT];
 #pragma unroll
       for (int e = 0; e < RECV_PT; ++e) {
         const int idx = tid + PNT * e;
-        src[e] = nullptr;
-        if (idx < total) {
-          const cplx *a = (idx < hdr) ? (ONE_ROUND ? sc + idx : sc + (size_t)idx * rec)
-                                      : dslots + (size_t)c * jb + (idx - hdr);
-          src[e] = (const unsigned long long *)a;
-          vx[e] = ld_agent(src[e]);
-          vy[e] = ld_agent(src[e] + 1);
-        }
+        ei[e] = (idx >= total) ? -1
+                : (idx >= hdr) ? base + P * rstr + (idx - hdr)
+                : ONE_ROUND    ? base + (idx / rec) * rstr + idx % rec
+                               : base + idx * rstr;
+        if (ei[e] >= 0) v[e] = rec_load(rs, ei[e]);
       }
-      long spins = 0;
+      const unsigned long long t0 = wall_clock64();
       for (;;) {
         bool all = true;
 #pragma unroll
         for (int e = 0; e < RECV_PT; ++e) {
-          if (src[e] && (vx[e] == SENT || vy[e] == SENT)) {
+          if (ei[e] >= 0 && rec_empty(v[e])) {
             all = false;
-            vx[e] = ld_agent(src[e]);
-            vy[e] = ld_agent(src[e] + 1);
+            v[e] = rec_load(rs, ei[e]);
           }
         }
         if (all) break;
-        if (++spins > SPIN_LIMIT) {
+        if (!ok || wait_expired(t0)) {
           if (ok) atomicOr(dev_err, 1);
           ok = false;
           break;
@@ -248,10 +317,9 @@ __global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, in
 #pragma unroll
       for (int e = 0; e < RECV_PT; ++e) {
         const int idx = tid + PNT * e;
-        if (idx < total) {
-          const cplx v = cmk(__longlong_as_double((long long)vx[e]), __longlong_as_double((long long)vy[e]));
-          if (idx < hdr) recv[idx] = v;
-          else drow[idx - hdr] = v;
+        if (ei[e] >= 0) {
+          if (idx < hdr) smem[idx] = rec_value(v[e]);
+          else drow[idx - hdr] = rec_value(v[e]);
         }
       }
     }
@@ -262,179 +330,242 @@ __global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, in
     long pw = -1;
     int ww = -1;
     if (P <= 64) {
-      const double hv = (lane < P) ? (ONE_ROUND ? recv[lane * rec] : recv[lane]).x : -1.0;
+      const cplx h = (lane < P) ? (ONE_ROUND ? smem[lane * rec] : smem[lane]) : cmk(-1.0, -1.0);
       double vm;
-      const int fl = wave_argmax_first(hv, vm);
+      const int fl = wave_argmax_first(h.x, vm);
       if (fl >= 0) {
         ww = fl;
         vw = vm;
-        pw = (long)(ONE_ROUND ? recv[fl * rec] : recv[fl]).y;
+        pw = (long)readlane_f64(h.y, fl);
       }
     } else {
       double lv = -1.0;
-      for (int t = lane; t < P; t += 64) lv = fmax(lv, (ONE_ROUND ? recv[t * rec] : recv[t]).x);
+      for (int t = lane; t < P; t += 64) lv = fmax(lv, (ONE_ROUND ? smem[t * rec] : smem[t]).x);
       lv = wave_max_f64(lv);
       int li = 0x7fffffff;
       if (lv >= 0.0)
         for (int t = lane; t < P; t += 64)
-          if ((ONE_ROUND ? recv[t * rec] : recv[t]).x == lv) { li = t; break; }
+          if ((ONE_ROUND ? smem[t * rec] : smem[t]).x == lv) {
+            li = t;
+            break;
+          }
       li = wave_min_int(li);
       if (li != 0x7fffffff) {
         ww = li;
         vw = lv;
-        pw = (long)(ONE_ROUND ? recv[li * rec] : recv[li]).y;
+        pw = (long)(ONE_ROUND ? smem[li * rec] : smem[li]).y;
       }
     }
     if (ww < 0) {  // no comparable candidate (a column of NaNs): keep the diagonal row, report it
       vw = 0.0;
       pw = gc;
     }
-    const cplx *pivrow;
-    if (ww < 0) {
-      pivrow = drow;
-    } else if (ONE_ROUND) {
-      pivrow = recv + (size_t)ww * rec + 1;
-    } else {
-      if (tid < jb) wrow[tid] = poll_cplx(sc + (size_t)ww * rec + 1 + tid, dev_err, ok);
-      __syncthreads();
-      pivrow = wrow;
-    }
+    // pivot row and old diagonal row, one column per lane
+    const cplx dr = csel(col_ok, drow[lane], cmk(0, 0));
+    cplx pr;
+    if (ww < 0) pr = dr;
+    else if (ONE_ROUND) pr = csel(col_ok, smem[ww * rec + 1 + lane], cmk(0, 0));
+    else pr = col_ok ? rec_poll(rs, base + ww * rstr + 1 + lane, dev_err, ok) : cmk(0, 0);
     const long p = pw;
-    if (tid == 0) {
-      s_piv[c] = (int)p;
-      if (g == 0) {
-        ipiv[gc] = (int32_t)p;
-        if (vw == 0.0 && dev_err[1] == 0) dev_err[1] = (int32_t)(gc + 1);
+    if (g == 0 && tid == 0) {
+      ipiv[gc] = (int32_t)p;
+      if (vw == 0.0 && dev_err[1] == 0) dev_err[1] = (int32_t)(gc + 1);
+    }
+    // row interchange in registers: row gc <- pivot row, row p <- old row gc
+    // (value selects on every slot: a conditional store would index a[] dynamically)
+    if (p != gc) {
+      const long ia = gc - wr0, ib = p - wr0;
+      if (ia >= 0 && ia < RPT) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) a[i] = csel(i == ia, pr, a[i]);
+      }
+      if (ib >= 0 && ib < RPT) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) a[i] = csel(i == ib, dr, a[i]);
       }
     }
-    // pivot row for the updates; row interchange in LDS (both rows come from records)
-    if (tid < jb) {
-      prow[tid] = pivrow[tid];
-      if (p != gc) {
-        if (gc >= r0 && gc < r1) pan[tid * rpw + (gc - r0)] = pivrow[tid];
-        if (p >= r0 && p < r1) pan[tid * rpw + (p - r0)] = drow[tid];
-      }
-    }
-    __syncthreads();
-    // scale column c and update column c + 1 of every row below the pivot; the
-    // candidates of column c + 1
-    double nv = -1.0;
-    if (tid < nrows && r0 + tid > gc) {
-      const int r = tid;
-      if (vw != 0.0) {
-        const cplx l = cmul(pan[c * rpw + r], crecip(prow[c]));
-        pan[c * rpw + r] = l;
-        if (c + 1 < jb) {
-          const cplx x = csub(pan[(c + 1) * rpw + r], cmul(l, prow[c + 1]));
-          pan[(c + 1) * rpw + r] = x;
-          nv = l1abs(x);
+    // multipliers (column c) and the rank-1 update of columns > c, rows > gc: lane c
+    // takes l = a_c / u_c, every lane > c subtracts l u (q = u on lanes > c, else 0)
+    if (wr0 + wn - 1 > gc) {
+      const cplx ip = (vw == 0.0) ? cmk(0, 0) : pivot_recip(readlane_c(pr, c));
+      const bool is_c = (lane == c);
+      const cplx q = csel(lane > c, pr, cmk(0, 0));
+      if (wr0 > gc && wn == RPT) {  // every row of the wavefront is below the pivot
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const cplx t = cmul(a[i], ip);
+          const cplx l = readlane_c(t, c);
+          a[i] = csel(is_c, t, csub(a[i], cmul(l, q)));
         }
       } else {
-        pan[c * rpw + r] = cmk(0, 0);  // zero column below a zero pivot: multipliers 0
-        if (c + 1 < jb) nv = l1abs(pan[(c + 1) * rpw + r]);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const bool upd = i < wn && wr0 + i > gc;
+          const cplx t = cmul(a[i], ip);
+          const cplx l = csel(upd, readlane_c(t, c), cmk(0, 0));
+          a[i] = csel(is_c && upd, t, csub(a[i], cmul(l, q)));
+        }
       }
     }
     if (c + 1 < jb) {
-      local_candidate(nv);
+      wave_candidate(c + 1, gc);
       __syncthreads();
       publish(c + 1);
-      __syncthreads();  // the published rows are read before the deferred update changes them
+    }
+    if (g == 0 && wave == 0) {
+      const int ca = __builtin_amdgcn_readlane(pcont, c);
+      const bool inpanel = p < (long)j + jb;
+      int cb, eidx = -1;
+      if (inpanel) {
+        cb = __builtin_amdgcn_readlane(pcont, (int)(p - j));
+      } else {
+        const unsigned long long mk = __ballot(lane < nextra && epos == (int)p);
+        if (mk) {
+          eidx = (int)__ffsll((long long)mk) - 1;
+          cb = __builtin_amdgcn_readlane(econt, eidx);
+        } else {
+          eidx = nextra++;
+          cb = (int)p;
+          if (lane == eidx) epos = (int)p;
+        }
+      }
+      pcont = (lane == c) ? cb : pcont;
+      pcont = (inpanel && lane == (int)(p - j)) ? ca : pcont;
+      econt = (!inpanel && lane == eidx) ? ca : econt;
     }
   }
   __syncthreads();
 
-  for (int idx = tid; idx < nrows * jb; idx += PNT) {
-    const int r = idx % nrows, c = idx / nrows;
-    A[(r0 + r) + (long)(j + c) * lda] = pan[c * rpw + r];
+  // write back through the LDS tile (coalesced column writes)
+  for (int ch = 0; ch < RPW; ch += CH) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int lr = wave * RPT + i - ch;
+      if (lr >= 0 && lr < CH && col_ok) smem[lane * PT_LD + lr] = a[i];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < CH * jb; idx += PNT) {
+      const int r = idx % CH, c = idx / CH;
+      const long gr = r0 + ch + r;
+      if (gr < N) A[gr + (long)(j + c) * lda] = smem[c * PT_LD + r];
+    }
+    __syncthreads();
   }
-  // refill the other slot buffer (used by the next panel) with the empty pattern
-  {
+  // refill the words the next panel uses in the other slot buffer with the empty pattern
+  if (next_P > 0) {
+    const int nrec = next_jb + 1, nrstr = BM_REC_SPREAD ? REC_STRIDE : nrec;
+    const int ncstr = BM_REC_SPREAD ? (next_P + 1) * REC_STRIDE : next_P * nrec + next_jb;
+    const int per_col = next_P * nrec + next_jb;
     unsigned long long *ns = (unsigned long long *)next_slots;
-    const size_t nw = (size_t)next_words;
-    for (size_t idx = (size_t)g * PNT + tid; idx < nw; idx += (size_t)P * PNT) ns[idx] = SENT;
-    unsigned long long *nd = (unsigned long long *)next_dslots;
-    for (size_t idx = (size_t)g * PNT + tid; idx < (size_t)2 * jb * jb; idx += (size_t)P * PNT) nd[idx] = SENT;
+    for (int idx = g * PNT + tid; idx < next_jb * per_col; idx += P * PNT) {
+      const int col = idx / per_col, rem = idx % per_col;
+      const int el = col * ncstr + ((rem < next_P * nrec) ? (rem / nrec) * nrstr + rem % nrec
+                                                           : next_P * nrstr + (rem - next_P * nrec));
+      ns[2 * (size_t)el] = SENT;
+      ns[2 * (size_t)el + 1] = SENT;
+    }
   }
   // net permutation of the panel's interchanges on rows >= j: pairs (dst, src)
-  if (g == 0 && tid == 0) {
-    int *key = s_key, *val = s_val;
-    int cnt = 0;
-    for (int s = 0; s < jb; ++s) {
-      const int a = j + s, b = s_piv[s];
-      if (a == b) continue;
-      int ia = -1, ib = -1;
-      for (int e = 0; e < cnt; ++e) {
-        if (key[e] == a) ia = e;
-        if (key[e] == b) ib = e;
-      }
-      if (ia < 0) { key[cnt] = a; val[cnt] = a; ia = cnt++; }
-      if (ib < 0) { key[cnt] = b; val[cnt] = b; ib = cnt++; }
-      const int t = val[ia];
-      val[ia] = val[ib];
-      val[ib] = t;
+  if (g == 0 && wave == 0) {
+    const bool m1 = lane < jb && pcont != j + lane;
+    const bool m2 = lane < nextra && econt != epos;
+    const unsigned long long b1 = __ballot(m1), b2 = __ballot(m2);
+    const int n1 = __popcll(b1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (m1) {
+      const int k = __popcll(b1 & below);
+      swp[1 + 2 * k] = j + lane;
+      swp[2 + 2 * k] = pcont;
     }
-    int np = 0;
-    for (int e = 0; e < cnt; ++e)
-      if (key[e] != val[e]) {
-        swp[1 + 2 * np] = key[e];
-        swp[2 + 2 * np] = val[e];
-        ++np;
-      }
-    swp[0] = np;
+    if (m2) {
+      const int k = n1 + __popcll(b2 & below);
+      swp[1 + 2 * k] = epos;
+      swp[2 + 2 * k] = econt;
+    }
+    if (lane == 0) swp[0] = n1 + __popcll(b2);
   }
 }
 
 // ---------------------------------------------------------------------------
-// 2. row interchanges outside the panel: columns [0, j) and [j + jb, ncol)
+// 2. row interchanges outside the panel, and U12 = L11^{-1} A12
+//
+// Workgroups [0, nleft): SWAP_COLS columns each of [0, j), interchanges only.
+// Workgroups [nleft, ...): ST_CW columns each of [j + jb, ncol): interchanges, then
+// forward substitution with the unit lower L11 (in LDS) on rows j .. j + jb - 1,
+// lane = row, two columns per wavefront, the solved value of row c broadcast from
+// lane c by readlane.
 // ---------------------------------------------------------------------------
 #define SWAP_COLS 16
-#define TI_LDS ((size_t)(2 * TI_N * (TI_N + 1) + 1024) * sizeof(cplx))  // M, X, T of tri_inv64
+#define ST_CW 8
+#define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB + 2 * LU_NB * ST_CW) * sizeof(cplx))
 
-// 2 + 3a. row interchanges outside the panel: columns [0, j) and [j + jb, ncol);
-// the last workgroup instead inverts the unit lower L11 of the panel into linv
-// (64 x 64, column-major, identity-padded when jb < 64) for U12 = L11^{-1} A12.
-__global__ __launch_bounds__(256) void swap_linv_kernel(cplx *A, long lda, int j, int jb, int ncol, const int32_t *swp,
-                                                        cplx *linv) {
+__global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int ncol, const int32_t *swp,
+                                                        int nleft) {
   extern __shared__ cplx sm[];
-  if (blockIdx.x == gridDim.x - 1) {
-    cplx *Ms = sm, *Xs = sm + TI_N * (TI_N + 1), *T = sm + 2 * TI_N * (TI_N + 1);
-    for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) {
-      const int r = idx % TI_N, c = idx / TI_N;
-      Ms[r + c * (TI_N + 1)] = (r < jb && c < jb) ? A[(j + r) + (long)(j + c) * lda] : cmk(r == c ? 1.0 : 0.0, 0.0);
+  const int np = swp[0];
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x < nleft) {
+    if (np == 0) return;
+    cplx *buf = sm;  // [2 LU_NB][SWAP_COLS]
+    const int cbase = blockIdx.x * SWAP_COLS;
+    for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
+      const int e = idx % np, col = cbase + idx / np;
+      if (col < j) buf[idx] = A[swp[2 + 2 * e] + (long)col * lda];
     }
     __syncthreads();
-    tri_inv64<true>(Ms, TI_N + 1, Xs, TI_N + 1, T);
-    for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) linv[idx] = Xs[idx % TI_N + (idx / TI_N) * (TI_N + 1)];
+    for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
+      const int e = idx % np, col = cbase + idx / np;
+      if (col < j) A[swp[1 + 2 * e] + (long)col * lda] = buf[idx];
+    }
     return;
   }
-  cplx *buf = sm;  // [2 LU_NB][SWAP_COLS]
-  const int np = swp[0];
-  if (np == 0) return;
-  const int nout = ncol - jb;
-  const int cbase = blockIdx.x * SWAP_COLS;
-  for (int idx = threadIdx.x; idx < np * SWAP_COLS; idx += 256) {
+  const int c0 = j + jb + ((int)blockIdx.x - nleft) * ST_CW;
+  const int ncw = (ncol - c0 < ST_CW) ? ncol - c0 : ST_CW;
+  cplx *Ls = sm;                     // L11, column-major, ld LU_NB
+  cplx *X = Ls + LU_NB * LU_NB;      // rows j .. j + jb - 1 of the columns, [ST_CW][LU_NB]
+  cplx *buf = X + ST_CW * LU_NB;     // interchange sources, [2 LU_NB][ST_CW]
+  for (int idx = tid; idx < jb * jb; idx += 256) {
+    const int r = idx % jb, c = idx / jb;
+    Ls[c * LU_NB + r] = A[(j + r) + (long)(j + c) * lda];
+  }
+  for (int idx = tid; idx < jb * ST_CW; idx += 256) {
+    const int r = idx % jb, cl = idx / jb;
+    if (cl < ncw) X[cl * LU_NB + r] = A[(j + r) + (long)(c0 + cl) * lda];
+  }
+  for (int idx = tid; idx < np * ST_CW; idx += 256) {
     const int e = idx % np, cl = idx / np;
-    const int oc = cbase + cl;
-    if (oc < nout) {
-      const int col = (oc < j) ? oc : oc + jb;
-      buf[e * SWAP_COLS + cl] = A[swp[2 + 2 * e] + (long)col * lda];
+    if (cl < ncw) buf[idx] = A[swp[2 + 2 * e] + (long)(c0 + cl) * lda];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < np * ST_CW; idx += 256) {
+    const int e = idx % np, cl = idx / np;
+    if (cl < ncw) {
+      const int dst = swp[1 + 2 * e];
+      if (dst < j + jb) X[cl * LU_NB + (dst - j)] = buf[idx];
+      else A[dst + (long)(c0 + cl) * lda] = buf[idx];
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < np * SWAP_COLS; idx += 256) {
-    const int e = idx % np, cl = idx / np;
-    const int oc = cbase + cl;
-    if (oc < nout) {
-      const int col = (oc < j) ? oc : oc + jb;
-      A[swp[1 + 2 * e] + (long)col * lda] = buf[e * SWAP_COLS + cl];
-    }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int ca = 2 * wave, cb = 2 * wave + 1;
+  const bool row_ok = lane < jb;
+  cplx xa = (row_ok && ca < ncw) ? X[ca * LU_NB + lane] : cmk(0, 0);
+  cplx xb = (row_ok && cb < ncw) ? X[cb * LU_NB + lane] : cmk(0, 0);
+  for (int c = 0; c < jb - 1; ++c) {
+    const cplx l = (lane > c && row_ok) ? Ls[c * LU_NB + lane] : cmk(0, 0);
+    const cplx ya = readlane_c(xa, c), yb = readlane_c(xb, c);
+    xa = csub(xa, cmul(l, ya));
+    xb = csub(xb, cmul(l, yb));
+  }
+  if (row_ok) {
+    if (ca < ncw) A[(j + lane) + (long)(c0 + ca) * lda] = xa;
+    if (cb < ncw) A[(j + lane) + (long)(c0 + cb) * lda] = xb;
   }
 }
 
 // ---------------------------------------------------------------------------
 // driver
 // ---------------------------------------------------------------------------
-#define SLOT_ELEMS ((size_t)LU_NB * PANEL_PMAX * (LU_NB + 1))  // complex values per slot buffer
 
 bm_getrf_ws *bm_getrf_ws_create(int n) {
   bm_getrf_ws *w = new bm_getrf_ws();
@@ -442,9 +573,7 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
   w->npanel = (n + LU_NB - 1) / LU_NB;
   const int nblk = (n + BM_DIAG_NB - 1) / BM_DIAG_NB;
   bool ok = hipMalloc(&w->slots, sizeof(cplx) * 2 * SLOT_ELEMS) == hipSuccess;
-  ok = ok && hipMalloc(&w->dslots, sizeof(cplx) * 2 * LU_NB * LU_NB) == hipSuccess;
   ok = ok && hipMalloc(&w->swp, sizeof(int32_t) * (size_t)w->npanel * SWP_STRIDE) == hipSuccess;
-  ok = ok && hipMalloc(&w->linv, sizeof(cplx) * TI_N * TI_N) == hipSuccess;
   ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * 8) == hipSuccess;
   ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS) == hipSuccess;
   if (!ok) {
@@ -457,9 +586,7 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
 void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   if (!w) return;
   (void)hipFree(w->slots);
-  (void)hipFree(w->dslots);
   (void)hipFree(w->swp);
-  (void)hipFree(w->linv);
   (void)hipFree(w->solve_sync);
   (void)hipFree(w->zbuf);
   delete w;
@@ -467,22 +594,32 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
 
 __global__ void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv);
 
+#define TI_LDS ((size_t)(2 * TI_N * (TI_N + 1) + 1024) * sizeof(cplx))  // M, X, T of tri_inv64
+
+typedef void (*panel_fn)(int, cplx *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int, int,
+                         int32_t *);
+static const panel_fn panel_fns[2][3] = {{panel_kernel<4, false>, panel_kernel<8, false>, panel_kernel<16, false>},
+                                         {panel_kernel<4, true>, panel_kernel<8, true>, panel_kernel<16, true>}};
+
 static int panel_attr_done[64];
 
-// rows per workgroup and workgroup count of a panel of R rows and width jb
-static bool panel_shape(int R, int jb, int ncu, int one_round, int *rpw_out, int *P_out) {
-  const size_t budget = PANEL_LDS_MAX;
-  for (int P = 1; P <= PANEL_PMAX && P <= ncu; ++P) {
-    const int rpw = (R + P - 1) / P;
-    if (rpw > 256) continue;
-    const size_t recv = one_round ? (size_t)P * (jb + 1) : (size_t)P;
-    if (((size_t)jb * rpw + recv) * sizeof(cplx) <= budget) {
-      *rpw_out = rpw;
-      *P_out = (R + rpw - 1) / rpw;
-      return true;
-    }
+// rows per wavefront (as an index into {4, 8, 16}: 32, 64 or 128 rows per
+// workgroup) and workgroup count of a panel of R rows: the fewest rows per
+// wavefront that keep P <= PANEL_TARGET_P, else 16 rows per wavefront and as many
+// workgroups as needed
+static bool panel_shape(int R, int ncu, int *rpt_idx, int *P_out, int *one_round) {
+  const int pmax = (ncu < PANEL_PMAX) ? ncu : PANEL_PMAX;
+  int k = 0, P = 0;
+  for (k = 0; k < 3; ++k) {
+    P = (R + PNW * (4 << k) - 1) / (PNW * (4 << k));
+    if (P <= PANEL_TARGET_P) break;
   }
-  return false;
+  if (k == 3) k = 2;
+  if (P < 1 || P > pmax) return false;
+  *rpt_idx = k;
+  *P_out = P;
+  *one_round = (P <= PANEL_ONE_ROUND_PMAX);
+  return true;
 }
 
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w) {
@@ -490,12 +627,12 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   PANEL_LDS_MAX));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   PANEL_LDS_MAX));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_linv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)TI_LDS));
+    for (int o = 0; o < 2; ++o)
+      for (int k = 0; k < 3; ++k)
+        BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[o][k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)PANEL_LDS));
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ST_LDS));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)TI_LDS));
     panel_attr_done[dev] = 1;
@@ -503,63 +640,55 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   int ncu = 0;
   BM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   BM_HIP_TRY(hipMemsetAsync(dev_err, 0, 2 * sizeof(int32_t), s));
-  // launch shape of every panel: one-round exchange when all records fit in LDS
   const int npanel = (n + LU_NB - 1) / LU_NB;
-  int shape[3 * 1024];  // rpw, P, one_round per panel
+  int shape[3 * 1024];  // rows-per-lane index, P, one_round per panel
   if (npanel > 1024) return BM_E_ARG;
   for (int pi = 0; pi < npanel; ++pi) {
-    const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB, R = n - j;
-    int rpw = 0, P = 0, one_round = 1;
-    if (!panel_shape(R, jb, ncu, 1, &rpw, &P) || P > PANEL_ONE_ROUND_PMAX) {
-      one_round = 0;
-      if (!panel_shape(R, jb, ncu, 0, &rpw, &P)) return BM_E_ARG;  // too tall for an LDS-resident panel
-    }
-    shape[3 * pi] = rpw;
-    shape[3 * pi + 1] = P;
-    shape[3 * pi + 2] = one_round;
+    const int R = n - pi * LU_NB;
+    if (!panel_shape(R, ncu, &shape[3 * pi], &shape[3 * pi + 1], &shape[3 * pi + 2])) return BM_E_ARG;
   }
-  {
+  if (npanel > 0) {  // the first panel's words of slot buffer 0; each panel refills the next one's
     const int jb0 = (n < LU_NB) ? n : LU_NB;
-    BM_HIP_TRY(hipMemsetAsync(w->slots, 0xFF, sizeof(cplx) * (size_t)jb0 * shape[1] * (jb0 + 1), s));
-    BM_HIP_TRY(hipMemsetAsync(w->dslots, 0xFF, sizeof(cplx) * LU_NB * LU_NB, s));
+    const size_t cstr0 = BM_REC_SPREAD ? (size_t)(shape[1] + 1) * REC_STRIDE : (size_t)shape[1] * (jb0 + 1) + jb0;
+    BM_HIP_TRY(hipMemsetAsync(w->slots, 0xFF, sizeof(cplx) * (size_t)jb0 * cstr0, s));
   }
   const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
     const int jb = (n - j < LU_NB) ? n - j : LU_NB;
-    int rpw = shape[3 * pi], P = shape[3 * pi + 1], one_round = shape[3 * pi + 2];
-    int next_words = 0;
+    int P = shape[3 * pi + 1];
+    int next_P = 0, next_jb = 0;
     if (pi + 1 < npanel) {
-      const int jbn = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
-      next_words = 2 * jbn * shape[3 * (pi + 1) + 1] * (jbn + 1);
+      next_jb = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
+      next_P = shape[3 * (pi + 1) + 1];
     }
+    // all workgroups of the panel on one XCD (measured slower on MI355X: off)
+    int xs = 1;
+#ifdef BM_PANEL_XCD
+    xs = (BM_PANEL_XCD && ncu >= 256 && P <= ncu / 8) ? 8 : 1;
+#endif
     cplx *cur = w->slots + (size_t)(pi & 1) * SLOT_ELEMS, *nxt = w->slots + (size_t)((pi + 1) & 1) * SLOT_ELEMS;
-    cplx *dcur = w->dslots + (size_t)(pi & 1) * LU_NB * LU_NB, *dnxt = w->dslots + (size_t)((pi + 1) & 1) * LU_NB * LU_NB;
     int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
     long ldal = (long)lda;
-    void *args[] = {&n, &A, &ldal, &j, (void *)&jb, &rpw, &P, &ipiv, &dev_err, &cur, &dcur, &nxt, &dnxt,
-                    &next_words, &swp};
-    const size_t lds = ((size_t)jb * rpw + (one_round ? (size_t)P * (jb + 1) : (size_t)P)) * sizeof(cplx);
-    const void *fn = one_round ? (const void *)panel_kernel<true> : (const void *)panel_kernel<false>;
-    // All P workgroups must run at the same time.  The panel's LDS allows one
-    // workgroup per CU and P <= the CU count (checked in panel_shape), so on a
-    // device that is not saturated by other work every workgroup is resident at
-    // once; a plain launch avoids the ~11 us start and drain cost per panel of
-    // a cooperative launch.  Every wait in the kernel is bounded, so a launch
-    // whose workgroups cannot all become resident ends with BM_E_DEVICE, not a hang.
-    BM_HIP_TRY(hipLaunchKernel(fn, dim3(P), dim3(PNT), args, (unsigned)lds, s));
-    const int nout = n - jb;
-    const int nswap = (nout + SWAP_COLS - 1) / SWAP_COLS;
-    hipLaunchKernelGGL(swap_linv_kernel, dim3(nswap + 1), dim3(256), TI_LDS, s, A, ldal, j, jb, n,
-                       (const int32_t *)swp, w->linv);
-    BM_HIP_TRY(hipGetLastError());
+    int nn = n, jj = j, jbb = jb;
+    void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &xs, &swp};
+    // All P workgroups must run at the same time.  P <= the CU count (checked in
+    // panel_shape) and one workgroup fits a CU, so on a device that is not
+    // saturated by other work every workgroup is resident at once; a plain launch
+    // avoids the start and drain cost of a cooperative launch.  Every wait in the
+    // kernel is bounded, so a launch whose workgroups cannot all become resident
+    // ends with BM_E_DEVICE, not a hang.
+    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[shape[3 * pi + 2]][shape[3 * pi]], dim3(xs * P), dim3(PNT),
+                               args, PANEL_LDS, s));
     const int nr = n - j - jb;
+    const int nleft = (j + SWAP_COLS - 1) / SWAP_COLS, nright = (nr + ST_CW - 1) / ST_CW;
+    if (nleft + nright > 0) {
+      hipLaunchKernelGGL(swap_trsm_kernel, dim3(nleft + nright), dim3(256), ST_LDS, s, A, ldal, j, jb, n,
+                         (const int32_t *)swp, nleft);
+      BM_HIP_TRY(hipGetLastError());
+    }
     if (nr > 0) {
-      // U12 = L11^{-1} A12 (in place: one 64-row tile of the GEMM covers all jb rows)
-      int rc = bm_launch_zgemm(s, jb, nr, jb, one, w->linv, TI_N, A + j + (long)(j + jb) * lda, lda, cmk(0, 0),
-                               A + j + (long)(j + jb) * lda, lda);
-      if (!rc)
-        rc = bm_launch_zgemm(s, nr, nr, jb, mone, A + (j + jb) + (long)j * lda, lda, A + j + (long)(j + jb) * lda, lda,
-                             one, A + (j + jb) + (long)(j + jb) * lda, lda);
+      const int rc = bm_launch_zgemm(s, nr, nr, jb, mone, A + (j + jb) + (long)j * lda, lda,
+                                     A + j + (long)(j + jb) * lda, lda, one, A + (j + jb) + (long)(j + jb) * lda, lda);
       if (rc) return rc;
     }
   }

@@ -62,14 +62,11 @@ __device__ inline cplx csqrt_d(cplx w) {
 #define LU_NB 64                   // LU panel width
 #define BM_DIAG_NB 64              // block size of the triangular solves
 #define SWP_STRIDE (1 + 4 * LU_NB) // per panel: count, then (dst, src) row pairs
-#define SPIN_LIMIT (1L << 24)      // bound of every device-side wait
 
 struct bm_getrf_ws {
   int n, npanel;
-  cplx *slots;         // 2 buffers of [LU_NB columns][workgroups][LU_NB + 1] exchange records
-  cplx *dslots;        // 2 buffers of [LU_NB columns][LU_NB] diagonal rows
+  cplx *slots;         // 2 buffers of per-column exchange records (candidates and diagonal row)
   int32_t *swp;        // per panel: count, then (dst, src) pairs
-  cplx *linv;          // inverse of the current panel's unit lower 64 x 64 block
   int32_t *solve_sync; // ticket counter of the blocked triangular solves
   cplx *zbuf;          // solved blocks published by the triangular solves
 };
@@ -89,6 +86,12 @@ __device__ inline void st_cplx_agent(cplx *p, cplx v) {
   st_agent(q, (unsigned long long)__double_as_longlong(v.x));
   st_agent(q + 1, (unsigned long long)__double_as_longlong(v.y));
 }
+// Bound of every device-side wait: BM_WAIT_TICKS ticks of the constant-rate wall
+// clock (100 MHz: 50 ms), far above any legitimate wait.  A thread whose wait
+// expired raises the device error flag and does not wait again in that launch.
+#define BM_WAIT_TICKS (5LL * 1000 * 1000)
+__device__ inline bool wait_expired(unsigned long long t0) { return wall_clock64() - t0 > (unsigned long long)BM_WAIT_TICKS; }
+
 __device__ inline double l1abs(cplx v) { return fabs(v.x) + fabs(v.y); }
 // candidate order: larger value wins, then the smaller row
 __device__ inline bool better(double v, long g, double bv, long bg) {

@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
           zy[e] = ld_agent(zb + 2 * idx + 1);
         }
       }
-      long spins = 0;
+      const unsigned long long t0 = wall_clock64();
       for (;;) {
         bool all = true;
 #pragma unroll
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
           }
         }
         if (all) break;
-        if (++spins > SPIN_LIMIT) {
+        if (!ok || wait_expired(t0)) {
           if (ok) atomicOr(dev_err, 1);
           ok = false;
           break;
