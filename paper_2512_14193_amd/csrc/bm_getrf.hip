@@ -3,16 +3,16 @@
 // Used for U33 = -M31 M13 - M32 M23 (Theorem thm:LU) and, as the comparator, for
 // the 2N x 2N ordinary matrix.  Per panel of jb <= 64 columns starting at column j:
 //
-//  1. panel_kernel (P workgroups of 512 threads, all resident at once): the
-//     (n - j) x jb panel lives in registers for the whole panel, one column per lane
-//     and RPT consecutive rows per wavefront (workgroups and wavefronts in row
-//     order).  In the rank-1 update of column c every row takes its multiplier
-//     from lane c by a readlane, so the update touches neither LDS nor memory.  The
-//     pivot search of column c + 1 is a scan of lane c + 1 over its rows, then a
-//     combine of the eight wavefronts in LDS; each workgroup publishes its candidate
-//     (value, row and the whole candidate row) in an exchange record, every
-//     workgroup reads all P records, picks the same winner and exchanges the two rows
-//     in registers.  One cross-workgroup round trip per column.
+//  1. panel_kernel (P workgroups, all resident at once): the (n - j) x jb panel
+//     is held in LDS for the whole panel, 64 or 128 consecutive rows per
+//     workgroup.  In each workgroup one wavefront runs the chain that decides the
+//     pivots (receive the candidates of column c, select, exchange rows, scale
+//     column c, update column c + 1, publish the candidate of column c + 1) with
+//     no workgroup barrier, and the other wavefronts apply the rest of each rank-1
+//     update one step behind it.  The candidate of a workgroup (value, row and the
+//     whole candidate row) goes to an exchange record; every workgroup reads all
+//     P records and picks the same winner: one cross-workgroup round trip per
+//     column.
 //  2. swap_trsm_kernel: the panel's row interchanges, composed into one permutation
 //     of at most 2 jb rows, on every column outside the panel; for the columns right
 //     of the panel also U12 = L11^{-1} A12 by forward substitution, one wavefront per
@@ -30,27 +30,22 @@
 //
 // Exchange protocol: for column c every workgroup g writes one record
 //   slots[c][g] = { (value, row), candidate row (jb complex values) }
-// and the owner of row j + c also writes that row after the P records.  Slots are filled
-// with an all-ones bit pattern before the panel starts (a NaN the arithmetic
-// never produces), each 8-byte word is written exactly once with an agent-scope
-// store, and readers poll each word with agent-scope loads until it differs from
-// the pattern.  So the data itself is the synchronisation: no fence, no counter,
-// one round trip per column.  With ONE_ROUND every workgroup receives all P
-// records at once; otherwise it receives the P headers and then the winner's row.
+// and the owner of row j + c also writes that row after the P records.  Slots are
+// filled with an all-ones bit pattern before the panel starts (a NaN the
+// arithmetic never produces), each word is written exactly once with an
+// agent-scope store, and readers poll each word with agent-scope loads until it
+// differs from the pattern.  So the data itself is the synchronisation: no fence,
+// no counter, one round trip per column (a reader takes the headers, then the
+// winner's row, which has arrived with its header).
 // ---------------------------------------------------------------------------
 #define PANEL_PMAX 256            // max workgroups of a panel launch
-#define PANEL_ONE_ROUND_PMAX 32   // all records of a column are received at once up to this many workgroups
-#ifndef PANEL_TARGET_P
-#define PANEL_TARGET_P 32         // preferred workgroup count
-#endif
 #define SENT 0xFFFFFFFFFFFFFFFFULL  // empty exchange word (all ones)
-#define PNT 512                   // threads per panel workgroup (8 waves)
-#define PNW (PNT / 64)
-#define PT_LD 65                  // leading dimension of the LDS transpose tile
-#define PANEL_REC_ELEMS (PANEL_ONE_ROUND_PMAX * (LU_NB + 1) > PANEL_PMAX ? PANEL_ONE_ROUND_PMAX * (LU_NB + 1) : PANEL_PMAX)
-#define PANEL_LDS_ELEMS (PANEL_REC_ELEMS > LU_NB * PT_LD ? PANEL_REC_ELEMS : LU_NB * PT_LD)
-#define PANEL_LDS ((size_t)PANEL_LDS_ELEMS * sizeof(cplx))  // records of a column, or the transpose tile
-#define RECV_PT ((PANEL_REC_ELEMS + LU_NB + PNT - 1) / PNT)  // loads per thread per round
+#define SNT 448                   // threads per panel workgroup: one chain + SNB bulk wavefronts
+#define SNB 6
+#ifndef PANEL_RPL1_PMAX
+#define PANEL_RPL1_PMAX 32        // 64 rows per workgroup while P stays within this, else 128
+#endif
+#define PANEL_LDS(rpl) ((size_t)LU_NB * (64 * (rpl) + 1) * sizeof(cplx))
 
 // Records of one column sit REC_STRIDE complex values (4 KiB) apart so that the
 // reads of a column spread over many memory channels instead of queueing on a few.
@@ -163,293 +158,323 @@ __device__ inline cplx pivot_recip(cplx u) {
   return cmk(us.x * r, -us.y * r);
 }
 
-// Panel factorisation, lane = column.  Wavefront w of workgroup g holds RPT
-// consecutive rows r0 + w RPT + i (i < RPT) of the panel, lane c holding column c,
-// in registers for the whole panel.  Per column c:
-//   receive the records of column c; every wavefront selects the same winner p;
-//   rows j + c and p exchange (the two wavefronts holding them copy the records);
-//   every row below j + c takes its multiplier l = a_c / u_c (computed in lane c,
-//   broadcast by readlane) and subtracts l times the pivot row from its columns
-//   > c; lane c + 1 scans the updated column for the candidates of column c + 1,
-//   the wavefronts combine in LDS and the workgroup publishes its record.
+// Panel factorisation with split roles.  A workgroup holds RPW = 64 RPL rows of
+// the panel in LDS (column-major, padded stride LDP).  Wavefront 0 runs the chain
+// that decides the pivots, without workgroup barriers; wavefronts 1 .. SNB apply
+// the bulk of each rank-1 update one step behind it.  Per column c:
+//   wavefront 0: receives the P record headers of column c, selects the winner p
+//   and fetches its row, exchanges rows j + c and p, scales column c (the
+//   multipliers l_r = a_rc / u_c), updates column c + 1 and finds the
+//   workgroup's candidate for it, publishes that record (the candidate row
+//   completed on the fly for columns > c + 1) and then releases pivot c to the
+//   bulk wavefronts; it keeps columns c and c + 1 of its rows in registers;
+//   wavefronts 1 .. SNB: subtract l_r u_cc from columns cc >= c + 2 and count
+//   themselves done; wavefront 0 waits for that count before it touches rows or
+//   columns of the next step.
 // Exchange layout per column c (rs = record stride, cstride = complex values per column):
 //   slots[c * cstride + g * rs]  record of workgroup g: (value, row), then the row
 //   slots[c * cstride + P * rs]  the diagonal row j + c, by its owner
-// The P workgroups are blockIdx.x = xs g, g = 0 .. P - 1; the launch has xs P
-// workgroups and the others return at once (xs = 8 puts all P on one XCD).
-template <int RPT, bool ONE_ROUND>
-__global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
+template <int RPL>
+__global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
                                                     int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
-                                                    int next_jb, int xs, int32_t *swp) {
-  constexpr int RPW = PNW * RPT;           // rows per workgroup
-  constexpr int CH = RPW < 64 ? RPW : 64;  // rows per transpose chunk
-  extern __shared__ cplx smem[];           // the records of one column, or the transpose tile
-  __shared__ cplx drow[LU_NB];
-  __shared__ cplx s_cand[PNW];             // per wavefront: (value, local row)
+                                                    int next_jb, int32_t *swp) {
+  constexpr int RPW = 64 * RPL;  // rows per workgroup
+  constexpr int LDP = RPW + 1;   // column stride of the LDS panel (odd: conflict-free row reads)
+  extern __shared__ cplx pan[];  // jb x LDP
+  __shared__ cplx urow[2][LU_NB];  // pivot row of column c, for the bulk wavefronts
+  __shared__ int s_ready, s_bulk;  // last released pivot; bulk completions
 
-  if ((int)blockIdx.x % xs) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = (int)blockIdx.x / xs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = (int)blockIdx.x;
   const int rec = jb + 1;
   const int rstr = BM_REC_SPREAD ? REC_STRIDE : rec;
   const int cstride = BM_REC_SPREAD ? (P + 1) * REC_STRIDE : P * rec + jb;
   const __amdgpu_buffer_rsrc_t rs = rec_rsrc(slots);
   const long r0 = (long)j + (long)g * RPW;  // first row of the workgroup
-  const long wr0 = r0 + (long)wave * RPT;   // first row of the wavefront
-  const long wrem = (long)N - wr0;
-  const int wn = wrem <= 0 ? 0 : (wrem < RPT ? (int)wrem : RPT);  // rows of the wavefront inside the matrix
-  const bool col_ok = lane < jb;
+  const int nv = (N - r0 >= RPW) ? RPW : ((N - r0 > 0) ? (int)(N - r0) : 0);
   bool ok = true;
-  cplx a[RPT];
 
-  // load: coalesced column reads into the LDS tile, then each wavefront takes its rows
-  for (int ch = 0; ch < RPW; ch += CH) {
-    for (int idx = tid; idx < CH * jb; idx += PNT) {
-      const int r = idx % CH, c = idx / CH;
-      const long gr = r0 + ch + r;
-      smem[c * PT_LD + r] = (gr < N) ? A[gr + (long)(j + c) * lda] : cmk(0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int lr = wave * RPT + i - ch;
-      if (lr >= 0 && lr < CH) a[i] = csel(col_ok, smem[lane * PT_LD + (lr & (CH - 1))], cmk(0, 0));
-    }
-    __syncthreads();
+  for (int idx = tid; idx < RPW * jb; idx += SNT) {
+    const int r = idx % RPW, c = idx / RPW;
+    pan[c * LDP + r] = (r < nv) ? A[(r0 + r) + (long)(j + c) * lda] : cmk(0, 0);
   }
+  if (tid == 0) {
+    s_ready = -1;
+    s_bulk = 0;
+  }
+  __syncthreads();
 
-  // wavefront candidate of column cc among its rows > after: lane cc scans its rows
-  auto wave_candidate = [&](int cc, long after) __attribute__((always_inline)) {
-    double best = -1.0;
-    int bi = -1;
-    if (wr0 > after && wn == RPT) {
+  if (wave == 0) {
+    const bool col_ok = lane < jb;
+    // candidate among the rows > after of a column held as x[k] = row lane + 64 k:
+    // (value, local row), wave-uniform; ties go to the smallest row
+    auto cand = [&](const cplx(&x)[RPL], long after, double &vmax, int &lr) __attribute__((always_inline)) {
+      double v[RPL], best = -1.0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const double v = l1abs(a[i]);
-        if (v > best) {
-          best = v;
-          bi = i;
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        v[k] = (r < nv && r0 + r > after) ? l1abs(x[k]) : -1.0;
+        best = fmax(best, v[k]);
+      }
+      vmax = wave_max_f64(best);
+      lr = -1;
+      if (vmax >= 0.0) {
+#pragma unroll
+        for (int k = RPL - 1; k >= 0; --k) {
+          const unsigned long long m = __ballot(v[k] == vmax);
+          if (m) lr = 64 * k + (int)__ffsll((long long)m) - 1;
         }
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const double v = (i < wn && wr0 + i > after) ? l1abs(a[i]) : -1.0;
-        if (v > best) {
-          best = v;
-          bi = i;
-        }
-      }
-    }
-    best = readlane_f64(best, cc);
-    bi = __builtin_amdgcn_readlane(bi, cc);
-    if (lane == 0) s_cand[wave] = cmk(best, (bi >= 0) ? (double)(wave * RPT + bi) : -1.0);
-  };
-  // records of column cc: the workgroup's best candidate with its whole row (every
-  // record is filled, also without a candidate), and the diagonal row by its owner
-  auto publish = [&](int cc) __attribute__((always_inline)) {
-    const cplx cw = (lane < PNW) ? s_cand[lane] : cmk(-1.0, -1.0);
-    double v;
-    const int fw = wave_argmax_first(cw.x, v);  // waves in row order: ties go to the smaller row
-    const int lr = (fw >= 0) ? (int)readlane_f64(cw.y, fw) : -1;
-    const int base = cc * cstride;
-    if (wave == ((lr >= 0) ? lr / RPT : 0)) {
-      const int ic = (lr >= 0) ? lr % RPT : -1;
-      cplx x = cmk(0, 0);
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) x = csel(i == ic, a[i], x);
+    };
+    // records of column cc: header and candidate row lr, diagonal row; columns > cc
+    // still owe the update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
+    auto publish = [&](int cc, double v, int lr, cplx pr) __attribute__((always_inline)) {
+      const int base = cc * cstride;
       const int sc = base + g * rstr;
+      const bool late = (cc > 0) && lane > cc;
+      const long ld = (long)j + cc - r0;
+      const bool has_d = (ld >= 0 && ld < nv);
+      cplx x = cmk(0, 0), y = cmk(0, 0);
+      if (col_ok && lr >= 0) {
+        x = pan[lane * LDP + lr];
+        if (late) x = csub(x, cmul(pan[(cc - 1) * LDP + lr], pr));
+      }
+      if (col_ok && has_d) {
+        y = pan[lane * LDP + (int)ld];
+        if (late) y = csub(y, cmul(pan[(cc - 1) * LDP + (int)ld], pr));
+      }
       if (col_ok) rec_store(rs, sc + 1 + lane, x);
       if (lane == 0) rec_store(rs, sc, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
-    }
-    const long id = (long)j + cc - wr0;
-    if (id >= 0 && id < wn) {
-      cplx y = cmk(0, 0);
+      if (col_ok && has_d) rec_store(rs, base + P * rstr + lane, y);
+    };
+    cplx xc[RPL];  // column c of the workgroup's rows
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) y = csel(i == (int)id, a[i], y);
-      if (col_ok) rec_store(rs, base + P * rstr + lane, y);
-    }
-  };
-
-  wave_candidate(0, (long)j - 1);
-  __syncthreads();
-  publish(0);
-
-  // interchange bookkeeping (wave 0 of workgroup 0): lane l holds the source row of
-  // panel position j + l, and of the l-th further row touched by the interchanges
-  int pcont = j + lane, epos = -1, econt = 0, nextra = 0;
-
-  for (int c = 0; c < jb; ++c) {
-    const long gc = (long)j + c;
-    const int base = c * cstride;
-    // receive: every load of the round is issued before any is checked
+    for (int k = 0; k < RPL; ++k) xc[k] = pan[lane + 64 * k];
     {
-      const int hdr = ONE_ROUND ? P * rec : P;
-      const int total = hdr + jb;
-      int ei[RECV_PT];
-      bm_v4i v[RECV_PT];
-#pragma unroll
-      for (int e = 0; e < RECV_PT; ++e) {
-        const int idx = tid + PNT * e;
-        ei[e] = (idx >= total) ? -1
-                : (idx >= hdr) ? base + P * rstr + (idx - hdr)
-                : ONE_ROUND    ? base + (idx / rec) * rstr + idx % rec
-                               : base + idx * rstr;
-        if (ei[e] >= 0) v[e] = rec_load(rs, ei[e]);
-      }
-      const unsigned long long t0 = wall_clock64();
-      for (;;) {
-        bool all = true;
-#pragma unroll
-        for (int e = 0; e < RECV_PT; ++e) {
-          if (ei[e] >= 0 && rec_empty(v[e])) {
-            all = false;
-            v[e] = rec_load(rs, ei[e]);
-          }
-        }
-        if (all) break;
-        if (!ok || wait_expired(t0)) {
-          if (ok) atomicOr(dev_err, 1);
-          ok = false;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-#pragma unroll
-      for (int e = 0; e < RECV_PT; ++e) {
-        const int idx = tid + PNT * e;
-        if (ei[e] >= 0) {
-          if (idx < hdr) smem[idx] = rec_value(v[e]);
-          else drow[idx - hdr] = rec_value(v[e]);
-        }
-      }
+      double v;
+      int lr;
+      cand(xc, (long)j - 1, v, lr);
+      publish(0, v, lr, cmk(0, 0));
     }
-    __syncthreads();
-    // every wave selects the same winner: largest value, then the smallest
-    // workgroup index (= smallest row, the row ranges are in workgroup order)
-    double vw = -1.0;
-    long pw = -1;
-    int ww = -1;
-    if (P <= 64) {
-      const cplx h = (lane < P) ? (ONE_ROUND ? smem[lane * rec] : smem[lane]) : cmk(-1.0, -1.0);
-      double vm;
-      const int fl = wave_argmax_first(h.x, vm);
-      if (fl >= 0) {
-        ww = fl;
-        vw = vm;
-        pw = (long)readlane_f64(h.y, fl);
-      }
-    } else {
-      double lv = -1.0;
-      for (int t = lane; t < P; t += 64) lv = fmax(lv, (ONE_ROUND ? smem[t * rec] : smem[t]).x);
-      lv = wave_max_f64(lv);
-      int li = 0x7fffffff;
-      if (lv >= 0.0)
-        for (int t = lane; t < P; t += 64)
-          if ((ONE_ROUND ? smem[t * rec] : smem[t]).x == lv) {
-            li = t;
+    // interchange bookkeeping (workgroup 0): lane l holds the source row of panel
+    // position j + l, and of the l-th further row touched by the interchanges
+    int pcont = j + lane, epos = -1, econt = 0, nextra = 0;
+
+    for (int c = 0; c < jb; ++c) {
+      const long gc = (long)j + c;
+      const int base = c * cstride;
+      // receive the headers (lanes < P) and the diagonal row; all loads issued
+      // before any is checked
+      bm_v4i vh, vd;
+      const int eh = (lane < P) ? base + lane * rstr : -1;
+      const int ed = col_ok ? base + P * rstr + lane : -1;
+      if (eh >= 0) vh = rec_load(rs, eh);
+      if (ed >= 0) vd = rec_load(rs, ed);
+      {
+        const unsigned long long t0 = wall_clock64();
+        for (;;) {
+          bool all = true;
+          if (eh >= 0 && rec_empty(vh)) {
+            all = false;
+            vh = rec_load(rs, eh);
+          }
+          if (ed >= 0 && rec_empty(vd)) {
+            all = false;
+            vd = rec_load(rs, ed);
+          }
+          if (__all(all)) break;
+          if (!ok || wait_expired(t0)) {
+            if (ok) atomicOr(dev_err, 1);
+            ok = false;
             break;
           }
-      li = wave_min_int(li);
-      if (li != 0x7fffffff) {
-        ww = li;
-        vw = lv;
-        pw = (long)(ONE_ROUND ? smem[li * rec] : smem[li]).y;
-      }
-    }
-    if (ww < 0) {  // no comparable candidate (a column of NaNs): keep the diagonal row, report it
-      vw = 0.0;
-      pw = gc;
-    }
-    // pivot row and old diagonal row, one column per lane
-    const cplx dr = csel(col_ok, drow[lane], cmk(0, 0));
-    cplx pr;
-    if (ww < 0) pr = dr;
-    else if (ONE_ROUND) pr = csel(col_ok, smem[ww * rec + 1 + lane], cmk(0, 0));
-    else pr = col_ok ? rec_poll(rs, base + ww * rstr + 1 + lane, dev_err, ok) : cmk(0, 0);
-    const long p = pw;
-    if (g == 0 && tid == 0) {
-      ipiv[gc] = (int32_t)p;
-      if (vw == 0.0 && dev_err[1] == 0) dev_err[1] = (int32_t)(gc + 1);
-    }
-    // row interchange in registers: row gc <- pivot row, row p <- old row gc
-    // (value selects on every slot: a conditional store would index a[] dynamically)
-    if (p != gc) {
-      const long ia = gc - wr0, ib = p - wr0;
-      if (ia >= 0 && ia < RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) a[i] = csel(i == ia, pr, a[i]);
-      }
-      if (ib >= 0 && ib < RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) a[i] = csel(i == ib, dr, a[i]);
-      }
-    }
-    // multipliers (column c) and the rank-1 update of columns > c, rows > gc: lane c
-    // takes l = a_c / u_c, every lane > c subtracts l u (q = u on lanes > c, else 0)
-    if (wr0 + wn - 1 > gc) {
-      const cplx ip = (vw == 0.0) ? cmk(0, 0) : pivot_recip(readlane_c(pr, c));
-      const bool is_c = (lane == c);
-      const cplx q = csel(lane > c, pr, cmk(0, 0));
-      if (wr0 > gc && wn == RPT) {  // every row of the wavefront is below the pivot
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const cplx t = cmul(a[i], ip);
-          const cplx l = readlane_c(t, c);
-          a[i] = csel(is_c, t, csub(a[i], cmul(l, q)));
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const bool upd = i < wn && wr0 + i > gc;
-          const cplx t = cmul(a[i], ip);
-          const cplx l = csel(upd, readlane_c(t, c), cmk(0, 0));
-          a[i] = csel(is_c && upd, t, csub(a[i], cmul(l, q)));
+          __builtin_amdgcn_s_sleep(1);
         }
       }
-    }
-    if (c + 1 < jb) {
-      wave_candidate(c + 1, gc);
-      __syncthreads();
-      publish(c + 1);
-    }
-    if (g == 0 && wave == 0) {
-      const int ca = __builtin_amdgcn_readlane(pcont, c);
-      const bool inpanel = p < (long)j + jb;
-      int cb, eidx = -1;
-      if (inpanel) {
-        cb = __builtin_amdgcn_readlane(pcont, (int)(p - j));
+      // winner: largest value, then the smallest workgroup index (= smallest row)
+      double vw = -1.0;
+      long pw = -1;
+      int ww = -1;
+      if (P <= 64) {
+        const cplx h = (eh >= 0) ? rec_value(vh) : cmk(-1.0, -1.0);
+        double vm;
+        const int fl = wave_argmax_first(h.x, vm);
+        if (fl >= 0) {
+          ww = fl;
+          vw = vm;
+          pw = (long)readlane_f64(h.y, fl);
+        }
       } else {
-        const unsigned long long mk = __ballot(lane < nextra && epos == (int)p);
-        if (mk) {
-          eidx = (int)__ffsll((long long)mk) - 1;
-          cb = __builtin_amdgcn_readlane(econt, eidx);
+        // more than 64 workgroups: the headers again through the record buffer
+        double lv = -1.0;
+        for (int t = lane; t < P; t += 64) lv = fmax(lv, rec_poll(rs, base + t * rstr, dev_err, ok).x);
+        lv = wave_max_f64(lv);
+        int li = 0x7fffffff;
+        if (lv >= 0.0)
+          for (int t = lane; t < P; t += 64)
+            if (rec_poll(rs, base + t * rstr, dev_err, ok).x == lv) {
+              li = t;
+              break;
+            }
+        li = wave_min_int(li);
+        if (li != 0x7fffffff) {
+          ww = li;
+          vw = lv;
+          pw = (long)rec_poll(rs, base + li * rstr, dev_err, ok).y;
+        }
+      }
+      if (ww < 0) {  // no comparable candidate (a column of NaNs): keep the diagonal row, report it
+        vw = 0.0;
+        pw = gc;
+      }
+      const long p = pw;
+      const cplx dr = col_ok ? rec_value(vd) : cmk(0, 0);
+      const cplx pr = (ww < 0 || !col_ok) ? dr : rec_poll(rs, base + ww * rstr + 1 + lane, dev_err, ok);
+      // the bulk wavefronts must have finished the previous pivot (columns >= c + 1)
+      if (c >= 1 && c - 1 <= jb - 3) {
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(&s_bulk, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < SNB * c) {
+          if (!ok || wait_expired(t0)) {
+            if (ok) atomicOr(dev_err, 1);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      // row interchange: row gc <- pivot row, row p <- old row gc (in LDS and in
+      // the register copy of column c)
+      const long lg = gc - r0, lp = p - r0;
+      const cplx pc = readlane_c(pr, c), dcv = readlane_c(dr, c);
+      if (p != gc) {
+        if (col_ok) {
+          if (lg >= 0 && lg < nv) pan[lane * LDP + (int)lg] = pr;
+          if (lp >= 0 && lp < nv) pan[lane * LDP + (int)lp] = dr;
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          xc[k] = csel(lane + 64 * k == (int)lg, pc, xc[k]);
+          xc[k] = csel(lane + 64 * k == (int)lp, dcv, xc[k]);
+        }
+      }
+      if (col_ok) urow[c & 1][lane] = pr;
+      // multipliers of column c (rows below the pivot), update of column c + 1
+      const cplx ip = (vw == 0.0) ? cmk(0, 0) : pivot_recip(pc);
+      const bool have_next = (c + 1 < jb);
+      const cplx u1 = readlane_c(pr, have_next ? c + 1 : c);
+      cplx x1[RPL];
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) x1[k] = have_next ? pan[(c + 1) * LDP + lane + 64 * k] : cmk(0, 0);
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        if (r < nv && r0 + r > gc) {
+          const cplx l = cmul(xc[k], ip);
+          pan[c * LDP + r] = l;
+          x1[k] = csub(x1[k], cmul(l, u1));
+          if (have_next) pan[(c + 1) * LDP + r] = x1[k];
+        }
+      }
+      if (have_next) {
+        double v;
+        int lr;
+        cand(x1, gc, v, lr);
+        publish(c + 1, v, lr, pr);
+      }
+      // release pivot c to the bulk wavefronts
+      if (lane == 0) __hip_atomic_store(&s_ready, c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) xc[k] = x1[k];
+      if (g == 0) {
+        if (lane == 0) {
+          ipiv[gc] = (int32_t)p;
+          if (vw == 0.0 && dev_err[1] == 0) dev_err[1] = (int32_t)(gc + 1);
+        }
+        const int ca = __builtin_amdgcn_readlane(pcont, c);
+        const bool inpanel = p < (long)j + jb;
+        int cb, eidx = -1;
+        if (inpanel) {
+          cb = __builtin_amdgcn_readlane(pcont, (int)(p - j));
         } else {
-          eidx = nextra++;
-          cb = (int)p;
-          if (lane == eidx) epos = (int)p;
+          const unsigned long long mk = __ballot(lane < nextra && epos == (int)p);
+          if (mk) {
+            eidx = (int)__ffsll((long long)mk) - 1;
+            cb = __builtin_amdgcn_readlane(econt, eidx);
+          } else {
+            eidx = nextra++;
+            cb = (int)p;
+            if (lane == eidx) epos = (int)p;
+          }
+        }
+        pcont = (lane == c) ? cb : pcont;
+        pcont = (inpanel && lane == (int)(p - j)) ? ca : pcont;
+        econt = (!inpanel && lane == eidx) ? ca : econt;
+      }
+    }
+    // net permutation of the panel's interchanges on rows >= j: pairs (dst, src)
+    if (g == 0) {
+      const bool m1 = col_ok && pcont != j + lane;
+      const bool m2 = lane < nextra && econt != epos;
+      const unsigned long long b1 = __ballot(m1), b2 = __ballot(m2);
+      const int n1 = __popcll(b1);
+      const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      if (m1) {
+        const int k = __popcll(b1 & below);
+        swp[1 + 2 * k] = j + lane;
+        swp[2 + 2 * k] = pcont;
+      }
+      if (m2) {
+        const int k = n1 + __popcll(b2 & below);
+        swp[1 + 2 * k] = epos;
+        swp[2 + 2 * k] = econt;
+      }
+      if (lane == 0) swp[0] = n1 + __popcll(b2);
+    }
+  } else {
+    // bulk wavefronts: pivot c's update of columns >= c + 2, one step behind; the
+    // loads of a batch of BU columns are issued before any store
+    constexpr int NG = (SNB * 64) / RPW;  // column groups
+    constexpr int BU = 4;
+    const int bt = tid - 64;
+    const int r = bt % RPW, grp = bt / RPW;
+    for (int c = 0; c + 2 < jb; ++c) {
+      {
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(&s_ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < c) {
+          if (!ok || wait_expired(t0)) {
+            if (ok) atomicOr(dev_err, 1);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
       }
-      pcont = (lane == c) ? cb : pcont;
-      pcont = (inpanel && lane == (int)(p - j)) ? ca : pcont;
-      econt = (!inpanel && lane == eidx) ? ca : econt;
+      if (grp < NG && r < nv && r0 + r > (long)j + c) {
+        const cplx l = pan[c * LDP + r];
+        for (int cc0 = c + 2 + grp; cc0 < jb; cc0 += NG * BU) {
+          cplx av[BU], uv[BU];
+#pragma unroll
+          for (int b = 0; b < BU; ++b) {
+            const int cc = cc0 + b * NG;
+            if (cc < jb) {
+              av[b] = pan[cc * LDP + r];
+              uv[b] = urow[c & 1][cc];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < BU; ++b) {
+            const int cc = cc0 + b * NG;
+            if (cc < jb) pan[cc * LDP + r] = csub(av[b], cmul(l, uv[b]));
+          }
+        }
+      }
+      if (lane == 0) __hip_atomic_fetch_add(&s_bulk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   __syncthreads();
 
-  // write back through the LDS tile (coalesced column writes)
-  for (int ch = 0; ch < RPW; ch += CH) {
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int lr = wave * RPT + i - ch;
-      if (lr >= 0 && lr < CH && col_ok) smem[lane * PT_LD + lr] = a[i];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < CH * jb; idx += PNT) {
-      const int r = idx % CH, c = idx / CH;
-      const long gr = r0 + ch + r;
-      if (gr < N) A[gr + (long)(j + c) * lda] = smem[c * PT_LD + r];
-    }
-    __syncthreads();
+  for (int idx = tid; idx < RPW * jb; idx += SNT) {
+    const int r = idx % RPW, c = idx / RPW;
+    if (r < nv) A[(r0 + r) + (long)(j + c) * lda] = pan[c * LDP + r];
   }
   // refill the words the next panel uses in the other slot buffer with the empty pattern
   if (next_P > 0) {
@@ -457,32 +482,13 @@ __global__ __launch_bounds__(PNT) void panel_kernel(int N, cplx *A, long lda, in
     const int ncstr = BM_REC_SPREAD ? (next_P + 1) * REC_STRIDE : next_P * nrec + next_jb;
     const int per_col = next_P * nrec + next_jb;
     unsigned long long *ns = (unsigned long long *)next_slots;
-    for (int idx = g * PNT + tid; idx < next_jb * per_col; idx += P * PNT) {
+    for (int idx = g * SNT + tid; idx < next_jb * per_col; idx += P * SNT) {
       const int col = idx / per_col, rem = idx % per_col;
       const int el = col * ncstr + ((rem < next_P * nrec) ? (rem / nrec) * nrstr + rem % nrec
                                                            : next_P * nrstr + (rem - next_P * nrec));
       ns[2 * (size_t)el] = SENT;
       ns[2 * (size_t)el + 1] = SENT;
     }
-  }
-  // net permutation of the panel's interchanges on rows >= j: pairs (dst, src)
-  if (g == 0 && wave == 0) {
-    const bool m1 = lane < jb && pcont != j + lane;
-    const bool m2 = lane < nextra && econt != epos;
-    const unsigned long long b1 = __ballot(m1), b2 = __ballot(m2);
-    const int n1 = __popcll(b1);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (m1) {
-      const int k = __popcll(b1 & below);
-      swp[1 + 2 * k] = j + lane;
-      swp[2 + 2 * k] = pcont;
-    }
-    if (m2) {
-      const int k = n1 + __popcll(b2 & below);
-      swp[1 + 2 * k] = epos;
-      swp[2 + 2 * k] = econt;
-    }
-    if (lane == 0) swp[0] = n1 + __popcll(b2);
   }
 }
 
@@ -596,29 +602,22 @@ __global__ void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv);
 
 #define TI_LDS ((size_t)(2 * TI_N * (TI_N + 1) + 1024) * sizeof(cplx))  // M, X, T of tri_inv64
 
-typedef void (*panel_fn)(int, cplx *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int, int,
+typedef void (*panel_fn)(int, cplx *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int,
                          int32_t *);
-static const panel_fn panel_fns[2][3] = {{panel_kernel<4, false>, panel_kernel<8, false>, panel_kernel<16, false>},
-                                         {panel_kernel<4, true>, panel_kernel<8, true>, panel_kernel<16, true>}};
+static const panel_fn panel_fns[2] = {panel_kernel<1>, panel_kernel<2>};
 
 static int panel_attr_done[64];
 
-// rows per wavefront (as an index into {4, 8, 16}: 32, 64 or 128 rows per
-// workgroup) and workgroup count of a panel of R rows: the fewest rows per
-// wavefront that keep P <= PANEL_TARGET_P, else 16 rows per wavefront and as many
-// workgroups as needed
-static bool panel_shape(int R, int ncu, int *rpt_idx, int *P_out, int *one_round) {
+// rows per lane of the chain wavefront (1: 64, 2: 128 rows per workgroup) and the
+// workgroup count of a panel of R rows: 64 rows per workgroup while that keeps
+// P <= PANEL_RPL1_PMAX, else 128
+static bool panel_shape(int R, int ncu, int *rpl, int *P_out) {
   const int pmax = (ncu < PANEL_PMAX) ? ncu : PANEL_PMAX;
-  int k = 0, P = 0;
-  for (k = 0; k < 3; ++k) {
-    P = (R + PNW * (4 << k) - 1) / (PNW * (4 << k));
-    if (P <= PANEL_TARGET_P) break;
-  }
-  if (k == 3) k = 2;
+  int k = (R <= 64 * PANEL_RPL1_PMAX) ? 1 : 2;
+  const int P = (R + 64 * k - 1) / (64 * k);
   if (P < 1 || P > pmax) return false;
-  *rpt_idx = k;
+  *rpl = k;
   *P_out = P;
-  *one_round = (P <= PANEL_ONE_ROUND_PMAX);
   return true;
 }
 
@@ -627,10 +626,9 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
-    for (int o = 0; o < 2; ++o)
-      for (int k = 0; k < 3; ++k)
-        BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[o][k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)PANEL_LDS));
+    for (int k = 0; k < 2; ++k)
+      BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)PANEL_LDS(k + 1)));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ST_LDS));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -641,11 +639,11 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   BM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   BM_HIP_TRY(hipMemsetAsync(dev_err, 0, 2 * sizeof(int32_t), s));
   const int npanel = (n + LU_NB - 1) / LU_NB;
-  int shape[3 * 1024];  // rows-per-lane index, P, one_round per panel
+  int shape[3 * 1024];  // rows per lane, P per panel
   if (npanel > 1024) return BM_E_ARG;
   for (int pi = 0; pi < npanel; ++pi) {
     const int R = n - pi * LU_NB;
-    if (!panel_shape(R, ncu, &shape[3 * pi], &shape[3 * pi + 1], &shape[3 * pi + 2])) return BM_E_ARG;
+    if (!panel_shape(R, ncu, &shape[3 * pi], &shape[3 * pi + 1])) return BM_E_ARG;
   }
   if (npanel > 0) {  // the first panel's words of slot buffer 0; each panel refills the next one's
     const int jb0 = (n < LU_NB) ? n : LU_NB;
@@ -661,24 +659,19 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
       next_jb = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
       next_P = shape[3 * (pi + 1) + 1];
     }
-    // all workgroups of the panel on one XCD (measured slower on MI355X: off)
-    int xs = 1;
-#ifdef BM_PANEL_XCD
-    xs = (BM_PANEL_XCD && ncu >= 256 && P <= ncu / 8) ? 8 : 1;
-#endif
     cplx *cur = w->slots + (size_t)(pi & 1) * SLOT_ELEMS, *nxt = w->slots + (size_t)((pi + 1) & 1) * SLOT_ELEMS;
     int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
     long ldal = (long)lda;
     int nn = n, jj = j, jbb = jb;
-    void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &xs, &swp};
+    void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp};
     // All P workgroups must run at the same time.  P <= the CU count (checked in
     // panel_shape) and one workgroup fits a CU, so on a device that is not
     // saturated by other work every workgroup is resident at once; a plain launch
     // avoids the start and drain cost of a cooperative launch.  Every wait in the
     // kernel is bounded, so a launch whose workgroups cannot all become resident
     // ends with BM_E_DEVICE, not a hang.
-    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[shape[3 * pi + 2]][shape[3 * pi]], dim3(xs * P), dim3(PNT),
-                               args, PANEL_LDS, s));
+    const int rpl = shape[3 * pi];
+    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS(rpl), s));
     const int nr = n - j - jb;
     const int nleft = (j + SWAP_COLS - 1) / SWAP_COLS, nright = (nr + ST_CW - 1) / ST_CW;
     if (nleft + nright > 0) {
