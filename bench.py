@@ -49,7 +49,7 @@ def traffic_record():
     return rec.get("bytes_per_launch")
 
 
-def run_formulation(form, w, steps, warmup):
+def run_formulation(form, w, steps, warmup, precision="fp64"):
     import torch
     from paper_2512_14193_amd import binding as B
 
@@ -61,6 +61,8 @@ def run_formulation(form, w, steps, warmup):
     theta_inc = torch.as_tensor(w.theta_inc, dtype=torch.float64, device=dev)
     theta_obs = torch.as_tensor(w.theta_obs, dtype=torch.float64, device=dev)
     P = B.Problem(N, form)
+    if precision != "fp64":
+        P.set_precision(precision, tol=1e-12, max_iter=10)
     Bm = B.fortran_empty(P.rows, R)
     X = B.fortran_empty(P.rows, R)
     F = B.fortran_empty(len(w.theta_obs), R)
@@ -85,6 +87,7 @@ def run_formulation(form, w, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, cnt = P.phase_times()
+    refine = P.refine_stats()
     P.set_profiling(False)
     P.sync()  # raises if a kernel reported a device-side error
     info = P.block_lu(sync=True)
@@ -92,9 +95,32 @@ def run_formulation(form, w, steps, warmup):
         raise RuntimeError(f"{form}: singular factor, info = {info}")
     phases = {name: (ms[i] / cnt[i] if cnt[i] else None)
               for i, name in enumerate(["assemble", "schur_gemm", "lu", "solve", "far_field"])}
-    out = {"seconds": t1 - t0, "phase_ms": phases, "X": X.cpu().numpy(), "F": F.cpu().numpy()}
+    out = {"seconds": t1 - t0, "phase_ms": phases, "X": X.cpu().numpy(), "F": F.cpu().numpy(),
+           "refine_iterations": refine[0], "rel_residual": refine[1]}
     P.close()
     return out
+
+
+def mixed_precision_section(name, steps, warmup):
+    """FP64 block LU against the mixed-precision one (FP32 matrix-core Schur
+    complement and trailing updates + FP64 refinement to 1e-12 relative residual)
+    on the same workload, both end to end."""
+    import numpy as np
+    from paper_2512_14193_amd import inputs as I
+    w = I.workload(name)
+    N = w.boundary.n_nodes
+    res = {}
+    for prec in ("fp64", "mixed"):
+        r = run_formulation("mixed", w, steps, warmup, precision=prec)
+        ph = r["phase_ms"]
+        res[prec] = {"solves_per_s": steps / r["seconds"], "ms_per_step": 1e3 * r["seconds"] / steps,
+                     "phase_ms": ph, "schur_tflops": 16.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
+                     "refine_iterations": r["refine_iterations"], "rel_residual": r["rel_residual"], "X": r["X"]}
+    Xf, Xm = res["fp64"].pop("X"), res["mixed"].pop("X")
+    diff = float(np.max(np.linalg.norm(Xm - Xf, axis=0) / np.linalg.norm(Xf, axis=0)))
+    return {"workload": name, "unknowns": 3 * N, "steps": steps, "fp64": res["fp64"], "mixed": res["mixed"],
+            "speedup_mixed_over_fp64": res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"],
+            "rel_diff_mixed_vs_fp64": diff}
 
 
 def cpu_baseline(w):
@@ -134,6 +160,9 @@ def main():
     ap.add_argument("--workload", default="star2048")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs mixed-precision comparison")
+    ap.add_argument("--mixed-workload", default="star8192")
+    ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
@@ -194,6 +223,8 @@ def main():
                              "phase_ms": ordi["phase_ms"], "speedup_mixed_over_ordinary": value / v_ord,
                              "rel_diff_uq_mixed_vs_ordinary": diff,
                              "paper_context": "1.38-1.44x on 2x EPYC 9654 (CPU, zeta-corrected quadrature, disk)"}
+    if not args.no_mixed:
+        rec["mixed_precision"] = mixed_precision_section(args.mixed_workload, args.mixed_steps, 1)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -61,8 +61,16 @@ enum bm_status {
   BM_E_NOMEM = -2,   /* device allocation failed                               */
   BM_E_HIP = -3,     /* a HIP runtime call failed                              */
   BM_E_STATE = -4,   /* call out of order (e.g. bm_solve before bm_block_lu)   */
-  BM_E_DEVICE = -5   /* a kernel reported an internal error (e.g. a bounded
+  BM_E_DEVICE = -5,  /* a kernel reported an internal error (e.g. a bounded
                         wait expired); results of the call are invalid         */
+  BM_E_NOCONV = -6   /* mixed precision: the refinement of bm_solve stopped at
+                        max_iter above the tolerance; X holds the last iterate */
+};
+
+enum bm_precision {
+  BM_PREC_FP64 = 0,  /* FP64 throughout (default)                                   */
+  BM_PREC_MIXED = 1  /* Schur complement and trailing LU updates on the FP32 matrix
+                        cores, FP64 iterative refinement in bm_solve (mixed form)  */
 };
 
 /* Maximum number of right-hand sides handled per internal pass; bm_solve and
@@ -129,6 +137,25 @@ int bm_block_lu(bm_problem *p, int32_t *info);
  * Errors: BM_E_STATE before bm_block_lu, BM_E_ARG. */
 int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, int64_t ldx);
 
+/* Precision of the following bm_block_lu calls and of the solves with their
+ * factors.  BM_PREC_MIXED (mixed formulation only): U33 = -Bot * Top and the
+ * trailing updates of its LU run on the FP32 matrix cores (operands rounded to
+ * complex64, FP32 accumulation, FP64 storage); the panel factorisation, the
+ * row interchanges and the U12 substitution stay FP64.  bm_solve then refines
+ * every right-hand side, x <- x + F^{-1} (b - A x) with the FP64 blocks of the
+ * exact mixed system in the residual and the mixed-precision factors F, until
+ * ||b - A x||_2 <= tol ||b||_2 or max_iter steps; it synchronises the stream
+ * once per step and returns BM_E_NOCONV if a column misses the tolerance.
+ * Defaults: BM_PREC_FP64, tol = 1e-12, max_iter = 10.
+ * Errors: BM_E_ARG (unknown precision, mixed precision for BM_ORDINARY, tol <= 0,
+ * max_iter < 0). */
+int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_iter);
+
+/* Refinement statistics of the latest bm_solve (host pointers): the largest
+ * number of refinement steps over its column chunks and the final
+ * max_j ||b_j - A x_j||_2 / ||b_j||_2 (0 after an FP64 solve). */
+int bm_refine_stats(bm_problem *p, int32_t *iterations, double *rel_residual);
+
 /* Right-hand sides for incident plane waves u_in = exp(i k0 (cos th, sin th).x):
  * b3 = -u_in - beta d_nu u_in, b1 = b2 = 0 (mixed) or [b3; 0] (ordinary).
  * theta_inc: device array of nrhs angles.  B as in bm_solve. */
@@ -179,6 +206,11 @@ int bm_zgemm(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *al
              const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
              void *C, int64_t ldc);
 int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info);
+/* bm_zgemm_f32: as bm_zgemm, with A and B rounded to complex64 and the products
+ * accumulated in FP32 on the matrix cores; C stays complex128. */
+int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha,
+                 const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
+                 void *C, int64_t ldc);
 
 /* Text for a status code. */
 const char *bm_strerror(int code);

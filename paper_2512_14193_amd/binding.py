@@ -17,12 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbm_mi355x.so")
 
 BM_MIXED, BM_ORDINARY = 0, 1
-BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE = 0, -1, -2, -3, -4, -5
+BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
+BM_PREC_FP64, BM_PREC_MIXED = 0, 1
 BM_MAX_NRHS = 32
 
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
-            "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror"]
+            "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
+            "bm_zgemm_f32"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -70,6 +72,9 @@ def lib():
         L.bm_phase_times.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
         L.bm_zgemm.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_zgetrf.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
+        L.bm_zgemm_f32.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
+        L.bm_set_precision.argtypes = [vp, i32, ctypes.c_double, i32]
+        L.bm_refine_stats.argtypes = [vp, ctypes.POINTER(i32), dp]
         L.bm_strerror.argtypes = [ctypes.c_int]
         L.bm_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -206,6 +211,18 @@ class Problem:
     def sync(self):
         check(lib().bm_sync(self._h), "bm_sync")
 
+    def set_precision(self, precision: str = "fp64", tol: float = 1e-12, max_iter: int = 10):
+        """bm_set_precision: "fp64" or "mixed" (FP32 matrix cores + FP64 refinement)."""
+        code = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED}[precision]
+        check(lib().bm_set_precision(self._h, code, float(tol), int(max_iter)), "bm_set_precision")
+
+    def refine_stats(self):
+        """(refinement steps, final max relative residual) of the latest solve."""
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        check(lib().bm_refine_stats(self._h, ctypes.byref(it), ctypes.byref(rr)), "bm_refine_stats")
+        return it.value, rr.value
+
     def set_profiling(self, on: bool = True):
         check(lib().bm_set_profiling(self._h, 1 if on else 0), "bm_set_profiling")
 
@@ -227,6 +244,18 @@ def zgemm(alpha, A, B, beta, C, stream=None):
     be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
     check(lib().bm_zgemm(_stream_handle(stream), m, n, k, al, _ptr(A), _ld(A), _ptr(B), _ld(B), be, _ptr(C), _ld(C)),
           "bm_zgemm")
+    return C
+
+
+def zgemm_f32(alpha, A, B, beta, C, stream=None):
+    """C = alpha A B + beta C with complex64 operands and FP32 accumulation (complex128 in and out)."""
+    stream = stream or torch.cuda.current_stream()
+    m, k = A.shape
+    n = B.shape[1]
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    check(lib().bm_zgemm_f32(_stream_handle(stream), m, n, k, al, _ptr(A), _ld(A), _ptr(B), _ld(B), be, _ptr(C),
+                             _ld(C)), "bm_zgemm_f32")
     return C
 
 

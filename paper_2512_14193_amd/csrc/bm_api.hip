@@ -16,6 +16,7 @@ const char *bm_strerror(int code) {
     case BM_E_HIP: return "HIP runtime error";
     case BM_E_STATE: return "call out of order";
     case BM_E_DEVICE: return "device-side error (bounded wait expired)";
+    case BM_E_NOCONV: return "iterative refinement did not reach the tolerance";
     default: return code > 0 ? "singular factor (info > 0)" : "unknown status";
   }
 }
@@ -33,6 +34,9 @@ static void free_problem(bm_problem *p) {
   (void)hipFree(p->work_g);
   (void)hipFree(p->work_p);
   (void)hipFree(p->dev_err);
+  (void)hipFree(p->ir_r);
+  (void)hipFree(p->ir_d);
+  (void)hipFree(p->ir_norm);
   bm_getrf_ws_destroy(p->gws);
   for (int i = 0; i < BM_NPHASE; ++i)
     if (p->ev_created[i])
@@ -77,6 +81,14 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
     ok = ok && hipMalloc(&p->work_p, sizeof(cplx) * (wp > w2 ? wp : w2)) == hipSuccess;
   }
   ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 2) == hipSuccess;
+  if (formulation == BM_MIXED) {
+    ok = ok && hipMalloc(&p->ir_r, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
+    ok = ok && hipMalloc(&p->ir_d, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
+    ok = ok && hipMalloc(&p->ir_norm, sizeof(double) * 2 * BM_MAX_NRHS) == hipSuccess;
+  }
+  p->prec = BM_PREC_FP64;
+  p->ir_tol = 1e-12;
+  p->ir_maxit = 10;
   if (ok) p->gws = bm_getrf_ws_create((int)nf);
   if (!ok || !p->gws) {
     free_problem(p);
@@ -166,59 +178,136 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   if (p->form == BM_MIXED) {
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
     phase_begin(p, BM_PH_SCHUR);
-    rc = bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
+    // (FP32 matrix cores in mixed precision; bm_solve refines against the FP64 blocks)
+    rc = (p->prec == BM_PREC_MIXED ? bm_launch_zgemm32 : bm_launch_zgemm)(
+        p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
     phase_end(p, BM_PH_SCHUR);
     if (rc) return rc;
   }
   phase_begin(p, BM_PH_LU);
-  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws);
+  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec == BM_PREC_MIXED);
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);
   if (rc) return rc;
   p->state = BM_ST_FACTORED;
+  p->factored_prec = p->prec;
   if (info) return read_dev_err(p, info);
+  return BM_OK;
+}
+
+// One pass of the direct solve for nr <= BM_MAX_NRHS right-hand sides (X may
+// not alias B).  Mixed form, Corollary lem:for_ssm_RHS.
+static int solve_pass(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, cplx *Xc, int64_t ldx) {
+  const int n = p->n, nf = p->nf;
+  const int rows = (p->form == BM_MIXED) ? 3 * n : 2 * n;
+  BM_HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(cplx) * ldx, Bc, sizeof(cplx) * ldb, sizeof(cplx) * rows, nr,
+                              hipMemcpyDeviceToDevice, p->stream));
+  cplx *X3 = (p->form == BM_MIXED) ? Xc + 2 * n : Xc;
+  cplx *Y = p->work_g;  // nf x nr, ld nf
+  int rc;
+  if (p->form == BM_MIXED) {
+    // c = b3 - M31 b1 - M32 b2 = b3 - Bot [b1; b2]
+    rc = bm_launch_gemv_sub(p->stream, n, 2 * n, nr, p->bot, n, Xc, ldx, X3, ldx, p->work_p);
+    if (rc) return rc;
+  }
+  rc = bm_launch_gather(p->stream, nf, nr, p->perm, X3, ldx, Y, nf);
+  if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+  if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+  if (rc) return rc;
+  BM_HIP_TRY(hipMemcpy2DAsync(X3, sizeof(cplx) * ldx, Y, sizeof(cplx) * nf, sizeof(cplx) * nf, nr,
+                              hipMemcpyDeviceToDevice, p->stream));
+  if (p->form == BM_MIXED) {
+    // x1 = b1 - M13 z3, x2 = b2 - M23 z3:  [x1; x2] = [b1; b2] - Top z3
+    rc = bm_launch_gemv_sub(p->stream, 2 * n, n, nr, p->top, 2 * n, Y, nf, Xc, ldx, p->work_p);
+    if (rc) return rc;
+  }
+  return BM_OK;
+}
+
+// Residual r = b - A x of the mixed system with the FP64 blocks:
+//   [r1; r2] = [b1; b2] - [x1; x2] - Top x3,   r3 = b3 - Bot [x1; x2].
+// Returns max_j ||r_j|| / ||b_j|| (synchronises the stream).
+static int residual(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, const cplx *Xc, int64_t ldx, double *relres) {
+  const int n = p->n, rows = 3 * n;
+  cplx *R = p->ir_r;
+  int rc = bm_launch_ir_prep(p->stream, rows, 2 * n, nr, Bc, ldb, Xc, ldx, R, rows);
+  if (!rc) rc = bm_launch_gemv_sub(p->stream, 2 * n, n, nr, p->top, 2 * n, Xc + 2 * n, ldx, R, rows, p->work_p);
+  if (!rc) rc = bm_launch_gemv_sub(p->stream, n, 2 * n, nr, p->bot, n, Xc, ldx, R + 2 * n, rows, p->work_p);
+  if (!rc) rc = bm_launch_colnorms(p->stream, rows, nr, R, rows, Bc, ldb, p->ir_norm);
+  if (rc) return rc;
+  double h[2 * BM_MAX_NRHS];
+  BM_HIP_TRY(hipMemcpyAsync(h, p->ir_norm, sizeof(double) * 2 * nr, hipMemcpyDeviceToHost, p->stream));
+  BM_HIP_TRY(hipStreamSynchronize(p->stream));
+  double worst = 0.0;
+  for (int j = 0; j < nr; ++j) {
+    const double rj = sqrt(h[2 * j]), bj = sqrt(h[2 * j + 1]);
+    const double q = (bj > 0.0) ? rj / bj : rj;
+    if (!(q <= worst)) worst = q;  // NaN propagates
+  }
+  *relres = worst;
   return BM_OK;
 }
 
 int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv, int64_t ldx) {
   if (!p || nrhs < 0 || (nrhs > 0 && (!Bv || !Xv))) return BM_E_ARG;
   if (p->state < BM_ST_FACTORED) return BM_E_STATE;
-  const int n = p->n, nf = p->nf;
+  const int n = p->n;
   const int rows = (p->form == BM_MIXED) ? 3 * n : 2 * n;
   if (ldb < rows || ldx < rows) return BM_E_ARG;
   if (Bv == Xv) return BM_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   const cplx *B = (const cplx *)Bv;
   cplx *X = (cplx *)Xv;
+  const bool refine = (p->factored_prec == BM_PREC_MIXED);
+  int status = BM_OK;
+  p->ir_iters = 0;
+  p->ir_relres = 0.0;
   phase_begin(p, BM_PH_SOLVE);
   for (int r0 = 0; r0 < nrhs; r0 += BM_MAX_NRHS) {
     const int nr = (nrhs - r0 < BM_MAX_NRHS) ? nrhs - r0 : BM_MAX_NRHS;
     const cplx *Bc = B + (size_t)r0 * ldb;
     cplx *Xc = X + (size_t)r0 * ldx;
-    BM_HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(cplx) * ldx, Bc, sizeof(cplx) * ldb, sizeof(cplx) * rows, nr,
-                                hipMemcpyDeviceToDevice, p->stream));
-    cplx *X3 = (p->form == BM_MIXED) ? Xc + 2 * n : Xc;
-    cplx *Y = p->work_g;  // nf x nr, ld nf
-    int rc;
-    if (p->form == BM_MIXED) {
-      // Corollary lem:for_ssm_RHS: c = b3 - M31 b1 - M32 b2 = b3 - Bot [b1; b2]
-      rc = bm_launch_gemv_sub(p->stream, n, 2 * n, nr, p->bot, n, Xc, ldx, X3, ldx, p->work_p);
-      if (rc) return rc;
-    }
-    rc = bm_launch_gather(p->stream, nf, nr, p->perm, X3, ldx, Y, nf);
-    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
-    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+    int rc = solve_pass(p, nr, Bc, ldb, Xc, ldx);
     if (rc) return rc;
-    BM_HIP_TRY(hipMemcpy2DAsync(X3, sizeof(cplx) * ldx, Y, sizeof(cplx) * nf, sizeof(cplx) * nf, nr,
-                                hipMemcpyDeviceToDevice, p->stream));
-    if (p->form == BM_MIXED) {
-      // x1 = b1 - M13 z3, x2 = b2 - M23 z3:  [x1; x2] = [b1; b2] - Top z3
-      rc = bm_launch_gemv_sub(p->stream, 2 * n, n, nr, p->top, 2 * n, Y, nf, Xc, ldx, p->work_p);
-      if (rc) return rc;
+    if (refine) {
+      // FP64 iterative refinement: x += A_f^{-1} (b - A x) with the FP64 blocks in
+      // the residual and the mixed-precision factors in the correction
+      double rr = 0.0;
+      int it = 0;
+      for (;;) {
+        rc = residual(p, nr, Bc, ldb, Xc, ldx, &rr);
+        if (rc) return rc;
+        if (rr <= p->ir_tol || it >= p->ir_maxit) break;
+        rc = solve_pass(p, nr, p->ir_r, rows, p->ir_d, rows);
+        if (!rc) rc = bm_launch_axpy(p->stream, rows, nr, p->ir_d, rows, Xc, ldx);
+        if (rc) return rc;
+        ++it;
+      }
+      if (it > p->ir_iters) p->ir_iters = it;
+      if (!(rr <= p->ir_relres)) p->ir_relres = rr;
+      if (!(rr <= p->ir_tol)) status = BM_E_NOCONV;
     }
   }
   phase_end(p, BM_PH_SOLVE);
+  return status;
+}
+
+int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_iter) {
+  if (!p) return BM_E_ARG;
+  if (precision != BM_PREC_FP64 && precision != BM_PREC_MIXED) return BM_E_ARG;
+  if (precision == BM_PREC_MIXED && p->form != BM_MIXED) return BM_E_ARG;
+  if (!(tol > 0.0) || max_iter < 0) return BM_E_ARG;
+  p->prec = precision;
+  p->ir_tol = tol;
+  p->ir_maxit = max_iter;
+  return BM_OK;
+}
+
+int bm_refine_stats(bm_problem *p, int32_t *iterations, double *rel_residual) {
+  if (!p || !iterations || !rel_residual) return BM_E_ARG;
+  *iterations = p->ir_iters;
+  *rel_residual = p->ir_relres;
   return BM_OK;
 }
 
@@ -316,6 +405,16 @@ int bm_zgemm(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *al
                          (const cplx *)B, ldb, cmk(beta[0], beta[1]), (cplx *)C, ldc);
 }
 
+int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha, const void *A,
+                 int64_t lda, const void *B, int64_t ldb, const double *beta, void *C, int64_t ldc) {
+  if (m < 0 || n < 0 || k < 0 || !alpha || !beta) return BM_E_ARG;
+  if (m == 0 || n == 0) return BM_OK;
+  if (!C || (k > 0 && (!A || !B))) return BM_E_ARG;
+  if (lda < m || ldb < k || ldc < m) return BM_E_ARG;
+  return bm_launch_zgemm32((hipStream_t)hip_stream, m, n, k, cmk(alpha[0], alpha[1]), (const cplx *)A, lda,
+                           (const cplx *)B, ldb, cmk(beta[0], beta[1]), (cplx *)C, ldc);
+}
+
 int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info) {
   if (n < 0 || lda < n || (n > 0 && (!A || !ipiv))) return BM_E_ARG;
   if (n == 0) {
@@ -329,7 +428,7 @@ int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, 
     bm_getrf_ws_destroy(w);
     return BM_E_NOMEM;
   }
-  int rc = bm_getrf_run(s, n, (cplx *)A, lda, ipiv, dev_err, w);
+  int rc = bm_getrf_run(s, n, (cplx *)A, lda, ipiv, dev_err, w, 0);
   int32_t h[2] = {0, 0};
   if (hipMemcpyAsync(h, dev_err, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

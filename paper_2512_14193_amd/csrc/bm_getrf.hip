@@ -621,7 +621,8 @@ static bool panel_shape(int R, int ncu, int *rpl, int *P_out) {
   return true;
 }
 
-int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w) {
+int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                 int gemm32) {
   if (!w || w->n < n) return BM_E_ARG;
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
@@ -680,8 +681,9 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
       BM_HIP_TRY(hipGetLastError());
     }
     if (nr > 0) {
-      const int rc = bm_launch_zgemm(s, nr, nr, jb, mone, A + (j + jb) + (long)j * lda, lda,
-                                     A + j + (long)(j + jb) * lda, lda, one, A + (j + jb) + (long)(j + jb) * lda, lda);
+      const int rc = (gemm32 ? bm_launch_zgemm32 : bm_launch_zgemm)(
+          s, nr, nr, jb, mone, A + (j + jb) + (long)j * lda, lda, A + j + (long)(j + jb) * lda, lda, one,
+          A + (j + jb) + (long)(j + jb) * lda, lda);
       if (rc) return rc;
     }
   }

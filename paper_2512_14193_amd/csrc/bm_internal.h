@@ -134,6 +134,16 @@ struct bm_problem {
   int32_t *dev_err;     // device-side error flag and getrf info: [0] error, [1] info
   bm_getrf_ws *gws;
 
+  // precision of the factorisation (BM_PREC_*) and the FP64 refinement of bm_solve
+  int prec;
+  int factored_prec;    // precision of the factors held now
+  double ir_tol;
+  int ir_maxit;
+  int ir_iters;         // refinement steps of the last bm_solve
+  double ir_relres;     // its final max_j ||b_j - A x_j|| / ||b_j||
+  cplx *ir_r, *ir_d;    // mixed: 3N x BM_MAX_NRHS residual and correction
+  double *ir_norm;      // device: per column ||r_j||^2, ||b_j||^2
+
   int profiling;
   hipEvent_t ev[BM_NPHASE][BM_EV_RING][2];
   int ev_created[BM_NPHASE];
@@ -150,12 +160,15 @@ int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int
                         cplx *F, int64_t ldf);
 int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
                     const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
+// the same product on the FP32 matrix cores (operands rounded to complex64, FP32 accumulation)
+int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
+                      const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
 
 // LU
 bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
-                 bm_getrf_ws *w);
+                 bm_getrf_ws *w, int gemm32);
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);
 
 // solve support (bm_solve.hip): the composed row permutation, gathers, the skinny
@@ -168,6 +181,12 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
                        cplx *C, int64_t ldc, cplx *work);
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
+// refinement support: R = B - [X(0:n12, :); 0] (rows), X += D, per-column squared norms
+int bm_launch_ir_prep(hipStream_t s, int rows, int n12, int nrhs, const cplx *B, int64_t ldb, const cplx *X,
+                      int64_t ldx, cplx *R, int64_t ldr);
+int bm_launch_axpy(hipStream_t s, int rows, int nrhs, const cplx *D, int64_t ldd, cplx *X, int64_t ldx);
+int bm_launch_colnorms(hipStream_t s, int rows, int nrhs, const cplx *R, int64_t ldr, const cplx *B, int64_t ldb,
+                       double *out);
 
 
 #define BM_HIP_TRY(expr)                         \

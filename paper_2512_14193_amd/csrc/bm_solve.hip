@@ -308,3 +308,78 @@ int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// iterative refinement support (mixed-precision factorisation)
+// ---------------------------------------------------------------------------
+// R = B - [X(0:n12, :); 0]: the part of the residual b - A x that the identity
+// blocks of the mixed system contribute (the products with Top and Bot follow)
+__global__ void ir_prep_kernel(int rows, int n12, int nrhs, const cplx *B, long ldb, const cplx *X, long ldx,
+                               cplx *R, long ldr) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * nrhs) return;
+  const int i = (int)(idx % rows), j = (int)(idx / rows);
+  const cplx b = B[i + (long)j * ldb];
+  R[i + (long)j * ldr] = (i < n12) ? csub(b, X[i + (long)j * ldx]) : b;
+}
+
+__global__ void axpy_kernel(int rows, int nrhs, const cplx *D, long ldd, cplx *X, long ldx) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * nrhs) return;
+  const int i = (int)(idx % rows), j = (int)(idx / rows);
+  X[i + (long)j * ldx] = cadd(X[i + (long)j * ldx], D[i + (long)j * ldd]);
+}
+
+// out[2 j] = ||R(:, j)||^2, out[2 j + 1] = ||B(:, j)||^2: one workgroup per column,
+// fixed-order tree reduction (deterministic)
+__global__ __launch_bounds__(256) void colnorm_kernel(int rows, const cplx *R, long ldr, const cplx *B, long ldb,
+                                                      double *out) {
+  __shared__ double sr[256], sb[256];
+  const int j = blockIdx.x;
+  double ar = 0.0, ab = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) {
+    ar += cabs2(R[i + (long)j * ldr]);
+    ab += cabs2(B[i + (long)j * ldb]);
+  }
+  sr[threadIdx.x] = ar;
+  sb[threadIdx.x] = ab;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sr[threadIdx.x] += sr[threadIdx.x + h];
+      sb[threadIdx.x] += sb[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * j] = sr[0];
+    out[2 * j + 1] = sb[0];
+  }
+}
+
+int bm_launch_ir_prep(hipStream_t s, int rows, int n12, int nrhs, const cplx *B, int64_t ldb, const cplx *X,
+                      int64_t ldx, cplx *R, int64_t ldr) {
+  const long tot = (long)rows * nrhs;
+  if (tot == 0) return BM_OK;
+  hipLaunchKernelGGL(ir_prep_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, n12, nrhs, B,
+                     (long)ldb, X, (long)ldx, R, (long)ldr);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_axpy(hipStream_t s, int rows, int nrhs, const cplx *D, int64_t ldd, cplx *X, int64_t ldx) {
+  const long tot = (long)rows * nrhs;
+  if (tot == 0) return BM_OK;
+  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, nrhs, D, (long)ldd, X,
+                     (long)ldx);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_colnorms(hipStream_t s, int rows, int nrhs, const cplx *R, int64_t ldr, const cplx *B, int64_t ldb,
+                       double *out) {
+  if (nrhs == 0) return BM_OK;
+  hipLaunchKernelGGL(colnorm_kernel, dim3(nrhs), dim3(256), 0, s, rows, R, (long)ldr, B, (long)ldb, out);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}

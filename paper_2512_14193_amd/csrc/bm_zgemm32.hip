@@ -1,0 +1,168 @@
+// Complex GEMM on the FP32 matrix cores with FP64 operands and result:
+//   C = alpha A B + beta C,  A m x k, B k x n, C m x n, column-major complex128.
+// The operands are rounded to complex64 when they are staged into LDS, the
+// products are accumulated in FP32 by v_mfma_f32_32x32x2f32, and the result is
+// widened back to FP64 for the update of C.
+//
+// Used in the mixed-precision factorisation: the Schur complement
+// U33 = -[M31 M32][M13; M23] of Theorem (thm:LU) and the trailing updates of the
+// blocked LU run here; FP64 iterative refinement against the FP64 blocks then
+// recovers the FP64 solution.
+//
+// Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 128 x 128 tile of
+// C, two workgroups per CU (accumulators in VGPRs, no spills); each wave owns
+// 64 x 64 = 2 x 2 blocks of 32 x 32 with separate real and
+// imaginary FP32 accumulators (16 values per lane each).  A complex product costs
+// four real MFMAs: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  Operands are staged
+// through LDS in k-slices of G2_BK complex values, double buffered, with the global
+// loads of the next slice in flight during the MFMAs of the current one.
+//
+// MFMA operand order: the B fragment is the MFMA's first operand and the A
+// fragment its second, so the 32 x 32 result lands transposed: lane l holds row
+// l % 32 of C and register r the column (r % 4) + 8 (r / 4) + 4 (l / 32), and each
+// global store writes two 32-row column segments.
+#include "bm_internal.h"
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+#define G2_BM 128
+#define G2_BN 128
+#ifndef G2_BK
+#define G2_BK 8                       // k-slice of complex values per LDS stage
+#endif
+#define G2_LPT (G2_BK * G2_BM / 256)  // complex values of each operand loaded per thread and stage
+
+struct f32c {
+  float x, y;
+};
+
+__device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <bool BETA0>
+__global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
+                                                      long lda, const cplx *__restrict__ B, long ldb, cplx beta,
+                                                      cplx *__restrict__ C, long ldc, int tiles_m) {
+  __shared__ f32c As[2][G2_BK][G2_BM];
+  __shared__ f32c Bs[2][G2_BK][G2_BN];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int tile = blockIdx.x;
+  const int row0 = (tile % tiles_m) * G2_BM, col0 = (tile / tiles_m) * G2_BN;
+
+  // global -> LDS assignment (G2_LPT complex values per thread and operand)
+  //   A: 128 rows x G2_BK k: row tid % 128, k = tid / 128 + 2 u
+  //   B: G2_BK k x 128 cols: col tid / 2, k = G2_LPT (tid % 2) + u
+  const int a_r = tid & 127, a_k = tid >> 7;
+  const int b_c = tid >> 1, b_k = (tid & 1) * G2_LPT;
+
+  cplx ra[G2_LPT], rb[G2_LPT];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < G2_LPT; ++u) {
+      const int kk = k0 + a_k + (256 / G2_BM) * u, rr = row0 + a_r;
+      ra[u] = (rr < m && kk < k) ? A[rr + (long)kk * lda] : cmk(0, 0);
+      const int kb = k0 + b_k + u, cc = col0 + b_c;
+      rb[u] = (kb < k && cc < n) ? B[kb + (long)cc * ldb] : cmk(0, 0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < G2_LPT; ++u) {
+      As[buf][a_k + (256 / G2_BM) * u][a_r] = f32c{(float)ra[u].x, (float)ra[u].y};
+      Bs[buf][b_k + u][b_c] = f32c{(float)rb[u].x, (float)rb[u].y};
+    }
+  };
+
+  f32x16 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accr[a][b][r] = 0.f;
+        acci[a][b][r] = 0.f;
+      }
+
+  const int nk = (k + G2_BK - 1) / G2_BK;
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  const int fh = lane >> 5, fi = lane & 31;
+  // operand fragments of one k-pair, double buffered in registers so that the
+  // LDS reads of the next pair are in flight during the MFMAs of this one
+  f32c av[2][2], bv[2][2];
+  auto fload = [&](int buf, int k2, int slot) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[slot][a] = As[buf][k2 + fh][wm * 64 + a * 32 + fi];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[slot][b] = Bs[buf][k2 + fh][wn * 64 + b * 32 + fi];
+  };
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload((it + 1) * G2_BK);
+    fload(buf, 0, 0);
+#pragma unroll
+    for (int k2 = 0; k2 < G2_BK; k2 += 2) {
+      const int cur = (k2 >> 1) & 1;
+      if (k2 + 2 < G2_BK) fload(buf, k2 + 2, cur ^ 1);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma32(bv[cur][b].x, av[cur][a].x, accr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma32(bv[cur][b].y, av[cur][a].x, acci[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma32(bv[cur][b].y, -av[cur][a].y, accr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma32(bv[cur][b].x, av[cur][a].y, acci[a][b]);
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: lane l, register r -> C(row l % 32, col (r % 4) + 8 (r / 4) + 4 (l / 32))
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = row0 + wm * 64 + a * 32 + fi;
+        const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
+        if (row < m && col < n) {
+          const cplx v = cmk((double)accr[a][b][r], (double)acci[a][b][r]);
+          cplx out = cmul(alpha, v);
+          if (!BETA0) out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
+          C[row + (long)col * ldc] = out;
+        }
+      }
+}
+
+int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
+                      int64_t ldb, cplx beta, cplx *C, int64_t ldc) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  const int tm = (m + G2_BM - 1) / G2_BM, tn = (n + G2_BN - 1) / G2_BN;
+  const long tiles = (long)tm * tn;
+  if (tiles > 0x7fffffffL) return BM_E_ARG;
+  if (beta.x == 0.0 && beta.y == 0.0)
+    hipLaunchKernelGGL(zgemm32_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda,
+                       B, (long)ldb, beta, C, (long)ldc, tm);
+  else
+    hipLaunchKernelGGL(zgemm32_kernel<false>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
+                       (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}

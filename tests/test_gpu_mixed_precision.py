@@ -1,0 +1,113 @@
+"""Mixed precision: FP32 matrix-core Schur complement and trailing updates, FP64
+iterative refinement against the FP64 blocks of the mixed system.
+
+The refined solution must meet the same bar as the FP64 path: 1e-10 relative
+per right-hand side against the CPU oracle, with the refinement's own residual
+max_j ||b_j - A x_j|| / ||b_j|| at or below its tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2512_14193_amd import binding as B
+from paper_2512_14193_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def to_dev(a):
+    return B.fortran(torch.as_tensor(np.asarray(a, dtype=np.complex128)).cuda())
+
+
+def rel_cols(x, y):
+    return np.max(np.linalg.norm(x - y, axis=0) / np.linalg.norm(y, axis=0))
+
+
+@pytest.mark.parametrize("m,n,k", [(128, 128, 16), (130, 77, 45), (1, 3, 200), (257, 300, 129), (33, 1, 1000),
+                                   (256, 384, 2048)])
+@pytest.mark.parametrize("beta", [0.0, 0.5 - 1.5j])
+def test_zgemm_f32_vs_numpy(m, n, k, beta):
+    rng = np.random.default_rng(m * 7919 + n * 31 + k)
+    g = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)  # noqa: E731
+    A, Bm, C = g(m, k), g(k, n), g(m, n)
+    alpha = -0.7 + 0.2j
+    dC = to_dev(C)
+    B.zgemm_f32(alpha, to_dev(A), to_dev(Bm), beta, dC)
+    ref = alpha * (A @ Bm) + beta * C
+    # FP32 operands and accumulation: normwise error ||dC|| / (|alpha| ||A|| ||B||)
+    # of order 2^-24 (FP64 would leave ~1e-17)
+    rel = np.linalg.norm(to_np(dC) - ref) / (abs(alpha) * np.linalg.norm(A) * np.linalg.norm(Bm))
+    assert rel < 1e-6, rel
+    if k >= 45:
+        assert rel > 1e-12, rel  # the products really ran in FP32
+
+
+CASES = [
+    ("disk256", I.disk(256, 1.0), I.Physics.from_wavenumbers(2.0, 3.0)),
+    ("star200-complexk", I.star(200), I.Physics.from_wavenumbers(6.0 + 0.4j, 9.0 + 0.6j)),
+    ("ellipse130", I.ellipse(130, 2.0, 0.7), I.Physics.from_wavenumbers(3.0, 7.0, beta=0.3 + 0.5j)),
+]
+
+
+@pytest.mark.parametrize("name,bnd,ph", CASES, ids=[c[0] for c in CASES])
+def test_mixed_precision_plane_waves(name, bnd, ph):
+    N = bnd.n_nodes
+    P = B.Problem(N, "mixed")
+    P.assemble(bnd, ph)
+    P.set_precision("mixed", tol=1e-12, max_iter=10)
+    assert P.block_lu() == 0
+    theta = I.plane_wave_angles(3, 7)
+    Bh = O.rhs_plane_wave(bnd, ph, theta, "mixed")
+    X = to_np(P.solve(to_dev(Bh)))
+    it, rr = P.refine_stats()
+    assert 1 <= it <= 6 and rr <= 1e-12, (it, rr)
+    Xo = O.zgesv(O.build_mixed(bnd, ph), Bh)
+    assert rel_cols(X, Xo) < 1e-10
+
+
+def test_mixed_precision_general_rhs_ragged():
+    bnd, ph = I.star(296), I.Physics.from_wavenumbers(5.0, 8.0)
+    P = B.Problem(296, "mixed")
+    P.assemble(bnd, ph)
+    P.set_precision("mixed")
+    assert P.block_lu() == 0
+    Bh = I.probing_rhs(3 * 296, 37, 11)  # 37 > BM_MAX_NRHS: two refined chunks
+    X = to_np(P.solve(to_dev(Bh)))
+    it, rr = P.refine_stats()
+    assert it >= 1 and rr <= 1e-12
+    assert rel_cols(X, O.zgesv(O.build_mixed(bnd, ph), Bh)) < 1e-10
+
+
+def test_mixed_precision_no_convergence_and_switch_back():
+    bnd, ph = I.star(128), I.Physics.from_wavenumbers(4.0, 6.0)
+    P = B.Problem(128, "mixed")
+    P.assemble(bnd, ph)
+    P.set_precision("mixed", tol=1e-12, max_iter=0)  # no refinement step allowed
+    P.block_lu()
+    Bh = I.probing_rhs(3 * 128, 2, 3)
+    X = B.fortran_empty(3 * 128, 2)
+    with pytest.raises(B.BMError) as e:
+        P.solve(to_dev(Bh), X)
+    assert e.value.code == B.BM_E_NOCONV
+    it, rr = P.refine_stats()
+    assert it == 0 and 1e-12 < rr < 1e-3  # the unrefined FP32-level solution
+    Xo = O.zgesv(O.build_mixed(bnd, ph), Bh)
+    assert 1e-12 < rel_cols(to_np(X), Xo) < 1e-3
+    P.set_precision("fp64")
+    P.block_lu()
+    X = to_np(P.solve(to_dev(Bh)))
+    assert P.refine_stats() == (0, 0.0)
+    assert rel_cols(X, Xo) < 1e-10
+
+
+def test_mixed_precision_rejected_for_ordinary():
+    P = B.Problem(64, "ordinary")
+    with pytest.raises(B.BMError) as e:
+        P.set_precision("mixed")
+    assert e.value.code == B.BM_E_ARG
