@@ -69,8 +69,8 @@ enum bm_status {
 
 enum bm_precision {
   BM_PREC_FP64 = 0,  /* FP64 throughout (default)                                   */
-  BM_PREC_MIXED = 1  /* Schur complement and trailing LU updates on the FP32 matrix
-                        cores, FP64 iterative refinement in bm_solve (mixed form)  */
+  BM_PREC_MIXED = 1  /* Schur complement on the FP32 matrix cores, FP64 iterative
+                        refinement in bm_solve (mixed formulation)                 */
 };
 
 /* Maximum number of right-hand sides handled per internal pass; bm_solve and
@@ -138,10 +138,10 @@ int bm_block_lu(bm_problem *p, int32_t *info);
 int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, int64_t ldx);
 
 /* Precision of the following bm_block_lu calls and of the solves with their
- * factors.  BM_PREC_MIXED (mixed formulation only): U33 = -Bot * Top and the
- * trailing updates of its LU run on the FP32 matrix cores (operands rounded to
- * complex64, FP32 accumulation, FP64 storage); the panel factorisation, the
- * row interchanges and the U12 substitution stay FP64.  bm_solve then refines
+ * factors.  BM_PREC_MIXED (mixed formulation only): U33 = -Bot * Top runs on the
+ * FP32 matrix cores (operands rounded to complex64, FP32 accumulation, FP64
+ * storage); the LU of U33 stays FP64 (its trailing updates are bound by memory
+ * traffic, not by the matrix cores).  bm_solve then refines
  * every right-hand side, x <- x + F^{-1} (b - A x) with the FP64 blocks of the
  * exact mixed system in the residual and the mixed-precision factors F, until
  * ||b - A x||_2 <= tol ||b||_2 or max_iter steps; it synchronises the stream

@@ -185,7 +185,9 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
     if (rc) return rc;
   }
   phase_begin(p, BM_PH_LU);
-  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec == BM_PREC_MIXED);
+  // (the trailing updates of the LU have k = 64 and are bound by memory traffic, not
+  // by the matrix cores, so they stay FP64 in either precision)
+  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, 0);
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);

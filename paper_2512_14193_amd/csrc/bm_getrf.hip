@@ -18,6 +18,9 @@
 //     of the panel also U12 = L11^{-1} A12 by forward substitution, one wavefront per
 //     two columns with lane = row.
 //  3. trailing update A22 -= L21 U12 with the MFMA GEMM.
+//  Steps 2 and 3 run first for the next panel's columns only; for all other
+//  columns they run on a second stream while the next panel is factored
+//  (lookahead of depth one).
 //
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
@@ -46,6 +49,10 @@
 #define PANEL_RPL1_PMAX 32        // 64 rows per workgroup while P stays within this, else 128
 #endif
 #define PANEL_LDS(rpl) ((size_t)LU_NB * (64 * (rpl) + 1) * sizeof(cplx))
+// LDS requested by every panel launch: more than 160 KB minus any GEMM workgroup's
+// share, so that no workgroup of the concurrent trailing update lands on a CU that
+// runs a panel workgroup (the chain wavefront would lose issue slots)
+#define PANEL_LDS_ALLOC PANEL_LDS(2)
 
 // Records of one column sit REC_STRIDE complex values (4 KiB) apart so that the
 // reads of a column spread over many memory channels instead of queueing on a few.
@@ -495,8 +502,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 // ---------------------------------------------------------------------------
 // 2. row interchanges outside the panel, and U12 = L11^{-1} A12
 //
-// Workgroups [0, nleft): SWAP_COLS columns each of [0, j), interchanges only.
-// Workgroups [nleft, ...): ST_CW columns each of [j + jb, ncol): interchanges, then
+// Workgroups [0, nleft): SWAP_COLS columns each of [0, lcols), interchanges only.
+// Workgroups [nleft, ...): ST_CW columns each of [c0, c1): interchanges, then
 // forward substitution with the unit lower L11 (in LDS) on rows j .. j + jb - 1,
 // lane = row, two columns per wavefront, the solved value of row c broadcast from
 // lane c by readlane.
@@ -505,8 +512,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #define ST_CW 8
 #define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB + 2 * LU_NB * ST_CW) * sizeof(cplx))
 
-__global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int ncol, const int32_t *swp,
-                                                        int nleft) {
+__global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int lcols, int c0, int c1,
+                                                        const int32_t *swp, int nleft) {
   extern __shared__ cplx sm[];
   const int np = swp[0];
   const int tid = threadIdx.x;
@@ -516,17 +523,17 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     const int cbase = blockIdx.x * SWAP_COLS;
     for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
       const int e = idx % np, col = cbase + idx / np;
-      if (col < j) buf[idx] = A[swp[2 + 2 * e] + (long)col * lda];
+      if (col < lcols) buf[idx] = A[swp[2 + 2 * e] + (long)col * lda];
     }
     __syncthreads();
     for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
       const int e = idx % np, col = cbase + idx / np;
-      if (col < j) A[swp[1 + 2 * e] + (long)col * lda] = buf[idx];
+      if (col < lcols) A[swp[1 + 2 * e] + (long)col * lda] = buf[idx];
     }
     return;
   }
-  const int c0 = j + jb + ((int)blockIdx.x - nleft) * ST_CW;
-  const int ncw = (ncol - c0 < ST_CW) ? ncol - c0 : ST_CW;
+  const int cw0 = c0 + ((int)blockIdx.x - nleft) * ST_CW;
+  const int ncw = (c1 - cw0 < ST_CW) ? c1 - cw0 : ST_CW;
   cplx *Ls = sm;                     // L11, column-major, ld LU_NB
   cplx *X = Ls + LU_NB * LU_NB;      // rows j .. j + jb - 1 of the columns, [ST_CW][LU_NB]
   cplx *buf = X + ST_CW * LU_NB;     // interchange sources, [2 LU_NB][ST_CW]
@@ -536,11 +543,11 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
   }
   for (int idx = tid; idx < jb * ST_CW; idx += 256) {
     const int r = idx % jb, cl = idx / jb;
-    if (cl < ncw) X[cl * LU_NB + r] = A[(j + r) + (long)(c0 + cl) * lda];
+    if (cl < ncw) X[cl * LU_NB + r] = A[(j + r) + (long)(cw0 + cl) * lda];
   }
   for (int idx = tid; idx < np * ST_CW; idx += 256) {
     const int e = idx % np, cl = idx / np;
-    if (cl < ncw) buf[idx] = A[swp[2 + 2 * e] + (long)(c0 + cl) * lda];
+    if (cl < ncw) buf[idx] = A[swp[2 + 2 * e] + (long)(cw0 + cl) * lda];
   }
   __syncthreads();
   for (int idx = tid; idx < np * ST_CW; idx += 256) {
@@ -548,7 +555,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     if (cl < ncw) {
       const int dst = swp[1 + 2 * e];
       if (dst < j + jb) X[cl * LU_NB + (dst - j)] = buf[idx];
-      else A[dst + (long)(c0 + cl) * lda] = buf[idx];
+      else A[dst + (long)(cw0 + cl) * lda] = buf[idx];
     }
   }
   __syncthreads();
@@ -564,8 +571,8 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     xb = csub(xb, cmul(l, yb));
   }
   if (row_ok) {
-    if (ca < ncw) A[(j + lane) + (long)(c0 + ca) * lda] = xa;
-    if (cb < ncw) A[(j + lane) + (long)(c0 + cb) * lda] = xb;
+    if (ca < ncw) A[(j + lane) + (long)(cw0 + ca) * lda] = xa;
+    if (cb < ncw) A[(j + lane) + (long)(cw0 + cb) * lda] = xb;
   }
 }
 
@@ -582,6 +589,9 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
   ok = ok && hipMalloc(&w->swp, sizeof(int32_t) * (size_t)w->npanel * SWP_STRIDE) == hipSuccess;
   ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * 8) == hipSuccess;
   ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&w->e_next, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&w->e_rest, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     bm_getrf_ws_destroy(w);
     return nullptr;
@@ -595,6 +605,12 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   (void)hipFree(w->swp);
   (void)hipFree(w->solve_sync);
   (void)hipFree(w->zbuf);
+  if (w->aux) {
+    (void)hipStreamSynchronize(w->aux);
+    (void)hipStreamDestroy(w->aux);
+  }
+  if (w->e_next) (void)hipEventDestroy(w->e_next);
+  if (w->e_rest) (void)hipEventDestroy(w->e_rest);
   delete w;
 }
 
@@ -629,7 +645,7 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
     for (int k = 0; k < 2; ++k)
       BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)PANEL_LDS(k + 1)));
+                                     (int)PANEL_LDS_ALLOC));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ST_LDS));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -672,21 +688,36 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     // kernel is bounded, so a launch whose workgroups cannot all become resident
     // ends with BM_E_DEVICE, not a hang.
     const int rpl = shape[3 * pi];
-    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS(rpl), s));
+    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
+    // Lookahead: the stream s applies the panel's interchanges and its update to the
+    // next panel's columns only; the auxiliary stream applies them to every other
+    // column while s factors the next panel.  s waits for that rest of panel k - 1
+    // before it touches the columns of panel k + 1 (which were part of it).
     const int nr = n - j - jb;
-    const int nleft = (j + SWAP_COLS - 1) / SWAP_COLS, nright = (nr + ST_CW - 1) / ST_CW;
-    if (nleft + nright > 0) {
-      hipLaunchKernelGGL(swap_trsm_kernel, dim3(nleft + nright), dim3(256), ST_LDS, s, A, ldal, j, jb, n,
-                         (const int32_t *)swp, nleft);
-      BM_HIP_TRY(hipGetLastError());
-    }
-    if (nr > 0) {
-      const int rc = (gemm32 ? bm_launch_zgemm32 : bm_launch_zgemm)(
-          s, nr, nr, jb, mone, A + (j + jb) + (long)j * lda, lda, A + j + (long)(j + jb) * lda, lda, one,
-          A + (j + jb) + (long)(j + jb) * lda, lda);
-      if (rc) return rc;
-    }
+    const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
+    if (pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+    auto update = [&](hipStream_t st, int lcols, int c0, int c1) -> int {
+      const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 - c0 + ST_CW - 1) / ST_CW;
+      if (nleft + nright > 0) {
+        hipLaunchKernelGGL(swap_trsm_kernel, dim3(nleft + nright), dim3(256), ST_LDS, st, A, ldal, j, jb, lcols, c0,
+                           c1, (const int32_t *)swp, nleft);
+        BM_HIP_TRY(hipGetLastError());
+      }
+      if (nr > 0 && c1 > c0)
+        return (gemm32 ? bm_launch_zgemm32 : bm_launch_zgemm)(st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda, lda,
+                                                                A + j + (long)c0 * lda, lda, one,
+                                                                A + jn + (long)c0 * lda, lda);
+      return BM_OK;
+    };
+    int rc = update(s, 0, jn, jn + jbn);
+    if (rc) return rc;
+    BM_HIP_TRY(hipEventRecord(w->e_next, s));
+    BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+    rc = update(w->aux, j, jn + jbn, n);
+    if (rc) return rc;
+    BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
   }
+  if (npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
   return BM_OK;
 }
 

@@ -69,6 +69,8 @@ struct bm_getrf_ws {
   int32_t *swp;        // per panel: count, then (dst, src) pairs
   int32_t *solve_sync; // ticket counter of the blocked triangular solves
   cplx *zbuf;          // solved blocks published by the triangular solves
+  hipStream_t aux;     // second stream: the trailing update of panel k runs beside panel k + 1
+  hipEvent_t e_next, e_rest;
 };
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {

@@ -4,10 +4,9 @@
 // products are accumulated in FP32 by v_mfma_f32_32x32x2f32, and the result is
 // widened back to FP64 for the update of C.
 //
-// Used in the mixed-precision factorisation: the Schur complement
-// U33 = -[M31 M32][M13; M23] of Theorem (thm:LU) and the trailing updates of the
-// blocked LU run here; FP64 iterative refinement against the FP64 blocks then
-// recovers the FP64 solution.
+// Used in the mixed-precision factorisation for the Schur complement
+// U33 = -[M31 M32][M13; M23] of Theorem (thm:LU); FP64 iterative refinement
+// against the FP64 blocks then recovers the FP64 solution.
 //
 // Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 128 x 128 tile of
 // C, two workgroups per CU (accumulators in VGPRs, no spills); each wave owns

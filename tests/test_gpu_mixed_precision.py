@@ -1,5 +1,5 @@
-"""Mixed precision: FP32 matrix-core Schur complement and trailing updates, FP64
-iterative refinement against the FP64 blocks of the mixed system.
+"""Mixed precision: FP32 matrix-core Schur complement, FP64 iterative refinement
+against the FP64 blocks of the mixed system.
 
 The refined solution must meet the same bar as the FP64 path: 1e-10 relative
 per right-hand side against the CPU oracle, with the refinement's own residual
