@@ -54,13 +54,18 @@
 // runs a panel workgroup (the chain wavefront would lose issue slots)
 #define PANEL_LDS_ALLOC PANEL_LDS(2)
 
-// Records of one column sit REC_STRIDE complex values (4 KiB) apart so that the
-// reads of a column spread over many memory channels instead of queueing on a few.
+// BM_REC_SPREAD = 1 places the records of one column REC_STRIDE complex values
+// (4 KiB) apart, spreading a column's reads over more memory channels; measured
+// no faster on MI355X than the packed layout, so the packed one is the default.
 #ifndef BM_REC_SPREAD
 #define BM_REC_SPREAD 0
 #endif
 #define REC_STRIDE 256
+#if BM_REC_SPREAD
 #define SLOT_ELEMS ((size_t)LU_NB * (PANEL_PMAX + 1) * REC_STRIDE)  // complex values per slot buffer
+#else
+#define SLOT_ELEMS ((size_t)LU_NB * (PANEL_PMAX * (LU_NB + 1) + LU_NB))
+#endif
 
 // 16-byte agent-coherent loads and stores of the exchange records: buffer
 // instructions with the sc1 cache-policy bit (agent scope on gfx94x / gfx950).
