@@ -147,6 +147,97 @@ def cpu_baseline(w):
                       f"dense LU, {len(w.theta_inc)}-RHS solve, far field) on the host; {t:.1f} s"}
 
 
+def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
+    """The served contour sweep (256 requests on 8 circles |k - c| = 0.5, stars
+    with N in {512, ..., 4096}, 16 probing right-hand sides each) through the
+    request server: closed-loop capacity (all requests queued at once, with and
+    without graph replay for small N) and open-loop latency under Poisson
+    arrivals at `rate` requests per second."""
+    import numpy as np
+    import torch
+    from paper_2512_14193_amd import binding as B
+    from paper_2512_14193_amd import inputs as I
+
+    sw = I.serving_workload(rate=rate)
+    dev = torch.device("cuda")
+    geos = {}
+    for c, n in enumerate(sw.sizes):
+        bnd = I.star(int(n))
+        geos[c] = [torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+                   for a in (bnd.x, bnd.dx, bnd.ddx, bnd.d3x)]
+    Bs = [B.fortran(torch.as_tensor(I.probing_rhs(3 * r.n_nodes, sw.n_rhs, r.rhs_seed)).to(dev))
+          for r in sw.requests]
+    Xs = [B.fortran_empty(3 * r.n_nodes, sw.n_rhs) for r in sw.requests]
+    torch.cuda.synchronize()
+
+    def run(server, open_loop):
+        tickets = []
+        t0 = time.perf_counter()
+        for r in sw.requests:
+            if open_loop:
+                dt = t0 + r.arrival - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            tickets.append(server.submit(geos[r.contour], r.physics, Bs[r.index], Xs[r.index]))
+        res = [server.wait(t) for t in tickets]
+        bad = [x["status"] for x in res if x["status"] != 0]
+        if bad:
+            raise RuntimeError(f"served requests failed: {bad[:5]}")
+        return res
+
+    def warm(server, lanes=1):
+        """Create the handles (on every lane) and capture the graphs before timing."""
+        per_n = {}
+        for r in sw.requests:
+            per_n.setdefault(r.n_nodes, [])
+            if len(per_n[r.n_nodes]) < lanes:
+                per_n[r.n_nodes].append(r)
+        for rs in per_n.values():
+            for t in [server.submit(geos[r.contour], r.physics, Bs[r.index], Xs[r.index]) for r in rs]:
+                server.wait(t)
+
+    def summary(res):
+        lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+        span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+        by_n = {}
+        for x in res:
+            by_n.setdefault(x["n"], []).append(x)
+        return {"throughput_req_per_s": len(res) / span, "makespan_s": span,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                               "p99": float(np.percentile(lat, 99)), "max": float(lat.max()),
+                               "mean": float(lat.mean())},
+                "by_n": {str(n): {"requests": len(v),
+                                  "device_ms_mean": float(np.mean([x["device_ms"] for x in v])),
+                                  "latency_ms_p50": float(np.percentile([1e3 * (x["t_done"] - x["t_submit"])
+                                                                         for x in v], 50))}
+                         for n, v in sorted(by_n.items())}}
+
+    out = {"workload": "contour sweep: 8 circles |k-c|=0.5 (c ~ U[2,20]) x 32 nodes = 256 requests, "
+                       "star r=1+0.3cos5t with N ~ {512,1024,2048,4096}, k1 = 1.5 k0, 16 probing RHS, "
+                       "Poisson arrivals",
+           "sizes_per_contour": [int(n) for n in sw.sizes], "requests": len(sw.requests), "nrhs": sw.n_rhs,
+           "rate_req_per_s": rate, "max_inflight_per_lane": max_inflight, "graph_max_n": graph_max_n,
+           "lanes": lanes, "concurrent_max_n": concurrent_max_n}
+    srv = B.Server(max_inflight=max_inflight, graph_max_n=0, lanes=1)
+    warm(srv)
+    out["closed_loop_one_lane_eager"] = summary(run(srv, False))
+    srv.close()
+    srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
+                   concurrent_max_n=concurrent_max_n)
+    warm(srv, lanes)
+    closed = run(srv, False)
+    out["closed_loop"] = summary(closed)
+    out["capacity_req_per_s"] = out["closed_loop"]["throughput_req_per_s"]
+    sample = [0, 1, 2, 3, len(Xs) - 1]
+    before = [Xs[i].clone() for i in sample]
+    out["open_loop"] = summary(run(srv, True))
+    torch.cuda.synchronize()
+    out["bitwise_repeatable"] = all(torch.equal(Xs[i], b) for i, b in zip(sample, before))
+    out["server_stats"] = srv.stats()
+    srv.close()
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -171,6 +262,12 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--mixed-tol", type=float, default=1e-10,
                     help="relative residual target of the refinement in the mixed-precision comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the served contour sweep")
+    ap.add_argument("--serving-rate", type=float, default=50.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serving-graph-max-n", type=int, default=1024)
+    ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-lanes", type=int, default=4)
+    ap.add_argument("--serving-concurrent-max-n", type=int, default=2048)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
@@ -233,6 +330,9 @@ def main():
                              "paper_context": "1.38-1.44x on 2x EPYC 9654 (CPU, zeta-corrected quadrature, disk)"}
     if not args.no_mixed:
         rec["mixed_precision"] = mixed_precision_section(args.mixed_workload, args.mixed_steps, 1, args.mixed_tol)
+    if not args.no_serving:
+        rec["serving"] = serving_section(args.serving_rate, args.serving_graph_max_n, args.serving_inflight,
+                                         args.serving_lanes, args.serving_concurrent_max_n)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

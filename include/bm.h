@@ -63,8 +63,13 @@ enum bm_status {
   BM_E_STATE = -4,   /* call out of order (e.g. bm_solve before bm_block_lu)   */
   BM_E_DEVICE = -5,  /* a kernel reported an internal error (e.g. a bounded
                         wait expired); results of the call are invalid         */
-  BM_E_NOCONV = -6   /* mixed precision: the refinement of bm_solve stopped at
+  BM_E_NOCONV = -6,  /* mixed precision: the refinement of bm_solve stopped at
                         max_iter above the tolerance; X holds the last iterate */
+  BM_E_BUDGET = -7,  /* request server: one problem of the request's size needs
+                        more device memory than the server's budget            */
+  BM_E_CANCELED = -8,/* request server: the request was canceled before it started */
+  BM_E_TIMEOUT = -9  /* request server: bm_server_wait timed out; the request is
+                        still pending and can be waited for again               */
 };
 
 enum bm_precision {
@@ -211,6 +216,122 @@ int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, 
 int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha,
                  const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
                  void *C, int64_t ldc);
+
+/* Device bytes that bm_create(n, formulation, ...) allocates (*bytes, host).
+ * Errors: BM_E_ARG (as bm_create). */
+int bm_problem_bytes(int32_t n, int32_t formulation, int64_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Request server for contour solves.
+ *
+ * A contour-integral eigensolver (the Sakurai-Sugiura projection of Sec. 5.3)
+ * or a frequency sweep issues many independent solves A(k_j) X_j = B_j of the
+ * mixed system (eq. dis_mixedBM) at wavenumbers k_j on a closed curve, each
+ * with a block of right-hand sides (Corollary lem:for_ssm_RHS).  The server
+ * takes such requests from any host thread and runs each one as
+ * bm_assemble -> bm_block_lu -> bm_solve on device-resident problem handles:
+ *   - requests start in submission order as soon as they are admitted
+ *     (continuous admission: no request waits for a batch to fill); up to
+ *     max_inflight requests per lane are enqueued on the device ahead of
+ *     completion, so the device does not idle between requests;
+ *   - requests with N <= concurrent_max_n run concurrently on `lanes` streams
+ *     (their factorisations are bound by the latency of the pivot chain and
+ *     leave most CUs idle); a larger request runs alone: on the device it
+ *     waits for the work enqueued on every other lane, and later requests
+ *     wait for it;
+ *   - handles are kept per (lane, N, reuse_key) and reused by later requests;
+ *     the device bytes they hold never exceed hbm_budget_bytes: a request
+ *     whose handle is missing evicts least-recently-used handles that have no
+ *     pending work, waits for completions if that is not enough, and is
+ *     rejected at submission (BM_E_BUDGET) if one handle of its size alone
+ *     exceeds the budget;
+ *   - requests with the same nonzero reuse_key, N and parameters reuse the
+ *     factors of the previous one (the key asserts that the geometry is the
+ *     same): only bm_solve runs;
+ *   - for N <= graph_max_n the factorisation and solve of a request replay a
+ *     HIP graph captured once per handle (the host cost of a small request is
+ *     its kernel launches); results are bitwise identical to the eager path.
+ * Concurrency is limited to small problems because the panel factorisation
+ * needs all of its workgroups resident at once: the panels of all lanes fit
+ * beside each other (lanes * ceil(concurrent_max_n / 64) <= CUs / 2) and the
+ * kernels of small requests are short, whereas a large request's Schur
+ * complement occupies every CU for tens of milliseconds.  A request's result
+ * does not depend on the other requests (bitwise).  Mixed formulation, FP64
+ * precision.  The server is thread-safe. */
+typedef struct bm_server bm_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device bytes the handles may hold; <= 0: 90% of the
+                                device memory free at creation                      */
+  int32_t max_inflight;      /* requests per lane enqueued on the device ahead of
+                                completion; <= 0: 4                                  */
+  int32_t graph_max_n;       /* N up to which requests replay a captured HIP graph
+                                (0: never)                                           */
+  int32_t lanes;             /* concurrent streams, 1..16; 0: 4                    */
+  int32_t concurrent_max_n;  /* N up to which requests share the device; 0: 1024;
+                                with lanes > 1 it must be <= 2048 and
+                                lanes * ceil(concurrent_max_n / 64) <= CUs / 2      */
+} bm_server_config;
+
+/* One request.  Device arrays: the geometry (as bm_assemble), B (3N x nrhs,
+ * ldb >= 3N) and X (3N x nrhs, ldx >= 3N, not aliasing B).  They must hold
+ * their data when bm_server_submit is called and stay allocated until
+ * bm_server_wait has returned the request's result; X is complete then. */
+typedef struct {
+  int32_t n;                 /* nodes N (as bm_create)                           */
+  int32_t nrhs;              /* right-hand sides, >= 1                            */
+  bm_geometry geometry;
+  bm_params params;          /* as bm_assemble                                    */
+  const void *B;
+  int64_t ldb;
+  void *X;
+  int64_t ldx;
+  uint64_t reuse_key;        /* 0, or a caller key naming the geometry            */
+} bm_request;
+
+typedef struct {
+  int32_t status;            /* BM_OK, a negative bm_status, or info > 0 (exactly
+                                zero pivot in that 1-based column of U33)         */
+  int32_t reused_factors;    /* 1 if the factors of an earlier request were reused */
+  int32_t graph;             /* 1 if factorisation and solve replayed a HIP graph  */
+  int32_t n;
+  double t_submit;           /* host steady (monotonic) clock, seconds: submission */
+  double t_start;            /* ... the request's work was enqueued on the device */
+  double t_done;             /* ... the server saw the request's work complete    */
+  double device_ms;          /* device time of the request's work (HIP events)    */
+} bm_request_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected, canceled;
+  int64_t handles_created, evictions, factor_reuses, graph_launches;
+  int64_t handles_live, bytes_live, bytes_peak, budget;
+} bm_server_counters;
+
+/* Create a server on the current HIP device (cfg may be NULL for defaults).
+ * Errors: BM_E_ARG (negative fields, lanes > 16, the lane bound above),
+ * BM_E_HIP, BM_E_NOMEM. */
+int bm_server_create(const bm_server_config *cfg, bm_server **out);
+
+/* Queue a request (the struct is copied); *ticket (host) names it.  Checked at
+ * once: BM_E_ARG (as bm_create / bm_assemble / bm_solve), BM_E_BUDGET. */
+int bm_server_submit(bm_server *s, const bm_request *r, uint64_t *ticket);
+
+/* Wait up to timeout_s seconds (< 0: no limit) for a request and store its
+ * result (host).  Returns BM_OK once the result is stored (the request's own
+ * status is res->status) and forgets the ticket; BM_E_TIMEOUT if it is still
+ * pending; BM_E_ARG for an unknown ticket. */
+int bm_server_wait(bm_server *s, uint64_t ticket, double timeout_s, bm_request_result *res);
+
+/* Cancel a request that has not started: its result gets BM_E_CANCELED.
+ * BM_E_STATE if it has started or finished, BM_E_ARG for an unknown ticket. */
+int bm_server_cancel(bm_server *s, uint64_t ticket);
+
+/* Counters since creation (host). */
+int bm_server_stats(bm_server *s, bm_server_counters *st);
+
+/* Cancel the requests that have not started, wait for the others, release
+ * every handle and the server.  Results not yet waited for are discarded. */
+void bm_server_destroy(bm_server *s);
 
 /* Text for a status code. */
 const char *bm_strerror(int code);

@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "libbm_mi355x.so")
 
 BM_MIXED, BM_ORDINARY = 0, 1
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
+BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT = -7, -8, -9
 BM_PREC_FP64, BM_PREC_MIXED = 0, 1
 BM_MAX_NRHS = 32
 
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
-            "bm_zgemm_f32"]
+            "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
+            "bm_server_cancel", "bm_server_stats", "bm_server_destroy"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -37,6 +39,29 @@ class BMParams(ctypes.Structure):
                 ("k1_re", ctypes.c_double), ("k1_im", ctypes.c_double),
                 ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
                 ("beta_re", ctypes.c_double), ("beta_im", ctypes.c_double)]
+
+
+class BMServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("graph_max_n", ctypes.c_int32), ("lanes", ctypes.c_int32), ("concurrent_max_n", ctypes.c_int32)]
+
+
+class BMRequest(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("geometry", BMGeometry), ("params", BMParams),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("reuse_key", ctypes.c_uint64)]
+
+
+class BMRequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reused_factors", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
+class BMServerCounters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "completed", "failed", "rejected", "canceled", "handles_created", "evictions",
+        "factor_reuses", "graph_launches", "handles_live", "bytes_live", "bytes_peak", "budget")]
 
 
 class BMError(RuntimeError):
@@ -75,6 +100,14 @@ def lib():
         L.bm_zgemm_f32.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_set_precision.argtypes = [vp, i32, ctypes.c_double, i32]
         L.bm_refine_stats.argtypes = [vp, ctypes.POINTER(i32), dp]
+        L.bm_problem_bytes.argtypes = [i32, i32, ctypes.POINTER(i64)]
+        L.bm_server_create.argtypes = [ctypes.POINTER(BMServerConfig), ctypes.POINTER(vp)]
+        L.bm_server_submit.argtypes = [vp, ctypes.POINTER(BMRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.bm_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(BMRequestResult)]
+        L.bm_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.bm_server_stats.argtypes = [vp, ctypes.POINTER(BMServerCounters)]
+        L.bm_server_destroy.argtypes = [vp]
+        L.bm_server_destroy.restype = None
         L.bm_strerror.argtypes = [ctypes.c_int]
         L.bm_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -233,6 +266,83 @@ class Problem:
         cnt = (ctypes.c_int32 * 5)()
         check(lib().bm_phase_times(self._h, ms, cnt, 5), "bm_phase_times")
         return list(ms), list(cnt)
+
+
+def _params(physics) -> BMParams:
+    return BMParams(physics.k0.real, physics.k0.imag, physics.k1.real, physics.k1.imag,
+                    physics.eps0, physics.eps1, physics.beta.real, physics.beta.imag)
+
+
+def problem_bytes(n_nodes: int, formulation: str = "mixed") -> int:
+    """Device bytes of one problem handle (bm_problem_bytes)."""
+    b = ctypes.c_int64(0)
+    check(lib().bm_problem_bytes(int(n_nodes), BM_MIXED if formulation == "mixed" else BM_ORDINARY,
+                                 ctypes.byref(b)), "bm_problem_bytes")
+    return b.value
+
+
+class Server:
+    """Request server for contour solves (bm_server_*): requests run on
+    device-resident handles in submission order on a stream the server owns.
+
+    submit() takes device tensors that must already hold their data (synchronise
+    the producing stream first) and keeps references to them until wait()
+    returns the request's result."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_inflight: int = 4, graph_max_n: int = 0, lanes: int = 4,
+                 concurrent_max_n: int = 1024):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs on the GPU only")
+        cfg = BMServerConfig(int(hbm_budget_bytes), int(max_inflight), int(graph_max_n), int(lanes),
+                             int(concurrent_max_n))
+        h = ctypes.c_void_p()
+        check(lib().bm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bm_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bm_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, geometry, physics, B: torch.Tensor, X: torch.Tensor, reuse_key: int = 0) -> int:
+        """Queue a solve of the mixed system; geometry: four contiguous (N, 2)
+        float64 CUDA tensors; B, X: column-major complex128 (3N, nrhs).  Returns
+        the ticket."""
+        n = int(geometry[0].shape[0])
+        for t in geometry:
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == (n, 2)):
+                raise ValueError("geometry must be contiguous (N, 2) float64 CUDA tensors")
+        g = BMGeometry(*[t.data_ptr() for t in geometry])
+        r = BMRequest(n, int(B.shape[1]), g, _params(physics), _ptr(B), _ld(B), _ptr(X), _ld(X), int(reuse_key))
+        ticket = ctypes.c_uint64(0)
+        check(lib().bm_server_submit(self._h, ctypes.byref(r), ctypes.byref(ticket)), "bm_server_submit")
+        self._keep[ticket.value] = (geometry, B, X)
+        return ticket.value
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        """Result of a request as a dict (status, reused_factors, graph, n,
+        t_submit, t_start, t_done, device_ms); raises BMError(BM_E_TIMEOUT)."""
+        res = BMRequestResult()
+        check(lib().bm_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(res)),
+              "bm_server_wait")
+        self._keep.pop(ticket, None)
+        return {name: getattr(res, name) for name, _ in BMRequestResult._fields_}
+
+    def cancel(self, ticket: int):
+        check(lib().bm_server_cancel(self._h, ctypes.c_uint64(ticket)), "bm_server_cancel")
+
+    def stats(self) -> dict:
+        c = BMServerCounters()
+        check(lib().bm_server_stats(self._h, ctypes.byref(c)), "bm_server_stats")
+        return {name: getattr(c, name) for name, _ in BMServerCounters._fields_}
 
 
 def zgemm(alpha, A, B, beta, C, stream=None):

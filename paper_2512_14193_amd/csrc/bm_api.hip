@@ -17,6 +17,9 @@ const char *bm_strerror(int code) {
     case BM_E_STATE: return "call out of order";
     case BM_E_DEVICE: return "device-side error (bounded wait expired)";
     case BM_E_NOCONV: return "iterative refinement did not reach the tolerance";
+    case BM_E_BUDGET: return "request exceeds the server's device-memory budget";
+    case BM_E_CANCELED: return "request canceled";
+    case BM_E_TIMEOUT: return "wait timed out (request still pending)";
     default: return code > 0 ? "singular factor (info > 0)" : "unknown status";
   }
 }
@@ -134,13 +137,46 @@ static void phase_end(bm_problem *p, int ph) {
   ++p->ev_count[ph];
 }
 
-int bm_assemble(bm_problem *p, const bm_geometry *g, const bm_params *prm) {
-  if (!p || !g || !prm || !g->x || !g->dx || !g->ddx || !g->d3x) return BM_E_ARG;
-  if (!(prm->eps0 > 0.0) || !(prm->eps1 > 0.0)) return BM_E_ARG;
+}  // extern "C"
+
+int bm_check_params(const bm_params *prm) {
+  if (!prm) return BM_E_ARG;
+  if (!(prm->eps0 > 0.0) || !(prm->eps1 > 0.0) || !isfinite(prm->eps0) || !isfinite(prm->eps1)) return BM_E_ARG;
   if (prm->beta_im == 0.0 || !isfinite(prm->beta_re) || !isfinite(prm->beta_im)) return BM_E_ARG;
   const double ks[2][2] = {{prm->k0_re, prm->k0_im}, {prm->k1_re, prm->k1_im}};
   for (int w = 0; w < 2; ++w)
-    if (!(ks[w][0] > 0.0) || !(fabs(ks[w][1]) <= 0.5 * ks[w][0])) return BM_E_ARG;
+    if (!(ks[w][0] > 0.0) || !isfinite(ks[w][0]) || !(fabs(ks[w][1]) <= 0.5 * ks[w][0])) return BM_E_ARG;
+  return BM_OK;
+}
+
+extern "C" {
+
+int bm_problem_bytes(int32_t n, int32_t formulation, int64_t *bytes) {
+  if (!bytes) return BM_E_ARG;
+  *bytes = 0;
+  if (n < 8 || n > 65536 || (n % 2) != 0) return BM_E_ARG;
+  if (formulation != BM_MIXED && formulation != BM_ORDINARY) return BM_E_ARG;
+  // the allocations of bm_create, in the same order
+  const size_t N = (size_t)n, nf = (formulation == BM_MIXED) ? N : 2 * N;
+  const size_t nblk = (nf + BM_DIAG_NB - 1) / BM_DIAG_NB, c = sizeof(cplx);
+  size_t b = sizeof(double) * 8 * N + sizeof(double) * 4 * N;
+  if (formulation == BM_MIXED) b += 2 * (c * 2 * N * N);
+  b += c * nf * nf + sizeof(int32_t) * nf + c * nblk * 2 * BM_DIAG_NB * BM_DIAG_NB + sizeof(int32_t) * nf;
+  b += c * nf * BM_MAX_NRHS;
+  if (formulation == BM_MIXED) {
+    const size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
+    b += c * (wp > w2 ? wp : w2);
+  }
+  b += sizeof(int32_t) * 2;
+  if (formulation == BM_MIXED) b += 2 * (c * 3 * N * BM_MAX_NRHS) + sizeof(double) * 2 * BM_MAX_NRHS;
+  b += bm_getrf_ws_bytes((int)nf);
+  *bytes = (int64_t)b;
+  return BM_OK;
+}
+
+int bm_assemble(bm_problem *p, const bm_geometry *g, const bm_params *prm) {
+  if (!p || !g || !prm || !g->x || !g->dx || !g->ddx || !g->d3x) return BM_E_ARG;
+  if (int rc = bm_check_params(prm)) return rc;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   p->phys.k0 = cmk(prm->k0_re, prm->k0_im);
   p->phys.k1 = cmk(prm->k1_re, prm->k1_im);

@@ -629,6 +629,22 @@ static const panel_fn panel_fns[2] = {panel_kernel<1>, panel_kernel<2>};
 
 static int panel_attr_done[64];
 
+// Fill of 8-byte words (the error flags and the exchange sentinels).  A kernel
+// rather than hipMemsetAsync so that the factorisation can be captured in a HIP
+// graph and replayed.
+__global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+int bm_fill_u64(hipStream_t s, void *p, size_t n, unsigned long long v) {
+  if (n == 0) return BM_OK;
+  size_t nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)nb), dim3(256), 0, s, (unsigned long long *)p, n, v);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
 // rows per lane of the chain wavefront (1: 64, 2: 128 rows per workgroup) and the
 // workgroup count of a panel of R rows: 64 rows per workgroup while that keeps
 // P <= PANEL_RPL1_PMAX, else 128
@@ -642,9 +658,15 @@ static bool panel_shape(int R, int ncu, int *rpl, int *P_out) {
   return true;
 }
 
-int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
-                 int gemm32) {
-  if (!w || w->n < n) return BM_E_ARG;
+size_t bm_getrf_ws_bytes(int n) {
+  const size_t npanel = (size_t)(n + LU_NB - 1) / LU_NB, nblk = (size_t)(n + BM_DIAG_NB - 1) / BM_DIAG_NB;
+  return sizeof(cplx) * 2 * SLOT_ELEMS + sizeof(int32_t) * npanel * SWP_STRIDE + sizeof(int32_t) * 8 +
+         sizeof(cplx) * nblk * BM_DIAG_NB * BM_MAX_NRHS;
+}
+
+// Dynamic-LDS limits of the factorisation kernels on the current device (once per
+// device; called before any stream capture of the factorisation).
+int bm_getrf_prepare() {
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
@@ -657,9 +679,18 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
                                    (int)TI_LDS));
     panel_attr_done[dev] = 1;
   }
+  return BM_OK;
+}
+
+int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                 int gemm32) {
+  if (!w || w->n < n) return BM_E_ARG;
+  if (int rc0 = bm_getrf_prepare()) return rc0;
+  int dev = 0;
+  BM_HIP_TRY(hipGetDevice(&dev));
   int ncu = 0;
   BM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  BM_HIP_TRY(hipMemsetAsync(dev_err, 0, 2 * sizeof(int32_t), s));
+  if (int rc0 = bm_fill_u64(s, dev_err, 1, 0ull)) return rc0;  // [0] error, [1] info
   const int npanel = (n + LU_NB - 1) / LU_NB;
   int shape[3 * 1024];  // rows per lane, P per panel
   if (npanel > 1024) return BM_E_ARG;
@@ -670,7 +701,7 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   if (npanel > 0) {  // the first panel's words of slot buffer 0; each panel refills the next one's
     const int jb0 = (n < LU_NB) ? n : LU_NB;
     const size_t cstr0 = BM_REC_SPREAD ? (size_t)(shape[1] + 1) * REC_STRIDE : (size_t)shape[1] * (jb0 + 1) + jb0;
-    BM_HIP_TRY(hipMemsetAsync(w->slots, 0xFF, sizeof(cplx) * (size_t)jb0 * cstr0, s));
+    if (int rc0 = bm_fill_u64(s, w->slots, 2 * (size_t)jb0 * cstr0, ~0ull)) return rc0;
   }
   const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {

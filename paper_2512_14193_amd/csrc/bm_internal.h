@@ -169,6 +169,13 @@ int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx
 // LU
 bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);
+size_t bm_getrf_ws_bytes(int n);  // device bytes bm_getrf_ws_create(n) allocates
+int bm_getrf_prepare();           // kernel attributes on the current device (outside any capture)
+// parameter checks of bm_assemble (BM_OK or BM_E_ARG)
+int bm_check_params(const bm_params *prm);
+// Fill n 8-byte words at p with v on stream s (a kernel, so that the sequence stays
+// capturable in a HIP graph).
+int bm_fill_u64(hipStream_t s, void *p, size_t n, unsigned long long v);
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                  bm_getrf_ws *w, int gemm32);
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);

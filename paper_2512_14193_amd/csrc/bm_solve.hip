@@ -297,8 +297,9 @@ int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
   if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
   const int nblk = (n + TS_NB - 1) / TS_NB;
-  BM_HIP_TRY(hipMemsetAsync(w->solve_sync, 0, sizeof(int32_t) * 8, s));
-  BM_HIP_TRY(hipMemsetAsync(w->zbuf, 0xFF, sizeof(cplx) * (size_t)nblk * TS_NB * BM_MAX_NRHS, s));
+  int rc = bm_fill_u64(s, w->solve_sync, 4, 0ull);  // 8 int32 ticket words
+  if (!rc) rc = bm_fill_u64(s, w->zbuf, 2 * (size_t)nblk * TS_NB * BM_MAX_NRHS, ~0ull);
+  if (rc) return rc;
   if (lower)
     hipLaunchKernelGGL(trsv_kernel<true>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
                        w->solve_sync, w->zbuf, dev_err);

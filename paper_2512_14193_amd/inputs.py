@@ -159,3 +159,57 @@ def workload(name: str) -> Workload:
         return Workload(name, star(8192), Physics.from_wavenumbers(40.0, 80.0),
                         plane_wave_angles(8, SEED_BASE + 2), observation_angles())
     raise KeyError(name)
+
+
+@dataclasses.dataclass
+class ServedRequest:
+    """One solve of a served contour sweep."""
+    index: int          # position in arrival order
+    contour: int
+    node: int           # quadrature node on the contour
+    n_nodes: int        # boundary nodes N of the contour's star
+    physics: Physics
+    rhs_seed: int       # seed of its probing right-hand sides
+    arrival: float      # seconds after the start of the sweep
+
+
+@dataclasses.dataclass
+class ServingWorkload:
+    centers: np.ndarray     # contour centres c (real)
+    sizes: np.ndarray       # boundary nodes N per contour
+    radius: float
+    nodes_per_contour: int
+    n_rhs: int
+    rate: float             # Poisson arrival rate, requests per second
+    requests: list
+
+
+def contour_nodes(center: complex, radius: float, n_nodes: int) -> np.ndarray:
+    """Equispaced nodes k_j = c + r exp(i theta_j), theta_j = 2 pi (j + 1/2) / n
+    (the trapezoid nodes of a circular contour)."""
+    th = 2.0 * math.pi * (np.arange(n_nodes) + 0.5) / n_nodes
+    return complex(center) + radius * np.exp(1j * th)
+
+
+def serving_workload(n_contours: int = 8, nodes_per_contour: int = 32, radius: float = 0.5,
+                     sizes=(512, 1024, 2048, 4096), index: float = 1.5, n_rhs: int = 16,
+                     rate: float = 50.0, seed: int = SEED_BASE + 3) -> ServingWorkload:
+    """A served contour sweep: n_contours circles |k - c| = radius with c uniform
+    in [2, 20], each on a star boundary r = 1 + 0.3 cos 5t with N drawn from
+    `sizes`; every quadrature node of every circle is one request (interior
+    wavenumber k1 = index * k0, beta = i / k0) with n_rhs complex Gaussian probing
+    right-hand sides.  Requests arrive in a seeded random order of (contour, node)
+    with exponential inter-arrival times of mean 1 / rate (a Poisson process)."""
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(2.0, 20.0, n_contours)
+    ns = rng.choice(np.asarray(sizes), n_contours)
+    order = rng.permutation(n_contours * nodes_per_contour)
+    gaps = rng.exponential(1.0 / rate, order.size)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i, flat in enumerate(order):
+        c, j = divmod(int(flat), nodes_per_contour)
+        k0 = contour_nodes(centers[c], radius, nodes_per_contour)[j]
+        reqs.append(ServedRequest(i, c, j, int(ns[c]), Physics.from_wavenumbers(k0, index * k0),
+                                  seed + 1000 + int(flat), float(arrivals[i])))
+    return ServingWorkload(centers, ns, radius, nodes_per_contour, n_rhs, rate, reqs)

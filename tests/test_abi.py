@@ -31,3 +31,46 @@ def test_strerror_without_device():
     assert lib.bm_strerror(0) == b"ok"
     assert lib.bm_strerror(-1) == b"invalid argument"
     assert b"singular" in lib.bm_strerror(3)
+
+
+def test_problem_bytes_without_device():
+    # host arithmetic only: the sum of bm_create's allocations
+    b = {n: binding.problem_bytes(n) for n in (512, 1024, 2048, 4096)}
+    for n, v in b.items():
+        # blocks and U33 (80 N^2 bytes), O(N) vectors, the exchange buffers (34 MB)
+        # and the split-K partials of the solve (at most 1024 x 256 rows x 32 columns)
+        assert 80 * n * n < v < 80 * n * n + 4096 * n + 200 * 2 ** 20, (n, v)
+    assert binding.problem_bytes(512, "ordinary") < b[512]
+    lib = binding.lib()
+    out = ctypes.c_int64(0)
+    for n in (7, 9, 0, 65538):
+        assert lib.bm_problem_bytes(n, 0, ctypes.byref(out)) == binding.BM_E_ARG
+    assert lib.bm_strerror(binding.BM_E_BUDGET).startswith(b"request exceeds")
+    assert lib.bm_strerror(binding.BM_E_CANCELED) == b"request canceled"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the C layout (sizes and field
+    offsets from a C program compiled against include/bm.h)."""
+    import subprocess
+    structs = {"bm_geometry": binding.BMGeometry, "bm_params": binding.BMParams,
+               "bm_server_config": binding.BMServerConfig, "bm_request": binding.BMRequest,
+               "bm_request_result": binding.BMRequestResult, "bm_server_counters": binding.BMServerCounters}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

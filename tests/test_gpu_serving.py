@@ -1,0 +1,209 @@
+"""Request server (bm_server_*): contour solves of the mixed system served from
+device-resident handles.
+
+A request's result must not depend on what else the server runs: the same
+request run alone, in a mix of other sizes and wavenumbers, through a replayed
+HIP graph, after evictions, or through the plain bm_create/bm_assemble/
+bm_block_lu/bm_solve path gives bitwise the same X.  Parity with the oracle is
+checked to 1e-10 per right-hand side (the bar of the direct path).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2512_14193_amd import binding as B
+from paper_2512_14193_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def geo(bnd):
+    return [torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+            for a in (bnd.x, bnd.dx, bnd.ddx, bnd.d3x)]
+
+
+def rel_cols(x, y):
+    return np.max(np.linalg.norm(x - y, axis=0) / np.linalg.norm(y, axis=0))
+
+
+class Req:
+    def __init__(self, n, k0, nrhs, seed, key=0):
+        self.bnd = I.star(n)
+        self.ph = I.Physics.from_wavenumbers(k0, 1.5 * k0)
+        self.n = n
+        self.geo = geo(self.bnd)
+        self.Bh = I.probing_rhs(3 * n, nrhs, seed)
+        self.B = B.fortran(torch.as_tensor(self.Bh).cuda())
+        self.key = key
+
+    def new_x(self):
+        return B.fortran_empty(3 * self.n, self.Bh.shape[1])
+
+
+def direct(r):
+    P = B.Problem(r.n, "mixed")
+    P.assemble_device(r.geo, r.ph)
+    P.block_lu(sync=False)
+    X = P.solve(r.B)
+    P.sync()
+    torch.cuda.synchronize()
+    return X.clone()
+
+
+def serve(server, reqs):
+    torch.cuda.synchronize()  # inputs complete before submission
+    out = []
+    for r in reqs:
+        X = r.new_x()
+        out.append((server.submit(r.geo, r.ph, r.B, X, r.key), X))
+    res = [(server.wait(t), X) for t, X in out]
+    torch.cuda.synchronize()
+    return res
+
+
+def contour_mix():
+    """Three stars, wavenumbers on three circles |k - c| = 0.5, ragged RHS counts."""
+    reqs = []
+    for i, (n, c) in enumerate([(128, 4.0), (192, 6.0), (256, 8.0)]):
+        for j, k in enumerate(I.contour_nodes(c, 0.5, 4)):
+            reqs.append(Req(n, k, 5 + (i + j) % 3, 100 * i + j))
+    order = np.random.default_rng(7).permutation(len(reqs))
+    return [reqs[i] for i in order]
+
+
+@pytest.mark.parametrize("graph_max_n,lanes,concurrent_max_n", [(0, 1, 1024), (256, 4, 1024), (0, 4, 1024),
+                                                                 (256, 3, 128)])
+def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n):
+    """lanes > 1: requests with N <= concurrent_max_n run concurrently, larger
+    ones (N = 192, 256 when concurrent_max_n = 128) are fenced to run alone."""
+    reqs = contour_mix()
+    ref = [direct(r) for r in reqs]
+    alone = []
+    for r in reqs:
+        s = B.Server(max_inflight=2, graph_max_n=graph_max_n, lanes=1)
+        (res, X), = serve(s, [r])
+        assert res["status"] == 0
+        alone.append(X)
+        s.close()
+    s = B.Server(max_inflight=3, graph_max_n=graph_max_n, lanes=lanes, concurrent_max_n=concurrent_max_n)
+    mix = serve(s, reqs)
+    st = s.stats()
+    s.close()
+    for r, Xr, Xa, (res, Xm) in zip(reqs, ref, alone, mix):
+        assert res["status"] == 0 and res["n"] == r.n
+        assert res["t_submit"] <= res["t_start"] <= res["t_done"] and res["device_ms"] > 0
+        assert torch.equal(Xa, Xr), "alone != direct"
+        assert torch.equal(Xm, Xr), "in the mix != direct"
+        assert res["graph"] == (1 if r.n <= graph_max_n else 0)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert 3 <= st["handles_created"] <= 3 * lanes and (lanes > 1 or st["handles_created"] == 3)
+    assert st["graph_launches"] == sum(r.n <= graph_max_n for r in reqs)
+
+
+def test_served_solutions_vs_oracle():
+    reqs = [Req(128, 4.0 + 0.5j, 4, 1), Req(160, 6.0 - 0.5j, 3, 2), Req(128, 3.5, 2, 3)]
+    s = B.Server(graph_max_n=128)
+    out = serve(s, reqs)
+    s.close()
+    for r, (res, X) in zip(reqs, out):
+        assert res["status"] == 0
+        Xo = O.zgesv(O.build_mixed(r.bnd, r.ph), r.Bh)
+        assert rel_cols(X.cpu().numpy(), Xo) < 1e-10
+
+
+def test_graph_replays_with_eager_work_between():
+    """One handle's captured graph replayed for new wavenumbers, with the
+    program's own eager work and synchronisations between the replays: every
+    replay equals the eager result."""
+    reqs = [Req(192, k, 4, 10 + j) for j, k in enumerate(I.contour_nodes(5.0, 0.5, 5))]
+    ref = [direct(r) for r in reqs]
+    s = B.Server(max_inflight=1, graph_max_n=192, lanes=1)
+    junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+    for r, Xr in zip(reqs, ref):
+        (res, X), = serve(s, [r])
+        assert res["status"] == 0 and res["graph"] == 1
+        assert torch.equal(X, Xr)
+        junk = (junk * 1.0001 + 1.0).sin()  # eager work on the default stream
+        torch.cuda.synchronize()
+    st = s.stats()
+    s.close()
+    assert st["graph_launches"] == len(reqs) and st["handles_created"] == 1
+
+
+def test_budget_eviction_and_rejection():
+    reqs = contour_mix()
+    ref = [direct(r) for r in reqs]
+    b = {n: B.problem_bytes(n) for n in (128, 192, 256)}
+    # room for the two largest handles at most: alternating sizes force evictions
+    budget = b[256] + b[192] + 1
+    s = B.Server(hbm_budget_bytes=budget, max_inflight=2)
+    out = serve(s, reqs)
+    st = s.stats()
+    for Xr, (res, X) in zip(ref, out):
+        assert res["status"] == 0
+        assert torch.equal(X, Xr)
+    assert st["evictions"] > 0 and st["bytes_peak"] <= budget and st["budget"] == budget
+    s.close()
+    # a handle of the request's size alone exceeds the budget: rejected at submission
+    s = B.Server(hbm_budget_bytes=b[128] - 1)
+    r = Req(128, 4.0, 2, 5)
+    torch.cuda.synchronize()
+    with pytest.raises(B.BMError) as e:
+        s.submit(r.geo, r.ph, r.B, r.new_x())
+    assert e.value.code == B.BM_E_BUDGET
+    assert s.stats()["rejected"] == 1
+    s.close()
+
+
+def test_factor_reuse():
+    n = 160
+    a = Req(n, 5.0 + 0.2j, 3, 21, key=42)
+    b = Req(n, 5.0 + 0.2j, 6, 22, key=42)     # same key, N and parameters: solve only
+    c = Req(n, 5.5, 3, 23, key=42)            # same key, other wavenumber: refactor
+    ref = [direct(r) for r in (a, b, c)]
+    s = B.Server(graph_max_n=256)
+    out = serve(s, [a, b, c])
+    st = s.stats()
+    s.close()
+    assert [res["reused_factors"] for res, _ in out] == [0, 1, 0]
+    for Xr, (res, X) in zip(ref, out):
+        assert res["status"] == 0
+        assert torch.equal(X, Xr)
+    assert st["factor_reuses"] == 1 and st["handles_created"] == 1
+
+
+def test_cancel_timeout_and_invalid_requests():
+    big = Req(1024, 8.0, 4, 31)
+    small = [Req(128, 4.0 + 0.1 * j, 2, 40 + j) for j in range(4)]
+    s = B.Server(max_inflight=1, lanes=1)
+    torch.cuda.synchronize()
+    tickets = [(s.submit(r.geo, r.ph, r.B, X), X) for r, X in [(big, big.new_x())] + [(r, r.new_x()) for r in small]]
+    last, _ = tickets[-1]
+    s.cancel(last)  # still queued behind the N = 1024 request
+    with pytest.raises(B.BMError) as e:
+        s.wait(tickets[0][0], timeout=0.0)
+    assert e.value.code in (B.BM_E_TIMEOUT,)
+    results = [s.wait(t) for t, _ in tickets]
+    assert [r["status"] for r in results] == [0, 0, 0, 0, B.BM_E_CANCELED]
+    with pytest.raises(B.BMError) as e:
+        s.wait(last)  # results are forgotten once returned
+    assert e.value.code == B.BM_E_ARG
+    r = small[0]
+    bad = I.Physics.from_wavenumbers(4.0 + 3.0j, 6.0)  # |Im k0| > Re k0 / 2
+    for args in [(r.geo, bad, r.B, r.new_x()), (r.geo, r.ph, r.B, r.B)]:
+        with pytest.raises(B.BMError) as e:
+            s.submit(*args)
+        assert e.value.code == B.BM_E_ARG
+    st = s.stats()
+    s.close()
+    assert st["canceled"] == 1 and st["completed"] == 4 and st["rejected"] == 2
+
+
+def test_lane_bounds():
+    for kw in [dict(lanes=17), dict(lanes=16, concurrent_max_n=2048), dict(lanes=2, concurrent_max_n=4096),
+               dict(graph_max_n=-1)]:
+        with pytest.raises(B.BMError) as e:
+            B.Server(**kw)
+        assert e.value.code == B.BM_E_ARG
+    B.Server(lanes=8, concurrent_max_n=1024).close()  # 8 * 16 = 128 = CUs / 2
