@@ -238,6 +238,44 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
     return out
 
 
+# Table tb:ssm_eigenvalues: the first "Mixed" row of each eigenvalue and its time
+# on 2x EPYC 9654 (order-31 zeta-corrected quadrature, N = 4000)
+SSM_PRINTED = {2: (0.42948496520839791 - 1.2813737976521153j, 98.895),
+               3: (1.3080120322683002 - 1.6817888047453846j, 114.206)}
+
+
+def ssm_section(n_nodes, per_side):
+    """Sakurai-Sugiura eigenvalues of the mixed equation on the disk of radius
+    0.5 (eps0 = 1, eps1 = 4) in squares of side 0.1 around the two printed
+    eigenvalues, L = M = 4 (Table tb:ssm_parameters), through the request server."""
+    import mpmath as mp
+    import numpy as np
+    from paper_2512_14193_amd import binding as B
+    from paper_2512_14193_amd import inputs as I
+    from paper_2512_14193_amd import ssm
+
+    bnd = I.disk(n_nodes, 0.5)
+    srv = B.Server(lanes=4)
+    ssm.eigenvalues(bnd, 1.0, 4.0, SSM_PRINTED[2][0], per_side=1, server=srv)  # handle creation, untimed
+    out = {"boundary": f"disk a=0.5, N={n_nodes}", "eps0": 1.0, "eps1": 4.0, "contour": "square, side 0.1",
+           "nodes_per_side": per_side, "quadrature": "Gauss-Legendre per side", "n_rhs": 4, "n_moments": 4,
+           "results": []}
+    mp.mp.dps = 40
+    for order, (z0, paper_s) in SSM_PRINTED.items():
+        res = ssm.eigenvalues(bnd, 1.0, 4.0, z0, side=0.1, per_side=per_side, server=srv)
+        zero = complex(mp.findroot(lambda z: mp.hankel1(order, z), mp.mpc(z0.real, z0.imag)))
+        out["results"].append({
+            "hankel_order": order, "eigenvalues": [[v.real, v.imag] for v in res.eigenvalues],
+            "rank": res.rank, "singular_values_rel": [float(v) for v in res.singular_values[:6] / res.singular_values[0]],
+            "solves": res.n_solves, "seconds": res.seconds, "device_ms": res.device_ms,
+            "max_abs_err_vs_hankel_zero": float(np.max(np.abs(res.eigenvalues - zero))) if len(res.eigenvalues)
+            else None,
+            "printed_value_abs_err_vs_hankel_zero": abs(z0 - zero),
+            "paper_seconds_2x_epyc_9654": paper_s})
+    srv.close()
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -268,6 +306,9 @@ def main():
     ap.add_argument("--serving-inflight", type=int, default=4)
     ap.add_argument("--serving-lanes", type=int, default=4)
     ap.add_argument("--serving-concurrent-max-n", type=int, default=2048)
+    ap.add_argument("--no-ssm", action="store_true", help="skip the Sakurai-Sugiura eigenvalue section")
+    ap.add_argument("--ssm-n", type=int, default=4000)
+    ap.add_argument("--ssm-per-side", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
@@ -333,6 +374,8 @@ def main():
     if not args.no_serving:
         rec["serving"] = serving_section(args.serving_rate, args.serving_graph_max_n, args.serving_inflight,
                                          args.serving_lanes, args.serving_concurrent_max_n)
+    if not args.no_ssm:
+        rec["ssm"] = ssm_section(args.ssm_n, args.ssm_per_side)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

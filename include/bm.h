@@ -68,8 +68,12 @@ enum bm_status {
   BM_E_BUDGET = -7,  /* request server: one problem of the request's size needs
                         more device memory than the server's budget            */
   BM_E_CANCELED = -8,/* request server: the request was canceled before it started */
-  BM_E_TIMEOUT = -9  /* request server: bm_server_wait timed out; the request is
+  BM_E_TIMEOUT = -9, /* request server: bm_server_wait timed out; the request is
                         still pending and can be waited for again               */
+  BM_E_DOMAIN = -10  /* bm_assemble met an argument k r of the Hankel functions
+                        outside their supported domain (a wavenumber below the
+                        sector |Im k| <= Re k / 2 with |k| r >= 6); reported by
+                        the next synchronising call; the matrix is invalid     */
 };
 
 enum bm_precision {
@@ -94,7 +98,10 @@ typedef struct {
 } bm_geometry;
 
 /* Physical parameters (Sec. 2.1 and 3.1).  k0, k1: exterior and interior
- * wavenumbers, complex allowed with Re k > 0 and |Im k| <= Re k / 2.
+ * wavenumbers, complex allowed with Re k > 0 and Im k <= Re k / 2: the sector
+ * |Im k| <= Re k / 2 for any boundary size, and below it (Im k < -Re k / 2, where
+ * the complex eigenvalues of Sec. 5.3 lie) as long as |k| |x - y| < 6 for all
+ * node pairs (else BM_E_DOMAIN).
  * eps0, eps1 > 0: material constants.  beta: Burton-Miller constant,
  * Im(beta) != 0. */
 typedef struct {
@@ -120,8 +127,8 @@ void bm_destroy(bm_problem *p);
  * G = (i/4) H0^(1)(k|x-y|)).  Mixed: fills Top and Bot.  Ordinary: fills the
  * 2N x 2N matrix.  Geometry and parameters are read in stream order; the
  * geometry arrays may be freed once the stream has passed the call.
- * Errors: BM_E_ARG (null pointers, eps <= 0, Im beta == 0, k outside the
- * supported sector). */
+ * Errors: BM_E_ARG (null pointers, eps <= 0, Im beta == 0, Re k <= 0 or
+ * Im k > Re k / 2); BM_E_DOMAIN later (see bm_params). */
 int bm_assemble(bm_problem *p, const bm_geometry *geometry, const bm_params *params);
 
 /* Factorisation.  Mixed (Theorem thm:LU): U33 = -M31 M13 - M32 M23 = -Bot * Top
@@ -187,8 +194,9 @@ int bm_copy_blocks(bm_problem *p, void *a, int64_t lda, void *b, int64_t ldb);
 int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv);
 
 /* Synchronise the problem's stream and report device-side errors of the calls
- * enqueued so far: BM_OK, or BM_E_DEVICE if a kernel raised the error flag (a
- * bounded wait expired).  The flag stays set for the lifetime of the problem. */
+ * enqueued so far: BM_OK, BM_E_DOMAIN if the latest bm_assemble met an argument
+ * outside the Hankel domain, or BM_E_DEVICE if a kernel raised the error flag (a
+ * bounded wait expired; cleared by the next factorisation). */
 int bm_sync(bm_problem *p);
 
 /* Per-phase timing with HIP events recorded on the problem's stream around each
@@ -332,6 +340,22 @@ int bm_server_stats(bm_server *s, bm_server_counters *st);
 /* Cancel the requests that have not started, wait for the others, release
  * every handle and the server.  Results not yet waited for are discarded. */
 void bm_server_destroy(bm_server *s);
+
+/* Block moments of the Sakurai-Sugiura projection (Sec. 5.3).  A contour
+ * integral of z^m A(z)^{-1} over a closed curve, evaluated by quadrature at
+ * nodes z_j with weights w_j, reduces each solve X_j = A(z_j)^{-1} V to the
+ * L x L block U^H X_j; this call accumulates
+ *   S_m += c_m U^H X,   m = 0 .. nmom-1,
+ * with c_m = w_j ((z_j - gamma) / rho)^m supplied by the caller.
+ * U, X: rows x L, column-major complex128 (device), ldu, ldx >= rows;
+ * coef: host array of nmom complex values (2 nmom doubles);
+ * S: device array of nmom column-major L x L complex128 blocks (moment m at
+ * offset m L^2), accumulated in place (the caller zeroes it first).
+ * Deterministic (fixed summation order).  Ordered on `hip_stream`.
+ * Errors: BM_E_ARG (rows < 1, L < 1 or L > BM_MAX_NRHS, nmom < 1 or > 64,
+ * null pointers, leading dimensions below rows). */
+int bm_block_moments(void *hip_stream, int32_t rows, int32_t L, const void *U, int64_t ldu,
+                     const void *X, int64_t ldx, int32_t nmom, const double *coef, void *S);
 
 /* Text for a status code. */
 const char *bm_strerror(int code);

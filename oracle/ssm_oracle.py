@@ -1,0 +1,93 @@
+"""CPU oracle of the Sakurai-Sugiura block projection used in Sec. 5.3
+(Table tb:ssm_parameters, Table tb:ssm_eigenvalues).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, never by the solver package;
+it shares no code with the HIP path.
+
+The eigenvalues of a matrix-valued function T(z) inside a closed curve G are
+found from the moments of its resolvent (block SS-Hankel method):
+
+  1. quadrature of G: nodes z_j and weights w_j approximating (1/2 pi i) dz
+     (Gauss-Legendre on each side of the square contour);
+  2. moments  mu_m = sum_j w_j zeta_j^m  U^H T(z_j)^{-1} V,  m = 0 .. 2M - 1,
+     with zeta = (z - gamma) / rho (gamma the centre, rho the scale of G) and
+     random n x L probing blocks U, V;
+  3. block Hankel matrices  H = [mu_{a+b}],  H' = [mu_{a+b+1}],  a, b = 0 .. M - 1;
+  4. truncated SVD  H = W S Z^H  keeping the singular values above delta S_11;
+  5. the eigenvalues lambda of  W_K^H H' Z_K S_K^{-1}  give z = gamma + rho lambda;
+     those inside G are the eigenvalues of T there.
+
+For the mixed system T(omega) is the 3N x 3N matrix of eq. dis_mixedBM at
+k0 = omega sqrt(eps0), k1 = omega sqrt(eps1), assembled and solved by the
+dense oracle (explicit matrix, partial-pivot LU).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import oracle as O
+
+
+def square_nodes(center: complex, side: float, per_side: int):
+    """Counterclockwise square of the given side centred at `center`; on each side
+    the per_side Gauss-Legendre nodes of that segment, with weights (segment
+    length / 2) (Gauss weight) (direction) / (2 pi i), i.e. a quadrature of
+    (1/2 pi i) dz that is exact for polynomials of degree 2 per_side - 1 on each
+    side (the integrand is analytic along each side, so it converges
+    geometrically; the corners are segment ends and cost nothing)."""
+    h = side / 2.0
+    corners = [center + complex(h, -h), center + complex(h, h), center + complex(-h, h), center + complex(-h, -h)]
+    t, gw = np.polynomial.legendre.leggauss(per_side)
+    z, w = [], []
+    for s in range(4):
+        a, b = corners[s], corners[(s + 1) % 4]
+        for tq, gq in zip(t, gw):
+            z.append(0.5 * (a + b) + 0.5 * (b - a) * tq)
+            w.append(0.5 * (b - a) * gq / (2j * np.pi))
+    return np.array(z), np.array(w)
+
+
+def inside_square(z, center, side):
+    h = side / 2.0
+    return abs((z - center).real) < h and abs((z - center).imag) < h
+
+
+def ss_eigenvalues(solve, center, side, per_side, U, V, n_mom, delta=1e-12):
+    """Steps 1-5 above for a resolvent callback solve(z, V) = T(z)^{-1} V.
+    Returns (eigenvalues inside the square, singular values of H)."""
+    z, w = square_nodes(center, side, per_side)
+    rho = side / 2.0
+    L = U.shape[1]
+    mu = np.zeros((2 * n_mom, L, L), dtype=np.complex128)
+    for zj, wj in zip(z, w):
+        X = solve(zj, V)
+        P = U.conj().T @ X
+        zeta = (zj - center) / rho
+        for m in range(2 * n_mom):
+            mu[m] += wj * zeta ** m * P
+    H = np.zeros((n_mom * L, n_mom * L), dtype=np.complex128)
+    Hs = np.zeros_like(H)
+    for a in range(n_mom):
+        for b in range(n_mom):
+            H[a * L:(a + 1) * L, b * L:(b + 1) * L] = mu[a + b]
+            Hs[a * L:(a + 1) * L, b * L:(b + 1) * L] = mu[a + b + 1]
+    W, S, Zh = np.linalg.svd(H)
+    K = int(np.sum(S > delta * S[0]))
+    Bk = W[:, :K].conj().T @ Hs @ Zh[:K, :].conj().T @ np.diag(1.0 / S[:K])
+    lam = np.linalg.eigvals(Bk)
+    zs = center + rho * lam
+    return np.sort_complex(np.array([v for v in zs if inside_square(v, center, side)])), S
+
+
+def mixed_resolvent(boundary, eps0, eps1, beta_of=None):
+    """solve(omega, V) = A(omega)^{-1} V for the mixed system of eq. dis_mixedBM
+    with k_i = omega sqrt(eps_i) and beta = i / k0 unless beta_of(omega) is given."""
+    from paper_2512_14193_amd import inputs as I
+
+    def solve(omega, V):
+        k0, k1 = omega * np.sqrt(eps0), omega * np.sqrt(eps1)
+        beta = beta_of(omega) if beta_of else 1j / k0
+        ph = I.Physics(k0=k0, k1=k1, eps0=eps0, eps1=eps1, beta=beta)
+        return O.zgesv(O.build_mixed(boundary, ph), V)
+
+    return solve

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbm_mi355x.so")
 
 BM_MIXED, BM_ORDINARY = 0, 1
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
-BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT = -7, -8, -9
+BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT, BM_E_DOMAIN = -7, -8, -9, -10
 BM_PREC_FP64, BM_PREC_MIXED = 0, 1
 BM_MAX_NRHS = 32
 
@@ -26,7 +26,7 @@ EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
             "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
-            "bm_server_cancel", "bm_server_stats", "bm_server_destroy"]
+            "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -108,6 +108,7 @@ def lib():
         L.bm_server_stats.argtypes = [vp, ctypes.POINTER(BMServerCounters)]
         L.bm_server_destroy.argtypes = [vp]
         L.bm_server_destroy.restype = None
+        L.bm_block_moments.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, dp, vp]
         L.bm_strerror.argtypes = [ctypes.c_int]
         L.bm_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -343,6 +344,20 @@ class Server:
         c = BMServerCounters()
         check(lib().bm_server_stats(self._h, ctypes.byref(c)), "bm_server_stats")
         return {name: getattr(c, name) for name, _ in BMServerCounters._fields_}
+
+
+def block_moments(U, X, coef, S, stream=None):
+    """S[m] += coef[m] U^H X for m = 0..len(coef)-1 (bm_block_moments).  U, X:
+    column-major complex128 (rows, L); S: complex128 CUDA tensor of nmom * L * L
+    elements (moment m is the column-major L x L block at offset m L^2)."""
+    stream = stream or torch.cuda.current_stream()
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128)).view(np.float64)
+    L = U.shape[1]
+    if X.shape != U.shape or S.numel() < len(coef) * L * L or not S.is_contiguous():
+        raise ValueError("block_moments: shapes do not match")
+    check(lib().bm_block_moments(_stream_handle(stream), U.shape[0], L, _ptr(U), _ld(U), _ptr(X), _ld(X), len(coef),
+                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(S)), "bm_block_moments")
+    return S
 
 
 def zgemm(alpha, A, B, beta, C, stream=None):

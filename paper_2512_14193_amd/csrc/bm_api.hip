@@ -20,6 +20,7 @@ const char *bm_strerror(int code) {
     case BM_E_BUDGET: return "request exceeds the server's device-memory budget";
     case BM_E_CANCELED: return "request canceled";
     case BM_E_TIMEOUT: return "wait timed out (request still pending)";
+    case BM_E_DOMAIN: return "an argument k r of the Hankel functions lies outside the supported domain";
     default: return code > 0 ? "singular factor (info > 0)" : "unknown status";
   }
 }
@@ -83,7 +84,7 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
     size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
     ok = ok && hipMalloc(&p->work_p, sizeof(cplx) * (wp > w2 ? wp : w2)) == hipSuccess;
   }
-  ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 2) == hipSuccess;
+  ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 4) == hipSuccess;
   if (formulation == BM_MIXED) {
     ok = ok && hipMalloc(&p->ir_r, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
     ok = ok && hipMalloc(&p->ir_d, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
@@ -97,7 +98,7 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
     free_problem(p);
     return BM_E_NOMEM;
   }
-  if (hipMemsetAsync(p->dev_err, 0, 2 * sizeof(int32_t), p->stream) != hipSuccess) {
+  if (hipMemsetAsync(p->dev_err, 0, 4 * sizeof(int32_t), p->stream) != hipSuccess) {
     free_problem(p);
     return BM_E_HIP;
   }
@@ -143,9 +144,12 @@ int bm_check_params(const bm_params *prm) {
   if (!prm) return BM_E_ARG;
   if (!(prm->eps0 > 0.0) || !(prm->eps1 > 0.0) || !isfinite(prm->eps0) || !isfinite(prm->eps1)) return BM_E_ARG;
   if (prm->beta_im == 0.0 || !isfinite(prm->beta_re) || !isfinite(prm->beta_im)) return BM_E_ARG;
+  // Re k > 0 and Im k <= Re k / 2: the sector |Im k| <= Re k / 2, or the lower half
+  // plane beyond it, where the assembly checks |k| r < 6 itself (BM_E_DOMAIN)
   const double ks[2][2] = {{prm->k0_re, prm->k0_im}, {prm->k1_re, prm->k1_im}};
   for (int w = 0; w < 2; ++w)
-    if (!(ks[w][0] > 0.0) || !isfinite(ks[w][0]) || !(fabs(ks[w][1]) <= 0.5 * ks[w][0])) return BM_E_ARG;
+    if (!(ks[w][0] > 0.0) || !isfinite(ks[w][0]) || !isfinite(ks[w][1]) || !(ks[w][1] <= 0.5 * ks[w][0]))
+      return BM_E_ARG;
   return BM_OK;
 }
 
@@ -198,10 +202,11 @@ int bm_assemble(bm_problem *p, const bm_geometry *g, const bm_params *prm) {
 }
 
 static int read_dev_err(bm_problem *p, int32_t *info) {
-  int32_t h[2] = {0, 0};
+  int32_t h[4] = {0, 0, 0, 0};
   BM_HIP_TRY(hipMemcpyAsync(h, p->dev_err, sizeof(h), hipMemcpyDeviceToHost, p->stream));
   BM_HIP_TRY(hipStreamSynchronize(p->stream));
   if (info) *info = h[1];
+  if (h[2]) return BM_E_DOMAIN;
   return h[0] ? BM_E_DEVICE : BM_OK;
 }
 

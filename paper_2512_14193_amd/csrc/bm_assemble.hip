@@ -109,6 +109,7 @@ struct asm_args {
   const double *wts;
   cplx *top, *bot;  // mixed
   cplx *ord;        // ordinary
+  int32_t *dom_err; // set to 1 if an argument k r lies outside the supported domain
 };
 
 // Per-wavenumber symmetric scalars of an off-diagonal pair:
@@ -118,9 +119,10 @@ struct pair_k {
   cplx sig, del, nu;
 };
 
+template <bool WIDE>
 __device__ inline pair_k pair_scalars(cplx k, double r, double rinv, double R, double L, double h, double a,
-                                      double b, bool want_nu) {
-  const bm_hk4 hk = bm_hankel01(cscale(k, r));
+                                      double b, bool want_nu, bool *bad) {
+  const bm_hk4 hk = WIDE ? bm_hankel01_wide(cscale(k, r), bad) : bm_hankel01(cscale(k, r));
   pair_k o;
   // S: K = (i/4) H0, K1 = -J0/(4 pi)
   const cplx aS = cmk(-0.25 * hk.h0.y, 0.25 * hk.h0.x);
@@ -168,7 +170,7 @@ __device__ inline void store_entry(const asm_args &A, int blk, int row, int col,
   }
 }
 
-template <int FORM>
+template <int FORM, bool WIDE>
 __global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
   // unordered tile pair (I, J), I <= J, from the triangular index
   const long Lt = blockIdx.x;
@@ -208,8 +210,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
       const double K0 = (-2.0 * aa / r2 + 4.0 * dai * daj / (r2 * r2) - C) / (4.0 * BM_PI);
       const double kap = T + h * K0;  // N_0,ij = kap / s_i, N_0,ji = kap / s_j
 
-      const pair_k p0 = pair_scalars(ph.k0, r, rinv, R, L, h, a, b, true);
-      const pair_k p1 = pair_scalars(ph.k1, r, rinv, R, L, h, a, b, false);
+      bool bad = false;
+      const pair_k p0 = pair_scalars<WIDE>(ph.k0, r, rinv, R, L, h, a, b, true, &bad);
+      const pair_k p1 = pair_scalars<WIDE>(ph.k1, r, rinv, R, L, h, a, b, false, &bad);
+      if (WIDE && bad) atomicOr(A.dom_err, 1);
       // k0 operators at (i,j) and (j,i)
       const cplx S0ij = cscale(p0.sig, sj), S0ji = cscale(p0.sig, si);
       const cplx D0ij = cscale(p0.del, ndj), D0ji = cscale(p0.del, -ndi);
@@ -309,12 +313,21 @@ int bm_launch_assemble(bm_problem *p, const bm_geometry *g) {
   A.top = p->top;
   A.bot = p->bot;
   A.ord = p->lu;
+  A.dom_err = p->dev_err + 2;
+  // wide domain when a wavenumber lies below the sector |Im k| <= Re k / 2
+  const bool wide = (p->phys.k0.y < -0.5 * p->phys.k0.x) || (p->phys.k1.y < -0.5 * p->phys.k1.x);
+  if (int rc = bm_fill_u64(p->stream, p->dev_err + 2, 1, 0ull)) return rc;  // words 2, 3
   const long nt = (p->n + ASM_TB - 1) / ASM_TB;
   const long ntiles = nt * (nt + 1) / 2;
-  if (p->form == BM_MIXED)
-    hipLaunchKernelGGL(assemble_kernel<BM_MIXED>, dim3((unsigned)ntiles), dim3(256), 0, p->stream, A);
+  const dim3 grid((unsigned)ntiles);
+  if (p->form == BM_MIXED && !wide)
+    hipLaunchKernelGGL((assemble_kernel<BM_MIXED, false>), grid, dim3(256), 0, p->stream, A);
+  else if (p->form == BM_MIXED)
+    hipLaunchKernelGGL((assemble_kernel<BM_MIXED, true>), grid, dim3(256), 0, p->stream, A);
+  else if (!wide)
+    hipLaunchKernelGGL((assemble_kernel<BM_ORDINARY, false>), grid, dim3(256), 0, p->stream, A);
   else
-    hipLaunchKernelGGL(assemble_kernel<BM_ORDINARY>, dim3((unsigned)ntiles), dim3(256), 0, p->stream, A);
+    hipLaunchKernelGGL((assemble_kernel<BM_ORDINARY, true>), grid, dim3(256), 0, p->stream, A);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

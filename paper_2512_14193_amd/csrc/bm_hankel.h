@@ -13,6 +13,15 @@
 //                   on s in [0, 6.4] is accurate to ~1e-16 for |z| >= 3 in the sector.
 //                   J = (H^(1) + H^(2))/2 with H^(2)(z) = conj(H^(1)(conj z)).
 //   |z| >= 25       Hankel's asymptotic expansion (DLMF 10.17.5), terms until < 1e-17.
+//
+// Wide domain (bm_hankel01_wide): wavenumbers in the lower half plane beyond that
+// sector (Im k < -Re k / 2), where the complex resonances and fictitious
+// eigenvalues of Sec. 5.3 lie.  There the singularity s^2 = 2iz of the integral
+// approaches the integration path, so the power series is used instead, for
+// |z| < 6 with 26 terms (the last term is below 1e-26 of the largest); in the
+// lower half plane J and Y grow like H^(1), so the series loses at most a factor
+// e^{|z| - |Im z|} <= 30 to cancellation.  Larger |z| is outside the supported
+// domain: the caller flags it.
 #pragma once
 
 #include "bm_internal.h"
@@ -31,13 +40,14 @@ extern __constant__ double bm_hk_g0[BM_HQ + 1];
 extern __constant__ double bm_hk_g1[BM_HQ + 1];
 extern __constant__ double bm_hk_s2[BM_HQ + 1];
 
+template <int NT = 18>
 __device__ inline void bm_hankel_series(cplx z, bm_hk4 &o) {
   const cplx mw = cscale(cmul(z, z), -0.25);  // -z^2/4
   cplx t0 = cmk(1.0, 0.0), t1 = cmk(1.0, 0.0);
   cplx sj0 = cmk(0, 0), sj1 = cmk(0, 0), sy0 = cmk(0, 0), sy1 = cmk(0, 0);
   double hk = 0.0, hk1 = 1.0;  // harmonic numbers H_k, H_{k+1}
 #pragma unroll
-  for (int k = 0; k < 18; ++k) {
+  for (int k = 0; k < NT; ++k) {
     sj0 = cadd(sj0, t0);
     sj1 = cadd(sj1, t1);
     sy0 = cadd(sy0, cscale(t0, hk));
@@ -123,11 +133,27 @@ __device__ inline void bm_hankel_asymptotic(cplx z, bm_hk4 &o) {
   o.j1 = cscale(cadd(H11, H21), 0.5);
 }
 
+// Largest |z| of the wide domain
+#define BM_WIDE_ZMAX 6.0
+
+// Wide domain: power series only; *bad is set when |z| >= BM_WIDE_ZMAX.
+__device__ inline bm_hk4 bm_hankel01_wide(cplx z, bool *bad) {
+  bm_hk4 o;
+  const double az2 = cabs2(z);
+  if (az2 < 9.0) {
+    bm_hankel_series<18>(z, o);
+  } else {
+    if (!(az2 < BM_WIDE_ZMAX * BM_WIDE_ZMAX)) *bad = true;
+    bm_hankel_series<26>(z, o);
+  }
+  return o;
+}
+
 __device__ inline bm_hk4 bm_hankel01(cplx z) {
   bm_hk4 o;
   const double az2 = cabs2(z);
   if (az2 < 9.0) {
-    bm_hankel_series(z, o);
+    bm_hankel_series<18>(z, o);
   } else if (az2 < 625.0) {
     bm_hankel_integral(z, o.h0, o.h1);
     if (z.y == 0.0) {

@@ -133,7 +133,8 @@ struct bm_problem {
   cplx *dinv;           // inverses of the 64 x 64 diagonal blocks of L and U
   cplx *work_g;         // nf x BM_MAX_NRHS: permuted right-hand sides
   cplx *work_p;         // split-K partial sums of the skinny GEMMs
-  int32_t *dev_err;     // device-side error flag and getrf info: [0] error, [1] info
+  int32_t *dev_err;     // device-side flags: [0] error (bounded wait), [1] getrf info,
+                        // [2] assembly argument outside the Hankel domain, [3] unused
   bm_getrf_ws *gws;
 
   // precision of the factorisation (BM_PREC_*) and the FP64 refinement of bm_solve

@@ -102,7 +102,7 @@ struct bm_server {
   std::vector<srv_request *> inflight;
   std::vector<hipEvent_t> ev_start, ev_done;
   std::vector<int> free_slots;
-  int32_t *pinned = nullptr;         // 2 words per slot: error flag, info
+  int32_t *pinned = nullptr;         // 4 words per slot: error flag, info, domain flag, 0
   uint64_t use_clock = 0;
 };
 
@@ -285,7 +285,7 @@ int enqueue(bm_server *s, srv_request *rq) {
     }
   }
   if (rc) return rc;
-  BM_HIP_TRY(hipMemcpyAsync(s->pinned + 2 * rq->slot, h->p->dev_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BM_HIP_TRY(hipMemcpyAsync(s->pinned + 4 * rq->slot, h->p->dev_err, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   BM_HIP_TRY(hipEventRecord(s->ev_done[rq->slot], st));
   s->lanes[rq->lane].used = true;
   if (!is_small(s, r.n)) {
@@ -334,8 +334,9 @@ bool poll(bm_server *s) {
     if (e != hipSuccess) {
       status = BM_E_HIP;
     } else {
-      const int32_t *w = s->pinned + 2 * rq->slot;
-      if (w[0]) status = BM_E_DEVICE;
+      const int32_t *w = s->pinned + 4 * rq->slot;
+      if (w[2]) status = BM_E_DOMAIN;
+      else if (w[0]) status = BM_E_DEVICE;
       else if (w[1] > 0) status = w[1];
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, s->ev_start[rq->slot], s->ev_done[rq->slot]) == hipSuccess)
@@ -466,7 +467,7 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
     ok = hipEventCreate(&s->ev_start[i]) == hipSuccess && hipEventCreate(&s->ev_done[i]) == hipSuccess;
     s->free_slots.push_back(nslot - 1 - i);
   }
-  ok = ok && hipHostMalloc((void **)&s->pinned, sizeof(int32_t) * 2 * nslot, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&s->pinned, sizeof(int32_t) * 4 * nslot, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_server(s);
     return BM_E_HIP;

@@ -54,6 +54,42 @@ def test_hankel_vs_mpmath(z):
         assert abs(got - ref) <= 2e-15 * max(abs(ref), abs(h))
 
 
+def _wide_samples(n=1500, seed=17):
+    """The wide domain of the assembly: |z| < 6 with -pi/2 < arg z < -atan(1/2),
+    where the complex eigenvalues of Sec. 5.3 lie (the second printed zero,
+    1.308 - 1.682i, gives |k1 r| up to 4.3 on the disk of radius 0.5)."""
+    rng = np.random.default_rng(seed)
+    r = 6.0 * np.sqrt(rng.uniform(1e-6, 1.0, n))
+    ang = rng.uniform(-0.5 * np.pi + 1e-3, -np.arctan(0.5), n)
+    return r * np.exp(1j * ang)
+
+
+def test_hankel_wide_domain_vs_scipy_and_mpmath():
+    z = _wide_samples()
+    H0, H1, J0, J1 = O.hankel01(z)
+    for got, ref in ((H0, sp.hankel1(0, z)), (H1, sp.hankel1(1, z)), (J0, sp.jv(0, z)), (J1, sp.jv(1, z))):
+        # in the lower half plane J, Y and H^(1) all grow like e^{|Im z|}: relative to |H|
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), np.abs(H0))
+        assert err.max() < 2e-14, (z[np.argmax(err)], err.max())
+    mp.mp.dps = 30
+    for zc in (0.42948496520839791 - 1.2813737976521153j, 2.6160240645 - 3.3635776094j, 5.9j ** 0.5 * -1j,
+               0.1 - 5.9j, 3.0 - 4.0j):
+        zz = mp.mpc(zc.real, zc.imag)
+        h0, h1, _, _ = (v.item() for v in O.hankel01(np.array([zc])))
+        assert abs(h0 - complex(mp.hankel1(0, zz))) <= 1e-14 * abs(h0)
+        assert abs(h1 - complex(mp.hankel1(1, zz))) <= 1e-14 * abs(h1)
+
+
+def test_wide_domain_wronskian():
+    # J1 Y0 - J0 Y1 = 2 / (pi z) (DLMF 10.5.2)
+    z = _wide_samples(600, seed=5)
+    H0, H1, J0, J1 = O.hankel01(z)
+    Y0, Y1 = (H0 - J0) / 1j, (H1 - J1) / 1j
+    w = J1 * Y0 - J0 * Y1
+    scale = np.abs(H0) * np.abs(H1)
+    assert np.max(np.abs(w - 2 / (np.pi * z)) / np.maximum(scale, np.abs(2 / (np.pi * z)))) < 1e-14
+
+
 def test_wronskian_and_small_argument_limits():
     z = _domain_samples(800, seed=3)
     H0, H1, J0, J1 = O.hankel01(z)
