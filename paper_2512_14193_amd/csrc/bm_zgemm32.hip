@@ -10,11 +10,18 @@
 //
 // Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 128 x 128 tile of
 // C, two workgroups per CU (accumulators in VGPRs, no spills); each wave owns
-// 64 x 64 = 2 x 2 blocks of 32 x 32 with separate real and
-// imaginary FP32 accumulators (16 values per lane each).  A complex product costs
-// four real MFMAs: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  Operands are staged
-// through LDS in k-slices of G2_BK complex values, double buffered, with the global
-// loads of the next slice in flight during the MFMAs of the current one.
+// 64 x 64 = 2 x 2 blocks of 32 x 32.  Operands are staged through LDS in k-slices
+// of G2_BK complex values, double buffered, with the global loads of the next
+// slice in flight during the MFMAs of the current one.
+//
+// Complex products (G2_3M): Gauss's three-multiplication form,
+//   T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi),
+//   Re = T1 - T2,  Im = T3 - T1 - T2,
+// three real MFMAs per complex multiply-add instead of four (Re += Ar Br - Ai Bi,
+// Im += Ar Bi + Ai Br), with the sums Ar + Ai and Br + Bi formed in FP32 while
+// staging.  Its rounding error in Im is bounded by (|Ar| + |Ai|)(|Br| + |Bi|)
+// instead of |A||B| terms: the same order in FP32, and the refinement of the
+// mixed-precision solve removes it either way.
 //
 // MFMA operand order: the B fragment is the MFMA's first operand and the A
 // fragment its second, so the 32 x 32 result lands transposed: lane l holds row
@@ -30,21 +37,25 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #define G2_BK 8                       // k-slice of complex values per LDS stage
 #endif
 #define G2_LPT (G2_BK * G2_BM / 256)  // complex values of each operand loaded per thread and stage
-
-struct f32c {
-  float x, y;
-};
+#ifndef G2_3M
+#define G2_3M 1
+#endif
+#ifndef G2_OCC
+#define G2_OCC 2  // workgroups per CU
+#endif
+#define G2_NP (G2_3M ? 3 : 2)  // operand planes in LDS: (re, im[, re + im])
 
 __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
 template <bool BETA0>
-__global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
-                                                      long lda, const cplx *__restrict__ B, long ldb, cplx beta,
-                                                      cplx *__restrict__ C, long ldc, int tiles_m) {
-  __shared__ f32c As[2][G2_BK][G2_BM];
-  __shared__ f32c Bs[2][G2_BK][G2_BN];
+__global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int k, cplx alpha,
+                                                           const cplx *__restrict__ A, long lda,
+                                                           const cplx *__restrict__ B, long ldb, cplx beta,
+                                                           cplx *__restrict__ C, long ldc, int tiles_m) {
+  __shared__ float As[2][G2_NP][G2_BK][G2_BM];
+  __shared__ float Bs[2][G2_NP][G2_BK][G2_BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -71,21 +82,30 @@ __global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cp
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < G2_LPT; ++u) {
-      As[buf][a_k + (256 / G2_BM) * u][a_r] = f32c{(float)ra[u].x, (float)ra[u].y};
-      Bs[buf][b_k + u][b_c] = f32c{(float)rb[u].x, (float)rb[u].y};
+      const int ka = a_k + (256 / G2_BM) * u, kb = b_k + u;
+      const float xr = (float)ra[u].x, xi = (float)ra[u].y, yr = (float)rb[u].x, yi = (float)rb[u].y;
+      As[buf][0][ka][a_r] = xr;
+      As[buf][1][ka][a_r] = xi;
+      Bs[buf][0][kb][b_c] = yr;
+      Bs[buf][1][kb][b_c] = yi;
+      if (G2_3M) {
+        As[buf][2][ka][a_r] = xr + xi;
+        Bs[buf][2][kb][b_c] = yr + yi;
+      }
     }
   };
 
-  f32x16 accr[2][2], acci[2][2];
+  // 3M: acc[0] = sum Ar Br, acc[1] = sum Ai Bi, acc[2] = sum (Ar + Ai)(Br + Bi)
+  // 4M: acc[0] = Re, acc[1] = Im
+  f32x16 acc[G2_NP][2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int p = 0; p < G2_NP; ++p)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        accr[a][b][r] = 0.f;
-        acci[a][b][r] = 0.f;
-      }
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[p][a][b][r] = 0.f;
 
   const int nk = (k + G2_BK - 1) / G2_BK;
   if (nk > 0) {
@@ -96,12 +116,15 @@ __global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cp
   const int fh = lane >> 5, fi = lane & 31;
   // operand fragments of one k-pair, double buffered in registers so that the
   // LDS reads of the next pair are in flight during the MFMAs of this one
-  f32c av[2][2], bv[2][2];
+  float av[2][G2_NP][2], bv[2][G2_NP][2];
   auto fload = [&](int buf, int k2, int slot) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[slot][a] = As[buf][k2 + fh][wm * 64 + a * 32 + fi];
+    for (int p = 0; p < G2_NP; ++p) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b) bv[slot][b] = Bs[buf][k2 + fh][wn * 64 + b * 32 + fi];
+      for (int a = 0; a < 2; ++a) av[slot][p][a] = As[buf][p][k2 + fh][wm * 64 + a * 32 + fi];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[slot][p][b] = Bs[buf][p][k2 + fh][wn * 64 + b * 32 + fi];
+    }
   };
   for (int it = 0; it < nk; ++it) {
     const int buf = it & 1;
@@ -111,22 +134,24 @@ __global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cp
     for (int k2 = 0; k2 < G2_BK; k2 += 2) {
       const int cur = (k2 >> 1) & 1;
       if (k2 + 2 < G2_BK) fload(buf, k2 + 2, cur ^ 1);
+      if (G2_3M) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma32(bv[cur][b].x, av[cur][a].x, accr[a][b]);
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) acc[p][a][b] = mfma32(bv[cur][p][b], av[cur][p][a], acc[p][a][b]);
+      } else {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma32(bv[cur][b].y, av[cur][a].x, acci[a][b]);
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma32(bv[cur][b].y, -av[cur][a].y, accr[a][b]);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma32(bv[cur][b].x, av[cur][a].y, acci[a][b]);
+          for (int b = 0; b < 2; ++b) {
+            acc[0][a][b] = mfma32(bv[cur][0][b], av[cur][0][a], acc[0][a][b]);
+            acc[1][a][b] = mfma32(bv[cur][1][b], av[cur][0][a], acc[1][a][b]);
+            acc[0][a][b] = mfma32(bv[cur][1][b], -av[cur][1][a], acc[0][a][b]);
+            acc[1][a][b] = mfma32(bv[cur][0][b], av[cur][1][a], acc[1][a][b]);
+          }
+      }
     }
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -142,7 +167,16 @@ __global__ __launch_bounds__(256, 2) void zgemm32_kernel(int m, int n, int k, cp
         const int row = row0 + wm * 64 + a * 32 + fi;
         const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
         if (row < m && col < n) {
-          const cplx v = cmk((double)accr[a][b][r], (double)acci[a][b][r]);
+          float re, im;
+          if (G2_3M) {
+            const float t1 = acc[0][a][b][r], t2 = acc[1][a][b][r];
+            re = t1 - t2;
+            im = acc[2][a][b][r] - t1 - t2;
+          } else {
+            re = acc[0][a][b][r];
+            im = acc[1][a][b][r];
+          }
+          const cplx v = cmk((double)re, (double)im);
           cplx out = cmul(alpha, v);
           if (!BETA0) out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
           C[row + (long)col * ldc] = out;
