@@ -115,7 +115,9 @@ def mixed_precision_section(name, steps, warmup, tol):
         r = run_formulation("mixed", w, steps, warmup, precision=prec, tol=tol)
         ph = r["phase_ms"]
         res[prec] = {"solves_per_s": steps / r["seconds"], "ms_per_step": 1e3 * r["seconds"] / steps,
-                     "phase_ms": ph, "schur_tflops": 16.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
+                     "phase_ms": ph,
+                     "schur_tflops": 16.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
+                     "schur_executed_mfma_tflops": 12.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
                      "refine_iterations": r["refine_iterations"], "rel_residual": r["rel_residual"], "X": r["X"]}
     Xf, Xm = res["fp64"].pop("X"), res["mixed"].pop("X")
     diff = float(np.max(np.linalg.norm(Xm - Xf, axis=0) / np.linalg.norm(Xf, axis=0)))
@@ -331,10 +333,18 @@ def main():
     sec = mixed["seconds"]
     value = args.steps / sec
     ph = mixed["phase_ms"]
+    # Algorithmic work: the Schur complement (m = n = N, k = 2N) is 8 m n k =
+    # 16 N^3 real flops, the LU of U33 8/3 N^3.  The Schur kernel uses Gauss's
+    # three-multiplication form and executes 12 N^3 real flops on the matrix
+    # cores; that executed rate is reported beside the algorithmic one (the
+    # hardware utilisation itself comes from the rocprof MFMA counters).
     flops_schur = 16.0 * N ** 3
+    flops_schur_mfma = 12.0 * N ** 3
     flops_lu = 8.0 / 3.0 * N ** 3
-    schur_tflops = flops_schur / (ph["schur_gemm"] * 1e-3) / 1e12
-    factor_tflops = (flops_schur + flops_lu) / ((ph["schur_gemm"] + ph["lu"]) * 1e-3) / 1e12
+    t_schur = ph["schur_gemm"] * 1e-3
+    schur_tflops = flops_schur / t_schur / 1e12
+    t_factor = (ph["schur_gemm"] + ph["lu"]) * 1e-3
+    factor_tflops = (flops_schur + flops_lu) / t_factor / 1e12
     traffic = traffic_record()
     rec = {
         "metric": "block-LU solves/s (mixed Burton-Miller, assemble + factor + 8-RHS solve + far field)",
@@ -352,9 +362,11 @@ def main():
         "config": {"workload": w.name, "boundary": w.boundary.name, "n_nodes": N, "unknowns": 3 * N,
                    "k0": w.physics.k0.real, "k1": w.physics.k1.real, "eps1": w.physics.eps1, "nrhs": R,
                    "far_field_angles": len(w.theta_obs), "quadrature": "Kress log-split"},
-        "roofline": {"bound": "mfma", "kernel": "zgemm_kernel (Schur complement, m=n=N, k=2N)",
+        "roofline": {"bound": "mfma",
+                     "kernel": "zgemm_kernel<true,true> (Schur complement, m=n=N, k=2N; 16 N^3 algorithmic flops)",
                      "achieved": schur_tflops, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic},
+        "schur_executed_mfma_tflops": flops_schur_mfma / t_schur / 1e12,
         "phase_ms": ph,
         "factor_tflops": factor_tflops,
         "factor_mfma_frac": factor_tflops / PEAK_FP64_MFMA_TFLOPS,

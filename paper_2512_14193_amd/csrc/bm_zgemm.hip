@@ -5,13 +5,19 @@
 // (m = n = N, k = 2N: six sevenths of the factorisation flops), for the
 // trailing updates of the blocked LU and for the skinny products of the solve.
 //
-// Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 64 x 64 tile of C,
-// up to four workgroups per CU (accumulators in VGPRs); each wave owns
-// 32 x 32 = 2 x 2 blocks of 16 x 16 and keeps separate real and
-// imaginary accumulators (8 x v_mfma_f64_16x16x4f64 results).  A complex product
-// costs four real MFMAs: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  Operands are
-// staged through LDS in k-slices of GM_BK complex values, double buffered, and the
-// fragments of the next k-quad are read from LDS during the MFMAs of this one.
+// Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 64 x 64 tile of C
+// (accumulators in VGPRs); each wave owns 32 x 32 = 2 x 2 blocks of 16 x 16
+// (v_mfma_f64_16x16x4f64 results).  Operands are staged through LDS in k-slices
+// of GM_BK complex values, double buffered, and the fragments of the next k-quad
+// are read from LDS during the MFMAs of this one.
+//
+// Complex products: for shallow products (k < GM_3M_MIN_K: the trailing updates
+// of the LU, bound by memory traffic) four real MFMAs per complex multiply-add,
+// Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br, four workgroups per CU.  For deep
+// ones (the Schur complement) Gauss's form with three: T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2 (the sums staged in
+// LDS), two workgroups per CU.  Its rounding error stays at the FP64 level,
+// bounded by (|Ar| + |Ai|)(|Br| + |Bi|) sums instead of |A||B| ones.
 //
 // MFMA operand order: the B fragment is fed as the MFMA's first operand and the A
 // fragment as its second, so that the 16 x 16 result lands transposed in the
@@ -28,17 +34,22 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 #define GM_BK 8
 #endif
 #define GM_LPT (GM_BK * GM_BM / 256)  // complex values of each operand loaded per thread and stage
+#ifndef GM_3M_MIN_K
+#define GM_3M_MIN_K 256  // Gauss's 3-multiplication form from this depth k on
+#endif
 
 __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <bool BETA0>
+template <bool BETA0, bool M3>
 __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
                                                     long lda, const cplx *__restrict__ B, long ldb, cplx beta,
                                                     cplx *__restrict__ C, long ldc, int tiles_m) {
   __shared__ cplx As[2][GM_BK][GM_BM];
   __shared__ cplx Bs[2][GM_BK][GM_BN + 1];
+  __shared__ double Ass[2][M3 ? GM_BK : 1][M3 ? GM_BM : 1];      // Ar + Ai
+  __shared__ double Bss[2][M3 ? GM_BK : 1][M3 ? GM_BN + 1 : 1];  // Br + Bi
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -67,16 +78,22 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
     for (int u = 0; u < GM_LPT; ++u) {
       As[buf][a_k + 4 * u][a_r] = ra[u];
       Bs[buf][b_k + u][b_c] = rb[u];
+      if constexpr (M3) {
+        Ass[buf][a_k + 4 * u][a_r] = ra[u].x + ra[u].y;
+        Bss[buf][b_k + u][b_c] = rb[u].x + rb[u].y;
+      }
     }
   };
 
-  dbl4 accr[2][2], acci[2][2];
+  // 4M: accr = Re, acci = Im.  3M: accr = sum Ar Br, acci = sum Ai Bi, accs = sum (Ar + Ai)(Br + Bi)
+  dbl4 accr[2][2], acci[2][2], accs[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       accr[a][b] = (dbl4){0, 0, 0, 0};
       acci[a][b] = (dbl4){0, 0, 0, 0};
+      accs[a][b] = (dbl4){0, 0, 0, 0};
     }
 
   const int nk = (k + GM_BK - 1) / GM_BK;
@@ -89,11 +106,18 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
   // operand fragments of one k-quad, double buffered in registers so that the LDS
   // reads of the next quad are in flight during the MFMAs of this one
   cplx av[2][2], bv[2][2];
+  double as[2][2], bs[2][2];
   auto fload = [&](int buf, int k4, int slot) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) av[slot][a] = As[buf][k4 + fq][wm * 32 + a * 16 + fi];
 #pragma unroll
     for (int b = 0; b < 2; ++b) bv[slot][b] = Bs[buf][k4 + fq][wn * 32 + b * 16 + fi];
+    if constexpr (M3) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) as[slot][a] = Ass[buf][k4 + fq][wm * 32 + a * 16 + fi];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bs[slot][b] = Bss[buf][k4 + fq][wn * 32 + b * 16 + fi];
+    }
   };
   for (int it = 0; it < nk; ++it) {
     const int buf = it & 1;
@@ -103,6 +127,16 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
     for (int k4 = 0; k4 < GM_BK; k4 += 4) {
       const int cur = (k4 >> 2) & 1;
       if (k4 + 4 < GM_BK) fload(buf, k4 + 4, cur ^ 1);
+if constexpr (M3) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accr[a][b] = mfma16(bv[cur][b].x, av[cur][a].x, accr[a][b]);
+          acci[a][b] = mfma16(bv[cur][b].y, av[cur][a].y, acci[a][b]);
+          accs[a][b] = mfma16(bs[cur][b], as[cur][a], accs[a][b]);
+        }
+} else {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -119,6 +153,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acci[a][b] = mfma16(bv[cur][b].x, av[cur][a].y, acci[a][b]);
+}
     }
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -134,7 +169,13 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
         const int row = row0 + wm * 32 + a * 16 + fi;
         const int col = col0 + wn * 32 + b * 16 + 4 * r + fq;
         if (row < m && col < n) {
-          const cplx v = cmk(accr[a][b][r], acci[a][b][r]);
+          cplx v;
+          if constexpr (M3) {
+            const double t1 = accr[a][b][r], t2 = acci[a][b][r];
+            v = cmk(t1 - t2, accs[a][b][r] - t1 - t2);
+          } else {
+            v = cmk(accr[a][b][r], acci[a][b][r]);
+          }
           cplx out = cmul(alpha, v);
           if (!BETA0) out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
           C[row + (long)col * ldc] = out;
@@ -148,12 +189,20 @@ int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *
   const int tm = (m + GM_BM - 1) / GM_BM, tn = (n + GM_BN - 1) / GM_BN;
   const long tiles = (long)tm * tn;
   if (tiles > 0x7fffffffL) return BM_E_ARG;
-  if (beta.x == 0.0 && beta.y == 0.0)
-    hipLaunchKernelGGL(zgemm_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B,
+  const bool b0 = beta.x == 0.0 && beta.y == 0.0, m3 = k >= GM_3M_MIN_K;
+  const dim3 grid((unsigned)tiles);
+  if (b0 && m3)
+    hipLaunchKernelGGL((zgemm_kernel<true, true>), grid, dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B, (long)ldb,
+                       beta, C, (long)ldc, tm);
+  else if (b0)
+    hipLaunchKernelGGL((zgemm_kernel<true, false>), grid, dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B,
+                       (long)ldb, beta, C, (long)ldc, tm);
+  else if (m3)
+    hipLaunchKernelGGL((zgemm_kernel<false, true>), grid, dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B,
                        (long)ldb, beta, C, (long)ldc, tm);
   else
-    hipLaunchKernelGGL(zgemm_kernel<false>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda,
-                       B, (long)ldb, beta, C, (long)ldc, tm);
+    hipLaunchKernelGGL((zgemm_kernel<false, false>), grid, dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B,
+                       (long)ldb, beta, C, (long)ldc, tm);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
