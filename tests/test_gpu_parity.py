@@ -78,7 +78,7 @@ def test_zgemm_vs_numpy(m, n, k, beta):
     assert np.abs(to_np(dC) - ref).max() < 1e-12 * np.abs(ref).max() * max(1, np.sqrt(k))
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 65, 200, 333])
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 200, 333, 2200])  # 2200: 128-row panels, then 64-row ones
 def test_zgetrf_vs_numpy(n):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
