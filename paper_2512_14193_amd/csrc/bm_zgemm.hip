@@ -34,6 +34,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 #define GM_BK 8
 #endif
 #define GM_LPT (GM_BK * GM_BM / 256)  // complex values of each operand loaded per thread and stage
+#ifndef BM_SHALLOW_GEMM
+#define BM_SHALLOW_GEMM 1
+#endif
 #ifndef GM_3M_MIN_K
 #define GM_3M_MIN_K 256  // Gauss's 3-multiplication form from this depth k on
 #endif
@@ -183,9 +186,64 @@ if constexpr (M3) {
       }
 }
 
+// Shallow, narrow products (k <= 64, n <= 64: the update of the next panel's
+// columns in the LU, on its critical path): 32 x 32 output tiles (four times the
+// workgroups of the 64 x 64 kernel) and the whole depth staged in one step, so a
+// workgroup waits for one round of global loads instead of k / GM_BK.
+#define GS_T 32
+#define GS_K 64
+__global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k, cplx alpha,
+                                                            const cplx *__restrict__ A, long lda,
+                                                            const cplx *__restrict__ B, long ldb, cplx beta,
+                                                            cplx *__restrict__ C, long ldc, int tiles_m) {
+  __shared__ cplx As[GS_K][GS_T];
+  __shared__ cplx Bs[GS_K][GS_T + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int row0 = (blockIdx.x % tiles_m) * GS_T, col0 = (blockIdx.x / tiles_m) * GS_T;
+#pragma unroll
+  for (int u = 0; u < GS_K * GS_T / 256; ++u) {
+    const int idx = tid + 256 * u;
+    const int ar = idx % GS_T, ak = idx / GS_T;  // A: row fastest (coalesced columns)
+    As[ak][ar] = (row0 + ar < m && ak < k) ? A[(row0 + ar) + (long)ak * lda] : cmk(0, 0);
+    const int bk = idx % GS_K, bc = idx / GS_K;  // B: k fastest (coalesced columns)
+    Bs[bk][bc] = (bk < k && col0 + bc < n) ? B[bk + (long)(col0 + bc) * ldb] : cmk(0, 0);
+  }
+  __syncthreads();
+  const int fq = lane >> 4, fi = lane & 15;
+  dbl4 accr = (dbl4){0, 0, 0, 0}, acci = (dbl4){0, 0, 0, 0};
+#pragma unroll 4
+  for (int k4 = 0; k4 < GS_K; k4 += 4) {
+    const cplx av = As[k4 + fq][wm * 16 + fi], bv = Bs[k4 + fq][wn * 16 + fi];
+    accr = mfma16(bv.x, av.x, accr);
+    acci = mfma16(bv.y, av.x, acci);
+    accr = mfma16(bv.y, -av.y, accr);
+    acci = mfma16(bv.x, av.y, acci);
+  }
+  // lane l, register r -> C(row fi, col 4 r + fq) of the wave's 16 x 16 block
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row0 + wm * 16 + fi, col = col0 + wn * 16 + 4 * r + fq;
+    if (row < m && col < n) {
+      cplx out = cmul(alpha, cmk(accr[r], acci[r]));
+      out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
+      C[row + (long)col * ldc] = out;
+    }
+  }
+}
+
 int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
                     int64_t ldb, cplx beta, cplx *C, int64_t ldc) {
   if (m <= 0 || n <= 0) return BM_OK;
+  if (BM_SHALLOW_GEMM && k <= GS_K && n <= 64) {
+    const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
+    const long tiles = (long)tm * tn;
+    if (tiles > 0x7fffffffL) return BM_E_ARG;
+    hipLaunchKernelGGL(zgemm_shallow_kernel, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda,
+                       B, (long)ldb, beta, C, (long)ldc, tm);
+    BM_HIP_TRY(hipGetLastError());
+    return BM_OK;
+  }
   const int tm = (m + GM_BM - 1) / GM_BM, tn = (n + GM_BN - 1) / GM_BN;
   const long tiles = (long)tm * tn;
   if (tiles > 0x7fffffffL) return BM_E_ARG;

@@ -65,7 +65,8 @@ def test_assembly_ordinary_entries(name, bnd, ph):
         assert err < 1e-12, (r0, c0, err)
 
 
-@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (130, 77, 45), (1, 3, 200), (257, 300, 129), (33, 1, 1000)])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (130, 77, 45), (1, 3, 200), (257, 300, 129), (33, 1, 1000),
+                                   (130, 64, 45), (2000, 33, 64), (95, 1, 7)])  # the last three: shallow kernel
 @pytest.mark.parametrize("beta", [0.0, 0.5 - 1.5j])
 def test_zgemm_vs_numpy(m, n, k, beta):
     rng = np.random.default_rng(m * 1000 + n + k)
