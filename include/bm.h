@@ -82,6 +82,13 @@ enum bm_precision {
                         refinement in bm_solve (mixed formulation)                 */
 };
 
+enum bm_quadrature {
+  BM_QUAD_KRESS = 0,  /* Kress' logarithmic splitting (default): spectral convergence  */
+  BM_QUAD_ZETA1 = 1   /* zeta-corrected trapezoid rule with one correction point, the
+                         lowest-order rule of Sec. 4: O(h) for N_k, the solution
+                         converges at O(1/N)                                          */
+};
+
 /* Maximum number of right-hand sides handled per internal pass; bm_solve and
  * bm_far_field accept any nrhs and loop over chunks of this size. */
 #define BM_MAX_NRHS 32
@@ -162,6 +169,19 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, i
  * Errors: BM_E_ARG (unknown precision, mixed precision for BM_ORDINARY, tol <= 0,
  * max_iter < 0). */
 int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_iter);
+
+/* Quadrature of the Nystrom discretisation used by the following bm_assemble
+ * calls (Sec. 4).  BM_QUAD_KRESS integrates the logarithmic and hypersingular
+ * parts of the kernels with Kress' weights (exact on trigonometric polynomials).
+ * BM_QUAD_ZETA1 uses the equispaced trapezoid rule on the full kernels with one
+ * local correction at the singular node: the weights that make the punctured
+ * rule exact on constants, 2 h ln(h / 2pi) for ln(4 sin^2((t - tau)/2)) and
+ * -h (N^2 - 1) / (24 pi) for the finite part of 1 / (8 pi sin^2((t - tau)/2)),
+ * h = 2 pi / N (the values of the zeta-function regularisation of those sums).
+ * The identity and zero blocks of eq. dis_mixedBM, and so Theorem thm:LU, hold
+ * for either rule.  The assembled blocks are invalidated (bm_assemble must
+ * run again).  Errors: BM_E_ARG (unknown quadrature). */
+int bm_set_quadrature(bm_problem *p, int32_t quadrature);
 
 /* Refinement statistics of the latest bm_solve (host pointers): the largest
  * number of refinement steps over its column chunks and the final

@@ -175,6 +175,37 @@ static void kress_weights_l(int N, long double *R, long double *T) {
   }
 }
 
+/* Zeta-corrected trapezoid weights with one correction point (the lowest-order
+ * rule of Sec. 4) for the same two integrals.  Off the singular node the plain
+ * trapezoid rule on the kernels: R_m = h ln(4 sin^2(pi m/N)), T_m = h / (8 pi
+ * sin^2(pi m/N)) (the singular part 1/(8 pi sin^2((t - tau)/2)) that T integrates).
+ * At the singular node the weight that makes the punctured rule exact on
+ * constants, from the finite sums
+ *   sum_{m=1}^{N-1} ln(2 sin(pi m/N)) = ln N,  sum_{m=1}^{N-1} 1/(4 sin^2(pi m/N)) = (N^2 - 1)/12
+ * and the exact integrals 0 (log kernel) and 0 (finite part of 1/(4 sin^2(u/2))):
+ *   R_0 = 2 h ln(h / (2 pi)),   T_0 = -h (N^2 - 1) / (24 pi),   h = 2 pi / N.
+ * (These are the values of the zeta-function regularisation: the punctured sum
+ * of ln|j h| is h ln(2 pi / h) because zeta'(0) = -ln(2 pi)/2, and of 1/(j h)^2 it
+ * is 2 zeta(2) / h^2 = pi^2 / (3 h^2), matching (N^2 - 1)/12 h to leading order.) */
+static void zeta_weights_l(int N, long double *R, long double *T) {
+  const long double h = 2.0L * PI_L / (long double)N;
+  R[0] = 2.0L * h * logl(h / (2.0L * PI_L));
+  T[0] = -h * ((long double)N * N - 1.0L) / (24.0L * PI_L);
+  for (int m = 1; m < N; ++m) {
+    const long double sn = sinl(PI_L * (long double)m / (long double)N);
+    R[m] = h * logl(4.0L * sn * sn);
+    T[m] = h / (8.0L * PI_L * sn * sn);
+  }
+}
+
+void orc_zeta_weights(int N, double *R, double *T) {
+  long double *r = (long double *)malloc(sizeof(long double) * N);
+  long double *t = (long double *)malloc(sizeof(long double) * N);
+  zeta_weights_l(N, r, t);
+  for (int m = 0; m < N; ++m) { R[m] = (double)r[m]; T[m] = (double)t[m]; }
+  free(r); free(t);
+}
+
 void orc_kress_weights(int N, double *R, double *T) {
   long double *r = (long double *)malloc(sizeof(long double) * N);
   long double *t = (long double *)malloc(sizeof(long double) * N);
@@ -293,13 +324,15 @@ static void op_entry(const geom_t *g, lcplx k, int i, int j, opent_t *o) {
   }
 }
 
+/* quad: 0 = Kress log-split weights, 1 = zeta-corrected trapezoid weights. */
 static int geom_init(geom_t *g, int N, const double *x, const double *dx,
-                     const double *ddx, const double *d3x) {
-  if (N < 4 || (N % 2) != 0) return -1;
+                     const double *ddx, const double *d3x, int quad) {
+  if (N < 4 || (N % 2) != 0 || quad < 0 || quad > 1) return -1;
   g->N = N; g->x = x; g->dx = dx; g->ddx = ddx; g->d3x = d3x;
   g->R = (long double *)malloc(sizeof(long double) * N);
   g->T = (long double *)malloc(sizeof(long double) * N);
-  kress_weights_l(N, g->R, g->T);
+  if (quad == 0) kress_weights_l(N, g->R, g->T);
+  else zeta_weights_l(N, g->R, g->T);
   return 0;
 }
 
@@ -309,9 +342,9 @@ static void geom_free(geom_t *g) { free(g->R); free(g->T); }
  * Any output pointer may be NULL. */
 int orc_layer_operators(int N, const double *x, const double *dx, const double *ddx,
                         const double *d3x, double kr, double ki,
-                        dcplx *S, dcplx *D, dcplx *Ds, dcplx *Nk) {
+                        dcplx *S, dcplx *D, dcplx *Ds, dcplx *Nk, int quad) {
   geom_t g;
-  if (geom_init(&g, N, x, dx, ddx, d3x)) return -1;
+  if (geom_init(&g, N, x, dx, ddx, d3x, quad)) return -1;
   lcplx k = (long double)kr + I * (long double)ki;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int i = 0; i < N; ++i) {
@@ -369,10 +402,10 @@ static void phys_init(phys_t *ph, const double *prm) {
  * the full matrix is too large).  out[s] = block(which[s]) entry (rows[s], cols[s]). */
 int orc_block_entries(int N, const double *x, const double *dx, const double *ddx,
                       const double *d3x, const double *prm, int ns, const int *which,
-                      const int *rows, const int *cols, dcplx *out) {
+                      const int *rows, const int *cols, dcplx *out, int quad) {
   geom_t g;
   phys_t ph;
-  if (geom_init(&g, N, x, dx, ddx, d3x)) return -1;
+  if (geom_init(&g, N, x, dx, ddx, d3x, quad)) return -1;
   phys_init(&ph, prm);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int s = 0; s < ns; ++s) out[s] = (dcplx)block_entry(&g, &ph, which[s], rows[s], cols[s]);
@@ -386,10 +419,10 @@ int orc_block_entries(int N, const double *x, const double *dx, const double *dd
  *   [ 0    I    M23 ]
  *   [ M31  M32  0   ]                                                          */
 int orc_build_mixed(int N, const double *x, const double *dx, const double *ddx,
-                    const double *d3x, const double *prm, dcplx *A) {
+                    const double *d3x, const double *prm, dcplx *A, int quad) {
   geom_t g;
   phys_t ph;
-  if (geom_init(&g, N, x, dx, ddx, d3x)) return -1;
+  if (geom_init(&g, N, x, dx, ddx, d3x, quad)) return -1;
   phys_init(&ph, prm);
   const size_t n3 = 3 * (size_t)N;
   memset(A, 0, sizeof(dcplx) * n3 * n3);
@@ -419,10 +452,10 @@ int orc_build_mixed(int N, const double *x, const double *dx, const double *ddx,
  *   [ M31            M32        ]
  *   [ D_k1 + I/2     -eps1 S_k1 ]                                              */
 int orc_build_ordinary(int N, const double *x, const double *dx, const double *ddx,
-                       const double *d3x, const double *prm, dcplx *A) {
+                       const double *d3x, const double *prm, dcplx *A, int quad) {
   geom_t g;
   phys_t ph;
-  if (geom_init(&g, N, x, dx, ddx, d3x)) return -1;
+  if (geom_init(&g, N, x, dx, ddx, d3x, quad)) return -1;
   phys_init(&ph, prm);
   const size_t n2 = 2 * (size_t)N;
 #pragma omp parallel for schedule(dynamic, 4)

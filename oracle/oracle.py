@@ -45,11 +45,12 @@ def lib():
             L = ctypes.CDLL(_LIB_PATH)
             L.orc_hankel01.argtypes = [ctypes.c_double, ctypes.c_double, _dptr]
             L.orc_kress_weights.argtypes = [ctypes.c_int, _dptr, _dptr]
+            L.orc_zeta_weights.argtypes = [ctypes.c_int, _dptr, _dptr]
             geo = [ctypes.c_int, _dptr, _dptr, _dptr, _dptr]
-            L.orc_layer_operators.argtypes = geo + [ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 4
-            L.orc_block_entries.argtypes = geo + [_dptr, ctypes.c_int, _iptr, _iptr, _iptr, ctypes.c_void_p]
-            L.orc_build_mixed.argtypes = geo + [_dptr, ctypes.c_void_p]
-            L.orc_build_ordinary.argtypes = geo + [_dptr, ctypes.c_void_p]
+            L.orc_layer_operators.argtypes = geo + [ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 4 + [ctypes.c_int]
+            L.orc_block_entries.argtypes = geo + [_dptr, ctypes.c_int, _iptr, _iptr, _iptr, ctypes.c_void_p, ctypes.c_int]
+            L.orc_build_mixed.argtypes = geo + [_dptr, ctypes.c_void_p, ctypes.c_int]
+            L.orc_build_ordinary.argtypes = geo + [_dptr, ctypes.c_void_p, ctypes.c_int]
             L.orc_rhs_plane_wave.argtypes = [ctypes.c_int, _dptr, _dptr, _dptr, ctypes.c_int,
                                              ctypes.c_int, _dptr, ctypes.c_void_p]
             L.orc_zgetrf.argtypes = [ctypes.c_int, ctypes.c_void_p, _iptr]
@@ -87,6 +88,9 @@ def hankel01(z):
     return out[..., 0], out[..., 1], out[..., 2], out[..., 3]
 
 
+QUADRATURES = {"kress": 0, "zeta": 1}
+
+
 def kress_weights(n_nodes: int):
     R = np.empty(n_nodes)
     T = np.empty(n_nodes)
@@ -94,13 +98,22 @@ def kress_weights(n_nodes: int):
     return R, T
 
 
-def layer_operators(boundary, k):
-    """S_k, D_k, D*_k, N_k as N x N matrices (Kress-split Nystrom)."""
+def zeta_weights(n_nodes: int):
+    """The one-point zeta-corrected trapezoid weights for the same two integrals."""
+    R = np.empty(n_nodes)
+    T = np.empty(n_nodes)
+    lib().orc_zeta_weights(n_nodes, _d(R), _d(T))
+    return R, T
+
+
+def layer_operators(boundary, k, quad="kress"):
+    """S_k, D_k, D*_k, N_k as N x N matrices (Nystrom; quad "kress": Kress log
+    split, "zeta": one-point zeta-corrected trapezoid rule)."""
     N = boundary.n_nodes
     mats = [np.empty((N, N), dtype=np.complex128) for _ in range(4)]
     keep, g = _geo(boundary)
     k = complex(k)
-    rc = lib().orc_layer_operators(*g, k.real, k.imag, *[_c(m) for m in mats])
+    rc = lib().orc_layer_operators(*g, k.real, k.imag, *[_c(m) for m in mats], QUADRATURES[quad])
     if rc:
         raise ValueError("invalid geometry")
     return tuple(mats)
@@ -109,7 +122,7 @@ def layer_operators(boundary, k):
 BLOCK_IDS = {"M13": 0, "M23": 1, "M31": 2, "M32": 3, "D1half": 4, "mEps1S1": 5}
 
 
-def block_entries(boundary, physics, which, rows, cols):
+def block_entries(boundary, physics, which, rows, cols, quad="kress"):
     """Entries of the named blocks at (rows[s], cols[s]), computed one by one."""
     which = np.ascontiguousarray([BLOCK_IDS[w] if isinstance(w, str) else int(w) for w in which],
                                  dtype=np.int32)
@@ -119,28 +132,28 @@ def block_entries(boundary, physics, which, rows, cols):
     keep, g = _geo(boundary)
     prm = physics.as_array()
     ip = lambda a: a.ctypes.data_as(_iptr)  # noqa: E731
-    lib().orc_block_entries(*g, _d(prm), rows.shape[0], ip(which), ip(rows), ip(cols), _c(out))
+    lib().orc_block_entries(*g, _d(prm), rows.shape[0], ip(which), ip(rows), ip(cols), _c(out), QUADRATURES[quad])
     return out
 
 
-def build_mixed(boundary, physics):
+def build_mixed(boundary, physics, quad="kress"):
     """Explicit 3N x 3N matrix [[I,0,M13],[0,I,M23],[M31,M32,0]]."""
     N = boundary.n_nodes
     A = np.empty((3 * N, 3 * N), dtype=np.complex128)
     keep, g = _geo(boundary)
     prm = physics.as_array()
-    if lib().orc_build_mixed(*g, _d(prm), _c(A)):
+    if lib().orc_build_mixed(*g, _d(prm), _c(A), QUADRATURES[quad]):
         raise ValueError("invalid geometry")
     return A
 
 
-def build_ordinary(boundary, physics):
+def build_ordinary(boundary, physics, quad="kress"):
     """Explicit 2N x 2N matrix [[M31, M32],[D_k1 + I/2, -eps1 S_k1]]."""
     N = boundary.n_nodes
     A = np.empty((2 * N, 2 * N), dtype=np.complex128)
     keep, g = _geo(boundary)
     prm = physics.as_array()
-    if lib().orc_build_ordinary(*g, _d(prm), _c(A)):
+    if lib().orc_build_ordinary(*g, _d(prm), _c(A), QUADRATURES[quad]):
         raise ValueError("invalid geometry")
     return A
 

@@ -20,13 +20,14 @@ BM_MIXED, BM_ORDINARY = 0, 1
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
 BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT, BM_E_DOMAIN = -7, -8, -9, -10
 BM_PREC_FP64, BM_PREC_MIXED = 0, 1
+BM_QUAD_KRESS, BM_QUAD_ZETA1 = 0, 1
 BM_MAX_NRHS = 32
 
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
             "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
-            "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments"]
+            "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -109,6 +110,7 @@ def lib():
         L.bm_server_destroy.argtypes = [vp]
         L.bm_server_destroy.restype = None
         L.bm_block_moments.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, dp, vp]
+        L.bm_set_quadrature.argtypes = [vp, i32]
         L.bm_strerror.argtypes = [ctypes.c_int]
         L.bm_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -249,6 +251,12 @@ class Problem:
         """bm_set_precision: "fp64" or "mixed" (FP32 matrix cores + FP64 refinement)."""
         code = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED}[precision]
         check(lib().bm_set_precision(self._h, code, float(tol), int(max_iter)), "bm_set_precision")
+
+    def set_quadrature(self, quadrature: str = "kress"):
+        """bm_set_quadrature: "kress" (log splitting) or "zeta" (one-point
+        zeta-corrected trapezoid rule); the problem must be assembled again."""
+        code = {"kress": BM_QUAD_KRESS, "zeta": BM_QUAD_ZETA1}[quadrature]
+        check(lib().bm_set_quadrature(self._h, code), "bm_set_quadrature")
 
     def refine_stats(self):
         """(refinement steps, final max relative residual) of the latest solve."""

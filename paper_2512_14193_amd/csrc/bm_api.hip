@@ -102,7 +102,8 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
     free_problem(p);
     return BM_E_HIP;
   }
-  int rc = bm_launch_weights(p->stream, n, p->wts);
+  p->quad = BM_QUAD_KRESS;
+  int rc = bm_launch_weights(p->stream, n, p->wts, p->quad);
   if (rc) {
     free_problem(p);
     return rc;
@@ -344,6 +345,16 @@ int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_i
   p->prec = precision;
   p->ir_tol = tol;
   p->ir_maxit = max_iter;
+  return BM_OK;
+}
+
+int bm_set_quadrature(bm_problem *p, int32_t quadrature) {
+  if (!p) return BM_E_ARG;
+  if (quadrature != BM_QUAD_KRESS && quadrature != BM_QUAD_ZETA1) return BM_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  if (int rc = bm_launch_weights(p->stream, p->n, p->wts, quadrature)) return rc;
+  p->quad = quadrature;
+  if (p->state > BM_ST_CREATED) p->state = BM_ST_CREATED;  // blocks of the old rule are stale
   return BM_OK;
 }
 

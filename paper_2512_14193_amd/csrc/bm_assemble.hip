@@ -90,8 +90,37 @@ __global__ __launch_bounds__(256) void weights_kernel(int N, double *wts) {
   }
 }
 
-int bm_launch_weights(hipStream_t s, int n, double *wts) {
-  hipLaunchKernelGGL(weights_kernel, dim3(n), dim3(256), 0, s, n, wts);
+// Zeta-corrected trapezoid weights with one correction point (the lowest-order
+// rule of Sec. 4) in place of R and T: off the singular node the plain trapezoid
+// rule on the same kernels, R_m = h L_m and T_m = h C_m / (4 pi) (T integrates
+// 1/(8 pi sin^2((t - tau)/2))); at the singular node the weight that makes the
+// punctured rule exact on constants, from sum_{m>0} ln(2 sin(pi m/N)) = ln N and
+// sum_{m>0} 1/(4 sin^2(pi m/N)) = (N^2 - 1)/12:
+//   R_0 = 2 h ln(h / (2 pi)),   T_0 = -h (N^2 - 1) / (24 pi),   h = 2 pi / N.
+__global__ void zeta_weights_kernel(int N, double *wts) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const double h = 2.0 * BM_PI / N;
+  if (m == 0) {
+    wts[0] = 2.0 * h * log(h / (2.0 * BM_PI));
+    wts[N] = -h * ((double)N * N - 1.0) / (24.0 * BM_PI);
+    wts[2 * N] = 0.0;
+    wts[3 * N] = 0.0;
+  } else {
+    const double sn = sinpi((double)m / (double)N);
+    const double L = log(4.0 * sn * sn), C = 1.0 / (2.0 * sn * sn);
+    wts[m] = h * L;
+    wts[N + m] = h * C / (4.0 * BM_PI);
+    wts[2 * N + m] = L;
+    wts[3 * N + m] = C;
+  }
+}
+
+int bm_launch_weights(hipStream_t s, int n, double *wts, int quad) {
+  if (quad == BM_QUAD_ZETA1)
+    hipLaunchKernelGGL(zeta_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, wts);
+  else
+    hipLaunchKernelGGL(weights_kernel, dim3(n), dim3(256), 0, s, n, wts);
   BM_HIP_TRY(hipGetLastError());
   return bm_hankel_init();
 }

@@ -138,6 +138,7 @@ struct bm_problem {
   bm_getrf_ws *gws;
 
   // precision of the factorisation (BM_PREC_*) and the FP64 refinement of bm_solve
+  int quad;             // BM_QUAD_*: weights in wts
   int prec;
   int factored_prec;    // precision of the factors held now
   double ir_tol;
@@ -156,7 +157,7 @@ struct bm_problem {
 // ---------------------------------------------------------------------------
 // internal launchers (all enqueue on `s` and return a bm_status)
 // ---------------------------------------------------------------------------
-int bm_launch_weights(hipStream_t s, int n, double *wts);
+int bm_launch_weights(hipStream_t s, int n, double *wts, int quad);  // quad: BM_QUAD_*
 int bm_launch_assemble(bm_problem *p, const bm_geometry *g);
 int bm_launch_rhs_plane_wave(bm_problem *p, int nrhs, const double *theta, cplx *B, int64_t ldb);
 int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int nang, const double *theta,
