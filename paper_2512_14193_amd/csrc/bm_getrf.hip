@@ -39,7 +39,7 @@
 // agent-scope store, and readers poll each word with agent-scope loads until it
 // differs from the pattern.  So the data itself is the synchronisation: no fence,
 // no counter, one round trip per column (a reader takes the headers, then the
-// winner's row, which has arrived with its header).
+// winner's row and the diagonal row, written right after the header).
 // ---------------------------------------------------------------------------
 #define PANEL_PMAX 256            // max workgroups of a panel launch
 #define SENT 0xFFFFFFFFFFFFFFFFULL  // empty exchange word (all ones)
@@ -175,10 +175,12 @@ __device__ inline cplx pivot_recip(cplx u) {
 // that decides the pivots, without workgroup barriers; wavefronts 1 .. SNB apply
 // the bulk of each rank-1 update one step behind it.  Per column c:
 //   wavefront 0: receives the P record headers of column c, selects the winner p
-//   and fetches its row, exchanges rows j + c and p, scales column c (the
-//   multipliers l_r = a_rc / u_c), updates column c + 1 and finds the
-//   workgroup's candidate for it, publishes that record (the candidate row
-//   completed on the fly for columns > c + 1) and then releases pivot c to the
+//   and fetches its row and the diagonal row; in registers it exchanges rows
+//   j + c and p, scales column c (the multipliers l_r = a_rc / u_c), updates
+//   column c + 1 and finds the workgroup's candidate for it, whose header it
+//   publishes at once (the header is what every reader waits for); only then
+//   come the LDS writes of the step and the candidate and diagonal rows
+//   (completed on the fly for columns > c + 1), and pivot c is released to the
 //   bulk wavefronts; it keeps columns c and c + 1 of its rows in registers;
 //   wavefronts 1 .. SNB: subtract l_r u_cc from columns cc >= c + 2 and count
 //   themselves done; wavefront 0 waits for that count before it touches rows or
@@ -237,9 +239,13 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         }
       }
     };
-    // records of column cc: header and candidate row lr, diagonal row; columns > cc
-    // still owe the update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
-    auto publish = [&](int cc, double v, int lr, cplx pr) __attribute__((always_inline)) {
+    // records of column cc: the header (value, row) as soon as the candidate is known
+    auto publish_head = [&](int cc, double v, int lr) __attribute__((always_inline)) {
+      if (lane == 0) rec_store(rs, cc * cstride + g * rstr, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
+    };
+    // then the candidate row lr and the diagonal row; columns > cc still owe the
+    // update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
+    auto publish_rows = [&](int cc, int lr, cplx pr) __attribute__((always_inline)) {
       const int base = cc * cstride;
       const int sc = base + g * rstr;
       const bool late = (cc > 0) && lane > cc;
@@ -254,8 +260,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         y = pan[lane * LDP + (int)ld];
         if (late) y = csub(y, cmul(pan[(cc - 1) * LDP + (int)ld], pr));
       }
-      if (col_ok) rec_store(rs, sc + 1 + lane, x);
-      if (lane == 0) rec_store(rs, sc, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
+      if (col_ok && lr >= 0) rec_store(rs, sc + 1 + lane, x);
       if (col_ok && has_d) rec_store(rs, base + P * rstr + lane, y);
     };
     cplx xc[RPL];  // column c of the workgroup's rows
@@ -265,7 +270,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       double v;
       int lr;
       cand(xc, (long)j - 1, v, lr);
-      publish(0, v, lr, cmk(0, 0));
+      publish_head(0, v, lr);
+      publish_rows(0, lr, cmk(0, 0));
     }
     // interchange bookkeeping (workgroup 0): lane l holds the source row of panel
     // position j + l, and of the l-th further row touched by the interchanges
@@ -274,26 +280,16 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
     for (int c = 0; c < jb; ++c) {
       const long gc = (long)j + c;
       const int base = c * cstride;
-      // receive the headers (lanes < P) and the diagonal row; all loads issued
-      // before any is checked
-      bm_v4i vh, vd;
+      // receive the headers (lanes < P)
+      bm_v4i vh;
       const int eh = (lane < P) ? base + lane * rstr : -1;
-      const int ed = col_ok ? base + P * rstr + lane : -1;
       if (eh >= 0) vh = rec_load(rs, eh);
-      if (ed >= 0) vd = rec_load(rs, ed);
       {
         const unsigned long long t0 = wall_clock64();
         for (;;) {
-          bool all = true;
-          if (eh >= 0 && rec_empty(vh)) {
-            all = false;
-            vh = rec_load(rs, eh);
-          }
-          if (ed >= 0 && rec_empty(vd)) {
-            all = false;
-            vd = rec_load(rs, ed);
-          }
+          const bool all = eh < 0 || !rec_empty(vh);
           if (__all(all)) break;
+          if (!all) vh = rec_load(rs, eh);
           if (!ok || wait_expired(t0)) {
             if (ok) atomicOr(dev_err, 1);
             ok = false;
@@ -339,8 +335,30 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         pw = gc;
       }
       const long p = pw;
-      const cplx dr = col_ok ? rec_value(vd) : cmk(0, 0);
-      const cplx pr = (ww < 0 || !col_ok) ? dr : rec_poll(rs, base + ww * rstr + 1 + lane, dev_err, ok);
+      // the winner's row and the diagonal row, both loads in flight together
+      cplx dr = cmk(0, 0), pr;
+      {
+        const int ed = col_ok ? base + P * rstr + lane : -1;
+        const int er = (col_ok && ww >= 0) ? base + ww * rstr + 1 + lane : -1;
+        bm_v4i vd, vr;
+        if (ed >= 0) vd = rec_load(rs, ed);
+        if (er >= 0) vr = rec_load(rs, er);
+        const unsigned long long t0 = wall_clock64();
+        for (;;) {
+          const bool okd = ed < 0 || !rec_empty(vd), okr = er < 0 || !rec_empty(vr);
+          if (__all(okd && okr)) break;
+          if (!okd) vd = rec_load(rs, ed);
+          if (!okr) vr = rec_load(rs, er);
+          if (!ok || wait_expired(t0)) {
+            if (ok) atomicOr(dev_err, 1);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (ed >= 0) dr = rec_value(vd);
+        pr = (er >= 0) ? rec_value(vr) : dr;
+      }
       // the bulk wavefronts must have finished the previous pivot (columns >= c + 1)
       if (c >= 1 && c - 1 <= jb - 3) {
         const unsigned long long t0 = wall_clock64();
@@ -353,45 +371,54 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      // row interchange: row gc <- pivot row, row p <- old row gc (in LDS and in
-      // the register copy of column c)
+      // row interchange (row gc <- pivot row, row p <- old row gc), multipliers of
+      // column c and the update of column c + 1, first in registers only: the
+      // candidate's header for column c + 1 goes out before any LDS write
       const long lg = gc - r0, lp = p - r0;
-      const cplx pc = readlane_c(pr, c), dcv = readlane_c(dr, c);
-      if (p != gc) {
-        if (col_ok) {
-          if (lg >= 0 && lg < nv) pan[lane * LDP + (int)lg] = pr;
-          if (lp >= 0 && lp < nv) pan[lane * LDP + (int)lp] = dr;
-        }
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-          xc[k] = csel(lane + 64 * k == (int)lg, pc, xc[k]);
-          xc[k] = csel(lane + 64 * k == (int)lp, dcv, xc[k]);
-        }
-      }
-      if (col_ok) urow[c & 1][lane] = pr;
-      // multipliers of column c (rows below the pivot), update of column c + 1
-      const cplx ip = (vw == 0.0) ? cmk(0, 0) : pivot_recip(pc);
       const bool have_next = (c + 1 < jb);
-      const cplx u1 = readlane_c(pr, have_next ? c + 1 : c);
-      cplx x1[RPL];
+      const cplx pc = readlane_c(pr, c), dcv = readlane_c(dr, c);
+      const cplx u1 = readlane_c(pr, have_next ? c + 1 : c), d1 = readlane_c(dr, have_next ? c + 1 : c);
+      cplx x1[RPL], lv[RPL];
 #pragma unroll
       for (int k = 0; k < RPL; ++k) x1[k] = have_next ? pan[(c + 1) * LDP + lane + 64 * k] : cmk(0, 0);
+      if (p != gc) {
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int r = lane + 64 * k;
+          xc[k] = csel(r == (int)lg, pc, xc[k]);
+          xc[k] = csel(r == (int)lp, dcv, xc[k]);
+          x1[k] = csel(r == (int)lg, u1, x1[k]);
+          x1[k] = csel(r == (int)lp, d1, x1[k]);
+        }
+      }
+      const cplx ip = (vw == 0.0) ? cmk(0, 0) : pivot_recip(pc);
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        lv[k] = cmul(xc[k], ip);
+        if (r < nv && r0 + r > gc) x1[k] = csub(x1[k], cmul(lv[k], u1));
+      }
+      double v = -1.0;
+      int lr = -1;
+      if (have_next) {
+        cand(x1, gc, v, lr);
+        publish_head(c + 1, v, lr);
+      }
+      // now LDS: the interchanged rows, the multipliers, column c + 1, the pivot row
+      if (p != gc && col_ok) {
+        if (lg >= 0 && lg < nv) pan[lane * LDP + (int)lg] = pr;
+        if (lp >= 0 && lp < nv) pan[lane * LDP + (int)lp] = dr;
+      }
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
         if (r < nv && r0 + r > gc) {
-          const cplx l = cmul(xc[k], ip);
-          pan[c * LDP + r] = l;
-          x1[k] = csub(x1[k], cmul(l, u1));
+          pan[c * LDP + r] = lv[k];
           if (have_next) pan[(c + 1) * LDP + r] = x1[k];
         }
       }
-      if (have_next) {
-        double v;
-        int lr;
-        cand(x1, gc, v, lr);
-        publish(c + 1, v, lr, pr);
-      }
+      if (col_ok) urow[c & 1][lane] = pr;
+      if (have_next) publish_rows(c + 1, lr, pr);
       // release pivot c to the bulk wavefronts
       if (lane == 0) __hip_atomic_store(&s_ready, c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
