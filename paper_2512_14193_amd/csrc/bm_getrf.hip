@@ -181,10 +181,11 @@ __device__ inline cplx pivot_recip(cplx u) {
 //   publishes at once (the header is what every reader waits for); only then
 //   come the LDS writes of the step and the candidate and diagonal rows
 //   (completed on the fly for columns > c + 1), and pivot c is released to the
-//   bulk wavefronts; it keeps columns c and c + 1 of its rows in registers;
-//   wavefronts 1 .. SNB: subtract l_r u_cc from columns cc >= c + 2 and count
-//   themselves done; wavefront 0 waits for that count before it touches rows or
-//   columns of the next step.
+//   bulk wavefronts; it also applies pivot c to column c + 2 and keeps that
+//   column in registers, so the next step starts without touching LDS;
+//   wavefronts 1 .. SNB: subtract l_r u_cc from columns cc >= c + 3 and count
+//   themselves done; wavefront 0 waits for that count before it writes rows or
+//   reads columns of the next step.
 // Exchange layout per column c (rs = record stride, cstride = complex values per column):
 //   slots[c * cstride + g * rs]  record of workgroup g: (value, row), then the row
 //   slots[c * cstride + P * rs]  the diagonal row j + c, by its owner
@@ -263,9 +264,12 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       if (col_ok && lr >= 0) rec_store(rs, sc + 1 + lane, x);
       if (col_ok && has_d) rec_store(rs, base + P * rstr + lane, y);
     };
-    cplx xc[RPL];  // column c of the workgroup's rows
+    cplx xc[RPL], xn[RPL];  // columns c and c + 1 of the workgroup's rows
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) xc[k] = pan[lane + 64 * k];
+    for (int k = 0; k < RPL; ++k) {
+      xc[k] = pan[lane + 64 * k];
+      xn[k] = (jb > 1) ? pan[LDP + lane + 64 * k] : cmk(0, 0);
+    }
     {
       double v;
       int lr;
@@ -359,28 +363,17 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         if (ed >= 0) dr = rec_value(vd);
         pr = (er >= 0) ? rec_value(vr) : dr;
       }
-      // the bulk wavefronts must have finished the previous pivot (columns >= c + 1)
-      if (c >= 1 && c - 1 <= jb - 3) {
-        const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&s_bulk, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < SNB * c) {
-          if (!ok || wait_expired(t0)) {
-            if (ok) atomicOr(dev_err, 1);
-            ok = false;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
       // row interchange (row gc <- pivot row, row p <- old row gc), multipliers of
-      // column c and the update of column c + 1, first in registers only: the
-      // candidate's header for column c + 1 goes out before any LDS write
+      // column c and the update of column c + 1 (held in registers since the last
+      // step), in registers only: the candidate's header for column c + 1 goes out
+      // before any LDS access
       const long lg = gc - r0, lp = p - r0;
-      const bool have_next = (c + 1 < jb);
+      const bool have_next = (c + 1 < jb), have_next2 = (c + 2 < jb);
       const cplx pc = readlane_c(pr, c), dcv = readlane_c(dr, c);
       const cplx u1 = readlane_c(pr, have_next ? c + 1 : c), d1 = readlane_c(dr, have_next ? c + 1 : c);
       cplx x1[RPL], lv[RPL];
 #pragma unroll
-      for (int k = 0; k < RPL; ++k) x1[k] = have_next ? pan[(c + 1) * LDP + lane + 64 * k] : cmk(0, 0);
+      for (int k = 0; k < RPL; ++k) x1[k] = xn[k];
       if (p != gc) {
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
@@ -404,16 +397,39 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         cand(x1, gc, v, lr);
         publish_head(c + 1, v, lr);
       }
-      // now LDS: the interchanged rows, the multipliers, column c + 1, the pivot row
+      // the bulk wavefronts must have finished the previous pivot (columns >= c + 2)
+      if (c >= 1 && c - 1 <= jb - 3) {
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(&s_bulk, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < SNB * c) {
+          if (!ok || wait_expired(t0)) {
+            if (ok) atomicOr(dev_err, 1);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      // now LDS: the interchanged rows; column c + 2 with pivot c applied, kept in
+      // registers for the next step (in LDS it stays one pivot behind, like the
+      // columns the bulk wavefronts update); the multipliers; column c + 1 from the
+      // pivot row down (the pivot row's entry is final); the pivot row
       if (p != gc && col_ok) {
         if (lg >= 0 && lg < nv) pan[lane * LDP + (int)lg] = pr;
         if (lp >= 0 && lp < nv) pan[lane * LDP + (int)lp] = dr;
       }
+      const cplx u2 = readlane_c(pr, have_next2 ? c + 2 : c);
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
-        if (r < nv && r0 + r > gc) {
-          pan[c * LDP + r] = lv[k];
+        cplx x2 = have_next2 ? pan[(c + 2) * LDP + r] : cmk(0, 0);
+        if (r < nv && r0 + r > gc) x2 = csub(x2, cmul(lv[k], u2));
+        xn[k] = x2;
+      }
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        if (r < nv && r0 + r >= gc) {
+          if (r0 + r > gc) pan[c * LDP + r] = lv[k];
           if (have_next) pan[(c + 1) * LDP + r] = x1[k];
         }
       }
@@ -469,7 +485,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       if (lane == 0) swp[0] = n1 + __popcll(b2);
     }
   } else {
-    // bulk wavefronts: pivot c's update of columns >= c + 2, one step behind; the
+    // bulk wavefronts: pivot c's update of columns >= c + 3, one step behind; the
     // loads of a batch of BU columns are issued before any store
     constexpr int NG = (SNB * 64) / RPW;  // column groups
     constexpr int BU = 4;
@@ -489,7 +505,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       }
       if (grp < NG && r < nv && r0 + r > (long)j + c) {
         const cplx l = pan[c * LDP + r];
-        for (int cc0 = c + 2 + grp; cc0 < jb; cc0 += NG * BU) {
+        for (int cc0 = c + 3 + grp; cc0 < jb; cc0 += NG * BU) {
           cplx av[BU], uv[BU];
 #pragma unroll
           for (int b = 0; b < BU; ++b) {
