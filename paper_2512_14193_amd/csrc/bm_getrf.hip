@@ -555,55 +555,95 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 // forward substitution with the unit lower L11 (in LDS) on rows j .. j + jb - 1,
 // lane = row, two columns per wavefront, the solved value of row c broadcast from
 // lane c by readlane.
+// The kernel sits on the path from one panel to the next, so its global loads are
+// issued in batches (each thread's loads of a phase are in flight together):
+// the interchange pairs with L11 and the block rows, then the interchange
+// sources.  Work items are mapped by fixed strides (64 rows, 2 LU_NB pairs), with
+// no division; every load is issued unconditionally (an item outside the block
+// reads the block's first element) so that no branch separates the loads, and
+// only the stores are predicated.
 // ---------------------------------------------------------------------------
 #define SWAP_COLS 16
 #define ST_CW 8
-#define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB + 2 * LU_NB * ST_CW) * sizeof(cplx))
+#define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
+#define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB) * sizeof(cplx))
+typedef double st_v2 __attribute__((ext_vector_type(2)));  // a complex value in flight (kept in registers)
+__device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
+__device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
 
 __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int lcols, int c0, int c1,
                                                         const int32_t *swp, int nleft) {
   extern __shared__ cplx sm[];
+  __shared__ int s_pair[2 * ST_NPAIR];  // (dst, src) rows of the interchange
   const int np = swp[0];
   const int tid = threadIdx.x;
   if ((int)blockIdx.x < nleft) {
     if (np == 0) return;
-    cplx *buf = sm;  // [2 LU_NB][SWAP_COLS]
-    const int cbase = blockIdx.x * SWAP_COLS;
-    for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
-      const int e = idx % np, col = cbase + idx / np;
-      if (col < lcols) buf[idx] = A[swp[2 + 2 * e] + (long)col * lda];
-    }
+    if (tid < 2 * np) s_pair[tid] = swp[1 + tid];
     __syncthreads();
-    for (int idx = tid; idx < np * SWAP_COLS; idx += 256) {
-      const int e = idx % np, col = cbase + idx / np;
-      if (col < lcols) A[swp[1 + 2 * e] + (long)col * lda] = buf[idx];
+    constexpr int LPT = ST_NPAIR * SWAP_COLS / 256;
+    const int cbase = blockIdx.x * SWAP_COLS;
+    st_v2 v[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = tid + 256 * q, e = idx % ST_NPAIR, col = cbase + idx / ST_NPAIR;
+      const bool ok = e < np && col < lcols;
+      v[q] = st_ld(A, ok ? s_pair[2 * e + 1] + (long)col * lda : (long)j);
+    }
+    __syncthreads();  // every source read before any row is overwritten
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = tid + 256 * q, e = idx % ST_NPAIR, col = cbase + idx / ST_NPAIR;
+      if (e < np && col < lcols) st_st(A, s_pair[2 * e] + (long)col * lda, v[q]);
     }
     return;
   }
   const int cw0 = c0 + ((int)blockIdx.x - nleft) * ST_CW;
   const int ncw = (c1 - cw0 < ST_CW) ? c1 - cw0 : ST_CW;
-  cplx *Ls = sm;                     // L11, column-major, ld LU_NB
-  cplx *X = Ls + LU_NB * LU_NB;      // rows j .. j + jb - 1 of the columns, [ST_CW][LU_NB]
-  cplx *buf = X + ST_CW * LU_NB;     // interchange sources, [2 LU_NB][ST_CW]
-  for (int idx = tid; idx < jb * jb; idx += 256) {
-    const int r = idx % jb, c = idx / jb;
-    Ls[c * LU_NB + r] = A[(j + r) + (long)(j + c) * lda];
+  cplx *Ls = sm;                 // L11, column-major, ld LU_NB
+  cplx *X = Ls + LU_NB * LU_NB;  // rows j .. j + jb - 1 of the columns, [ST_CW][LU_NB]
+  constexpr int LPT_L = LU_NB * LU_NB / 256, LPT_X = ST_CW * LU_NB / 256, LPT_S = ST_NPAIR * ST_CW / 256;
+  // phase 1: the pairs, L11 and the block rows, all in flight together
+  const long a0 = (long)j + (long)j * lda;  // L11's first element: the address of items outside the block
+  const int pr_v = swp[1 + ((tid < 2 * np) ? tid : 0)];
+  st_v2 lv[LPT_L], xv[LPT_X];
+#pragma unroll
+  for (int q = 0; q < LPT_L; ++q) {
+    const int idx = tid + 256 * q, r = idx % LU_NB, c = idx / LU_NB;
+    lv[q] = st_ld(A, (r < jb && c < jb) ? (j + r) + (long)(j + c) * lda : a0);
   }
-  for (int idx = tid; idx < jb * ST_CW; idx += 256) {
-    const int r = idx % jb, cl = idx / jb;
-    if (cl < ncw) X[cl * LU_NB + r] = A[(j + r) + (long)(cw0 + cl) * lda];
+#pragma unroll
+  for (int q = 0; q < LPT_X; ++q) {
+    const int idx = tid + 256 * q, r = idx % LU_NB, cl = idx / LU_NB;
+    xv[q] = st_ld(A, (r < jb && cl < ncw) ? (j + r) + (long)(cw0 + cl) * lda : a0);
   }
-  for (int idx = tid; idx < np * ST_CW; idx += 256) {
-    const int e = idx % np, cl = idx / np;
-    if (cl < ncw) buf[idx] = A[swp[2 + 2 * e] + (long)(cw0 + cl) * lda];
-  }
+  if (tid < 2 * np) s_pair[tid] = pr_v;
   __syncthreads();
-  for (int idx = tid; idx < np * ST_CW; idx += 256) {
-    const int e = idx % np, cl = idx / np;
-    if (cl < ncw) {
-      const int dst = swp[1 + 2 * e];
-      if (dst < j + jb) X[cl * LU_NB + (dst - j)] = buf[idx];
-      else A[dst + (long)(cw0 + cl) * lda] = buf[idx];
+  // phase 2: the interchange sources
+  st_v2 sv[LPT_S];
+#pragma unroll
+  for (int q = 0; q < LPT_S; ++q) {
+    const int idx = tid + 256 * q, e = idx % ST_NPAIR, cl = idx / ST_NPAIR;
+    sv[q] = st_ld(A, (e < np && cl < ncw) ? s_pair[2 * e + 1] + (long)(cw0 + cl) * lda : a0);
+  }
+#pragma unroll
+  for (int q = 0; q < LPT_L; ++q) {
+    const int idx = tid + 256 * q, r = idx % LU_NB, c = idx / LU_NB;
+    if (r < jb && c < jb) st_st(Ls, c * LU_NB + r, lv[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < LPT_X; ++q) {
+    const int idx = tid + 256 * q, r = idx % LU_NB, cl = idx / LU_NB;
+    if (r < jb && cl < ncw) st_st(X, cl * LU_NB + r, xv[q]);
+  }
+  __syncthreads();  // every source read (and X filled) before any destination is written
+#pragma unroll
+  for (int q = 0; q < LPT_S; ++q) {
+    const int idx = tid + 256 * q, e = idx % ST_NPAIR, cl = idx / ST_NPAIR;
+    if (e < np && cl < ncw) {
+      const int dst = s_pair[2 * e];
+      if (dst < j + jb) st_st(X, cl * LU_NB + (dst - j), sv[q]);
+      else st_st(A, dst + (long)(cw0 + cl) * lda, sv[q]);
     }
   }
   __syncthreads();
