@@ -28,6 +28,13 @@
 #include "bm_internal.h"
 #include "bm_trinv.h"
 
+// A complex value as a clang vector: arrays of these in loops the compiler unrolls
+// stay in registers (arrays of the HIP vector struct went to scratch memory), so a
+// thread's batch of global loads is in flight together.
+typedef double st_v2 __attribute__((ext_vector_type(2)));
+__device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
+__device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
+
 // ---------------------------------------------------------------------------
 // 1. panel factorisation
 //
@@ -208,9 +215,23 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
   const int nv = (N - r0 >= RPW) ? RPW : ((N - r0 > 0) ? (int)(N - r0) : 0);
   bool ok = true;
 
-  for (int idx = tid; idx < RPW * jb; idx += SNT) {
-    const int r = idx % RPW, c = idx / RPW;
-    pan[c * LDP + r] = (r < nv) ? A[(r0 + r) + (long)(j + c) * lda] : cmk(0, 0);
+  {
+    // the workgroup's block of the panel into LDS: each thread's loads in one
+    // batch (unconditional, an item outside the block reads the panel's first
+    // element), then the LDS stores
+    constexpr int PT = (RPW * LU_NB + SNT - 1) / SNT;
+    const long a0 = (long)j + (long)j * lda;
+    st_v2 v[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int idx = tid + SNT * q, r = idx % RPW, c = idx / RPW;
+      v[q] = st_ld(A, (r < nv && c < jb) ? (r0 + r) + (long)(j + c) * lda : a0);
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int idx = tid + SNT * q, r = idx % RPW, c = idx / RPW;
+      if (c < jb) st_st(pan, c * LDP + r, (r < nv) ? v[q] : st_v2{0.0, 0.0});
+    }
   }
   if (tid == 0) {
     s_ready = -1;
@@ -567,9 +588,6 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #define ST_CW 8
 #define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
 #define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB) * sizeof(cplx))
-typedef double st_v2 __attribute__((ext_vector_type(2)));  // a complex value in flight (kept in registers)
-__device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
-__device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
 
 __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int lcols, int c0, int c1,
                                                         const int32_t *swp, int nleft) {
