@@ -28,13 +28,6 @@
 #include "bm_internal.h"
 #include "bm_trinv.h"
 
-// A complex value as a clang vector: arrays of these in loops the compiler unrolls
-// stay in registers (arrays of the HIP vector struct went to scratch memory), so a
-// thread's batch of global loads is in flight together.
-typedef double st_v2 __attribute__((ext_vector_type(2)));
-__device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
-__device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
-
 // ---------------------------------------------------------------------------
 // 1. panel factorisation
 //

@@ -95,6 +95,15 @@ __device__ inline void st_cplx_agent(cplx *p, cplx v) {
 __device__ inline bool wait_expired(unsigned long long t0) { return wall_clock64() - t0 > (unsigned long long)BM_WAIT_TICKS; }
 
 __device__ inline double l1abs(cplx v) { return fabs(v.x) + fabs(v.y); }
+
+// A complex value as a clang vector: arrays of these in loops the compiler unrolls
+// stay in registers (arrays of the HIP vector struct can go to scratch memory), so
+// a thread's batch of global loads is in flight together.  Batched loads are
+// issued unconditionally (items outside a block read a valid stand-in address)
+// so that no branch separates them; only the stores are predicated.
+typedef double st_v2 __attribute__((ext_vector_type(2)));
+__device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
+__device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
 // candidate order: larger value wins, then the smaller row
 __device__ inline bool better(double v, long g, double bv, long bg) {
   return (v > bv) || (v == bv && g >= 0 && (bg < 0 || g < bg));

@@ -162,7 +162,21 @@ if constexpr (M3) {
     __syncthreads();
   }
 
-  // epilogue: lane l, register r -> C(row fi, col 4 r + fq) of each 16 x 16 block
+  // epilogue: lane l, register r -> C(row fi, col 4 r + fq) of each 16 x 16 block;
+  // with beta != 0 the sixteen C loads go out together first
+  st_v2 cin[2][2][4];
+  if constexpr (!BETA0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wm * 32 + a * 16 + fi;
+          const int col = col0 + wn * 32 + b * 16 + 4 * r + fq;
+          cin[a][b][r] = st_ld(C, (row < m && col < n) ? row + (long)col * ldc : 0);
+        }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -180,7 +194,7 @@ if constexpr (M3) {
             v = cmk(accr[a][b][r], acci[a][b][r]);
           }
           cplx out = cmul(alpha, v);
-          if (!BETA0) out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
+          if constexpr (!BETA0) out = cadd(out, cmul(beta, cmk(cin[a][b][r].x, cin[a][b][r].y)));
           C[row + (long)col * ldc] = out;
         }
       }
@@ -201,13 +215,24 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int row0 = (blockIdx.x % tiles_m) * GS_T, col0 = (blockIdx.x / tiles_m) * GS_T;
+  constexpr int GU = GS_K * GS_T / 256;
+  st_v2 av_[GU], bv_[GU];  // every load of the stage in flight together
 #pragma unroll
-  for (int u = 0; u < GS_K * GS_T / 256; ++u) {
+  for (int u = 0; u < GU; ++u) {
     const int idx = tid + 256 * u;
     const int ar = idx % GS_T, ak = idx / GS_T;  // A: row fastest (coalesced columns)
-    As[ak][ar] = (row0 + ar < m && ak < k) ? A[(row0 + ar) + (long)ak * lda] : cmk(0, 0);
+    av_[u] = st_ld(A, (row0 + ar < m && ak < k) ? (row0 + ar) + (long)ak * lda : 0);
     const int bk = idx % GS_K, bc = idx / GS_K;  // B: k fastest (coalesced columns)
-    Bs[bk][bc] = (bk < k && col0 + bc < n) ? B[bk + (long)(col0 + bc) * ldb] : cmk(0, 0);
+    bv_[u] = st_ld(B, (bk < k && col0 + bc < n) ? bk + (long)(col0 + bc) * ldb : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    const int idx = tid + 256 * u;
+    const int ar = idx % GS_T, ak = idx / GS_T;
+    const st_v2 z = {0.0, 0.0};
+    st_st(&As[0][0], ak * GS_T + ar, (row0 + ar < m && ak < k) ? av_[u] : z);
+    const int bk = idx % GS_K, bc = idx / GS_K;
+    st_st(&Bs[0][0], bk * (GS_T + 1) + bc, (bk < k && col0 + bc < n) ? bv_[u] : z);
   }
   __syncthreads();
   const int fq = lane >> 4, fi = lane & 15;
@@ -220,13 +245,20 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
     accr = mfma16(bv.y, -av.y, accr);
     acci = mfma16(bv.x, av.y, acci);
   }
-  // lane l, register r -> C(row fi, col 4 r + fq) of the wave's 16 x 16 block
+  // lane l, register r -> C(row fi, col 4 r + fq) of the wave's 16 x 16 block; the
+  // four C loads in flight together
+  st_v2 cv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row0 + wm * 16 + fi, col = col0 + wn * 16 + 4 * r + fq;
+    cv[r] = st_ld(C, (row < m && col < n) ? row + (long)col * ldc : 0);
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = row0 + wm * 16 + fi, col = col0 + wn * 16 + 4 * r + fq;
     if (row < m && col < n) {
       cplx out = cmul(alpha, cmk(accr[r], acci[r]));
-      out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
+      out = cadd(out, cmul(beta, cmk(cv[r].x, cv[r].y)));
       C[row + (long)col * ldc] = out;
     }
   }

@@ -158,12 +158,26 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
   }
 
   // epilogue: lane l, register r -> C(row l % 32, col (r % 4) + 8 (r / 4) + 4 (l / 32))
+  // (with beta != 0 the C loads of eight outputs go out together before any is used)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int h = 0; h < 2; ++h) {
+        st_v2 cin[8];
+        if constexpr (!BETA0) {
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            const int r = 8 * h + rr;
+            const int row = row0 + wm * 64 + a * 32 + fi;
+            const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
+            cin[rr] = st_ld(C, (row < m && col < n) ? row + (long)col * ldc : 0);
+          }
+        }
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int r = 8 * h + rr;
         const int row = row0 + wm * 64 + a * 32 + fi;
         const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
         if (row < m && col < n) {
@@ -178,9 +192,10 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
           }
           const cplx v = cmk((double)re, (double)im);
           cplx out = cmul(alpha, v);
-          if (!BETA0) out = cadd(out, cmul(beta, C[row + (long)col * ldc]));
+          if constexpr (!BETA0) out = cadd(out, cmul(beta, cmk(cin[rr].x, cin[rr].y)));
           C[row + (long)col * ldc] = out;
         }
+      }
       }
 }
 
