@@ -296,6 +296,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
   if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
+  if (nrhs <= 0 || n <= 0) return BM_OK;
   const int nblk = (n + TS_NB - 1) / TS_NB;
   int rc = bm_fill_u64(s, w->solve_sync, 4, 0ull);  // 8 int32 ticket words
   if (!rc) rc = bm_fill_u64(s, w->zbuf, 2 * (size_t)nblk * TS_NB * BM_MAX_NRHS, ~0ull);
