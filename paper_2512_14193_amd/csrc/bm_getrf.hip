@@ -577,6 +577,9 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 // reads the block's first element) so that no branch separates the loads, and
 // only the stores are predicated.
 // ---------------------------------------------------------------------------
+#ifndef BM_LU_EVENT_FLAGS
+#define BM_LU_EVENT_FLAGS hipEventDisableSystemFence
+#endif
 #define SWAP_COLS 16
 #define ST_CW 8
 #define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
@@ -689,8 +692,10 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
   ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * 8) == hipSuccess;
   ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&w->e_next, hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&w->e_rest, hipEventDisableTiming) == hipSuccess;
+  // the lookahead events only order the two streams of this device: no system-scope
+  // fence (the host never inspects them)
+  ok = ok && hipEventCreateWithFlags(&w->e_next, hipEventDisableTiming | BM_LU_EVENT_FLAGS) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&w->e_rest, hipEventDisableTiming | BM_LU_EVENT_FLAGS) == hipSuccess;
   if (!ok) {
     bm_getrf_ws_destroy(w);
     return nullptr;
