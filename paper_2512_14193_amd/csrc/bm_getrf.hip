@@ -269,11 +269,11 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       cplx x = cmk(0, 0), y = cmk(0, 0);
       if (col_ok && lr >= 0) {
         x = pan[lane * LDP + lr];
-        if (late) x = csub(x, cmul(pan[(cc - 1) * LDP + lr], pr));
+        if (late) x = cfms(x, pan[(cc - 1) * LDP + lr], pr);
       }
       if (col_ok && has_d) {
         y = pan[lane * LDP + (int)ld];
-        if (late) y = csub(y, cmul(pan[(cc - 1) * LDP + (int)ld], pr));
+        if (late) y = cfms(y, pan[(cc - 1) * LDP + (int)ld], pr);
       }
       if (col_ok && lr >= 0) rec_store(rs, sc + 1 + lane, x);
       if (col_ok && has_d) rec_store(rs, base + P * rstr + lane, y);
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
         lv[k] = cmul(xc[k], ip);
-        if (r < nv && r0 + r > gc) x1[k] = csub(x1[k], cmul(lv[k], u1));
+        if (r < nv && r0 + r > gc) x1[k] = cfms(x1[k], lv[k], u1);
       }
       double v = -1.0;
       int lr = -1;
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
         cplx x2 = have_next2 ? pan[(c + 2) * LDP + r] : cmk(0, 0);
-        if (r < nv && r0 + r > gc) x2 = csub(x2, cmul(lv[k], u2));
+        if (r < nv && r0 + r > gc) x2 = cfms(x2, lv[k], u2);
         xn[k] = x2;
       }
 #pragma unroll
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #pragma unroll
           for (int b = 0; b < BU; ++b) {
             const int cc = cc0 + b * NG;
-            if (cc < jb) pan[cc * LDP + r] = csub(av[b], cmul(l, uv[b]));
+            if (cc < jb) pan[cc * LDP + r] = cfms(av[b], l, uv[b]);
           }
         }
       }
@@ -666,11 +666,27 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
   const bool row_ok = lane < jb;
   cplx xa = (row_ok && ca < ncw) ? X[ca * LU_NB + lane] : cmk(0, 0);
   cplx xb = (row_ok && cb < ncw) ? X[cb * LU_NB + lane] : cmk(0, 0);
-  for (int c = 0; c < jb - 1; ++c) {
-    const cplx l = (lane > c && row_ok) ? Ls[c * LU_NB + lane] : cmk(0, 0);
-    const cplx ya = readlane_c(xa, c), yb = readlane_c(xb, c);
-    xa = csub(xa, cmul(l, ya));
-    xb = csub(xb, cmul(l, yb));
+  // the multipliers of eight steps are read from LDS ahead of them, so that a step's
+  // chain is only the broadcast of row c and one complex multiply-add
+  for (int c0 = 0; c0 < jb - 1; c0 += 8) {
+    st_v2 lvv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      const st_v2 z = {0.0, 0.0};
+      const st_v2 t = *reinterpret_cast<const st_v2 *>(Ls + (c < LU_NB ? c : LU_NB - 1) * LU_NB + lane);
+      lvv[u] = (c < jb - 1 && lane > c && row_ok) ? t : z;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      if (c < jb - 1) {
+        const cplx l = cmk(lvv[u].x, lvv[u].y);
+        const cplx ya = readlane_c(xa, c), yb = readlane_c(xb, c);
+        xa = cfms(xa, l, ya);
+        xb = cfms(xb, l, yb);
+      }
+    }
   }
   if (row_ok) {
     if (ca < ncw) A[(j + lane) + (long)(cw0 + ca) * lda] = xa;
