@@ -178,11 +178,12 @@ __device__ inline cplx pivot_recip(cplx u) {
 //   and fetches its row and the diagonal row; in registers it exchanges rows
 //   j + c and p, scales column c (the multipliers l_r = a_rc / u_c), updates
 //   column c + 1 and finds the workgroup's candidate for it, whose header it
-//   publishes at once (the header is what every reader waits for); only then
-//   come the LDS writes of the step and the candidate and diagonal rows
-//   (completed on the fly for columns > c + 1), and pivot c is released to the
-//   bulk wavefronts; it also applies pivot c to column c + 2 and keeps that
-//   column in registers, so the next step starts without touching LDS;
+//   publishes at once (the header is what every reader waits for); then come
+//   the candidate and diagonal rows of the record (from the registers and the LDS
+//   as it stands, completed on the fly for columns > c + 1), the LDS writes of the
+//   step, and pivot c is released to the bulk wavefronts; it also applies pivot
+//   c to column c + 2 and keeps that column in registers, so the next step
+//   starts without touching LDS;
 //   wavefronts 1 .. SNB: subtract l_r u_cc from columns cc >= c + 3 and count
 //   themselves done; wavefront 0 waits for that count before it writes rows or
 //   reads columns of the next step.
@@ -258,8 +259,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
     auto publish_head = [&](int cc, double v, int lr) __attribute__((always_inline)) {
       if (lane == 0) rec_store(rs, cc * cstride + g * rstr, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
     };
-    // then the candidate row lr and the diagonal row; columns > cc still owe the
-    // update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
+    // then (for column 0) the candidate row lr and the diagonal row; columns > cc
+    // still owe the update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
     auto publish_rows = [&](int cc, int lr, cplx pr) __attribute__((always_inline)) {
       const int base = cc * cstride;
       const int sc = base + g * rstr;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         y = pan[lane * LDP + (int)ld];
         if (late) y = cfms(y, pan[(cc - 1) * LDP + (int)ld], pr);
       }
-      if (col_ok && lr >= 0) rec_store(rs, sc + 1 + lane, x);
+      if (col_ok) rec_store(rs, sc + 1 + lane, x);  // zeros when the workgroup has no candidate
       if (col_ok && has_d) rec_store(rs, base + P * rstr + lane, y);
     };
     cplx xc[RPL], xn[RPL];  // columns c and c + 1 of the workgroup's rows
@@ -423,6 +424,31 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
           __builtin_amdgcn_s_sleep(1);
         }
       }
+      // the record rows of column c + 1 (candidate row lr, diagonal row gc + 1) from
+      // the registers and the LDS as it stands before this step's writes: row lp
+      // already counts as holding the old row gc (dr); column c is the multiplier, column
+      // c + 1 the updated value, columns > c + 1 still owe pivot c
+      if (have_next) {
+        auto rec_row = [&](int r) __attribute__((always_inline)) -> cplx {
+          cplx lr_c = cmk(0, 0), x1_c = cmk(0, 0);
+#pragma unroll
+          for (int k = 0; k < RPL; ++k)
+            if ((r >> 6) == k) {
+              lr_c = readlane_c(lv[k], r & 63);
+              x1_c = readlane_c(x1[k], r & 63);
+            }
+          cplx b = (r == (int)lp) ? dr : pan[lane * LDP + r];
+          if (lane == c) b = lr_c;
+          else if (lane == c + 1) b = x1_c;
+          else if (lane > c + 1) b = cfms(b, lr_c, pr);
+          return b;
+        };
+        const int base1 = (c + 1) * cstride;
+        const long ld = gc + 1 - r0;
+        const bool has_d = (ld >= 0 && ld < nv);
+        if (col_ok) rec_store(rs, base1 + g * rstr + 1 + lane, (lr >= 0) ? rec_row(lr) : cmk(0, 0));
+        if (col_ok && has_d) rec_store(rs, base1 + P * rstr + lane, rec_row((int)ld));
+      }
       // now LDS: the interchanged rows; column c + 2 with pivot c applied, kept in
       // registers for the next step (in LDS it stays one pivot behind, like the
       // columns the bulk wavefronts update); the multipliers; column c + 1 from the
@@ -448,7 +474,6 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         }
       }
       if (col_ok) urow[c & 1][lane] = pr;
-      if (have_next) publish_rows(c + 1, lr, pr);
       // release pivot c to the bulk wavefronts
       if (lane == 0) __hip_atomic_store(&s_ready, c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
