@@ -53,42 +53,54 @@ int bm_launch_gather(hipStream_t s, int nf, int nrhs, const int32_t *perm, const
 
 // ---------------------------------------------------------------------------
 // skinny GEMM  C = C - A B  (A m x k column-major, B k x nr, nr <= BM_MAX_NRHS)
-// stage 1: workgroup (row block, k split) -> partial sums; thread = row, the
-//          k-slice of B staged in LDS and broadcast to the 256 rows
+// stage 1: workgroup (256-row block, k split) -> partial sums; thread = row, the
+//          k-slice of B staged in LDS and broadcast to the 256 rows; the A loads of
+//          eight k values are issued together (unconditionally: rows past m read
+//          row 0), and the accumulators are sized for the right-hand-side count
 // stage 2: partials summed in split order and subtracted from C
+// The k split aims at GV_WG workgroups with at least GV_KC k values each, so that
+// A (read once) dominates the traffic and the partials stay small.
 // ---------------------------------------------------------------------------
 #define GV_ROWS 256
 #define GV_KC 32
+#define GV_UN 8
+#define GV_WG 256
+template <int NRM>
 __global__ __launch_bounds__(256) void gemv_partial_kernel(int m, int k, int nr, int kchunk, const cplx *A, long lda,
                                                            const cplx *B, long ldb, cplx *part) {
-  __shared__ cplx Bs[GV_KC][BM_MAX_NRHS];
+  __shared__ cplx Bs[GV_KC][NRM];
   const int i = blockIdx.x * GV_ROWS + threadIdx.x;
+  const int ia = (i < m) ? i : 0;
   const int ks = blockIdx.y;
   const int k0 = ks * kchunk, k1 = (k0 + kchunk < k) ? k0 + kchunk : k;
-  cplx acc[BM_MAX_NRHS];
+  cplx acc[NRM];
 #pragma unroll
-  for (int r = 0; r < BM_MAX_NRHS; ++r) acc[r] = cmk(0, 0);
+  for (int r = 0; r < NRM; ++r) acc[r] = cmk(0, 0);
   for (int kb = k0; kb < k1; kb += GV_KC) {
     const int kn = (k1 - kb < GV_KC) ? k1 - kb : GV_KC;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kn * nr; idx += 256) {
-      const int kk = idx % kn, r = idx / kn;
-      Bs[kk][r] = B[(kb + kk) + (long)r * ldb];
+    for (int idx = threadIdx.x; idx < GV_KC * NRM; idx += 256) {
+      const int kk = idx % GV_KC, r = idx / GV_KC;
+      Bs[kk][r] = (kk < kn && r < nr) ? B[(kb + kk) + (long)r * ldb] : cmk(0, 0);
     }
     __syncthreads();
-    if (i < m) {
-      for (int kk = 0; kk < kn; ++kk) {
-        const cplx a = A[i + (long)(kb + kk) * lda];
+    for (int u0 = 0; u0 < kn; u0 += GV_UN) {
+      st_v2 a[GV_UN];
 #pragma unroll
-        for (int r = 0; r < BM_MAX_NRHS; ++r)
-          if (r < nr) acc[r] = cadd(acc[r], cmul(a, Bs[kk][r]));
+      for (int u = 0; u < GV_UN; ++u) a[u] = st_ld(A, ia + (long)(kb + ((u0 + u < kn) ? u0 + u : 0)) * lda);
+#pragma unroll
+      for (int u = 0; u < GV_UN; ++u) {
+        // Bs rows past kn are zero, so the clamped loads add nothing
+        const cplx av = cmk(a[u].x, a[u].y);
+#pragma unroll
+        for (int r = 0; r < NRM; ++r) acc[r] = cadd(acc[r], cmul(av, Bs[u0 + u][r]));
       }
     }
   }
   if (i < m) {
     cplx *pp = part + (size_t)ks * m * nr;
 #pragma unroll
-    for (int r = 0; r < BM_MAX_NRHS; ++r)
+    for (int r = 0; r < NRM; ++r)
       if (r < nr) pp[i + (size_t)r * m] = acc[r];
   }
 }
@@ -102,12 +114,23 @@ __global__ void gemv_reduce_kernel(int m, int nr, int nsplit, const cplx *part, 
   C[i + (long)r * ldc] = csub(C[i + (long)r * ldc], s);
 }
 
-size_t bm_gemv_work_elems(int m, int k) {
+// k split of a launch: about GV_WG workgroups, at least GV_KC k values (a multiple
+// of GV_KC) per split
+static void gemv_split(int m, int k, int *ns_out, int *kchunk_out) {
   const int rb = (m + GV_ROWS - 1) / GV_ROWS;
-  int ns = 1024 / rb;
+  int ns = GV_WG / rb;
   if (ns < 1) ns = 1;
   const int maxs = (k + GV_KC - 1) / GV_KC;
   if (ns > maxs) ns = maxs;
+  int kchunk = (k + ns - 1) / ns;
+  kchunk = ((kchunk + GV_KC - 1) / GV_KC) * GV_KC;
+  *kchunk_out = kchunk;
+  *ns_out = (k + kchunk - 1) / kchunk;
+}
+
+size_t bm_gemv_work_elems(int m, int k) {
+  int ns, kchunk;
+  gemv_split(m, k, &ns, &kchunk);
   return (size_t)ns * m * BM_MAX_NRHS;
 }
 
@@ -116,15 +139,18 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
   if (m <= 0 || nr <= 0 || k <= 0) return BM_OK;
   if (nr > BM_MAX_NRHS) return BM_E_ARG;
   const int rb = (m + GV_ROWS - 1) / GV_ROWS;
-  int ns = 1024 / rb;
-  if (ns < 1) ns = 1;
-  const int maxs = (k + GV_KC - 1) / GV_KC;
-  if (ns > maxs) ns = maxs;
-  int kchunk = (k + ns - 1) / ns;
-  kchunk = ((kchunk + GV_KC - 1) / GV_KC) * GV_KC;
-  ns = (k + kchunk - 1) / kchunk;
-  hipLaunchKernelGGL(gemv_partial_kernel, dim3(rb, ns), dim3(256), 0, s, m, k, nr, kchunk, A, (long)lda, B, (long)ldb,
-                     work);
+  int ns, kchunk;
+  gemv_split(m, k, &ns, &kchunk);
+  const dim3 grid(rb, ns);
+  if (nr <= 8)
+    hipLaunchKernelGGL(gemv_partial_kernel<8>, grid, dim3(256), 0, s, m, k, nr, kchunk, A, (long)lda, B, (long)ldb,
+                       work);
+  else if (nr <= 16)
+    hipLaunchKernelGGL(gemv_partial_kernel<16>, grid, dim3(256), 0, s, m, k, nr, kchunk, A, (long)lda, B, (long)ldb,
+                       work);
+  else
+    hipLaunchKernelGGL(gemv_partial_kernel<BM_MAX_NRHS>, grid, dim3(256), 0, s, m, k, nr, kchunk, A, (long)lda, B,
+                       (long)ldb, work);
   BM_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(gemv_reduce_kernel, dim3((m + 255) / 256, nr), dim3(256), 0, s, m, nr, ns, (const cplx *)work, C,
                      (long)ldc);
