@@ -174,25 +174,34 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 #define TS_RG (BM_MAX_NRHS / 4)  // right-hand sides per thread
 #define ZSENT 0xFFFFFFFFFFFFFFFFULL
 
-// acc[u] += sign * sum_{s < 64} M[rr][s] Zs[s][rg + 4u].  Tiles are zero-padded to
-// 64 x 64, so every loop has a fixed trip count and the LDS loads of a group of
-// eight are issued together.
-__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int rr, int rg,
-                                int nper, cplx (&acc)[TS_RG], double sign) {
-#pragma unroll 2
-  for (int s0 = 0; s0 < TS_NB; s0 += 8) {
-    cplx m[8];
+// acc[u] += sign * (M Zs)[rr][rg + 4u] on the FP64 matrix cores, for the thread
+// with row rr = 16 w + (l % 16) and right-hand-side group rg = l / 16 (w = wavefront,
+// l = lane).  Per group of eight right-hand sides the B operand's 16 columns are
+// their real parts followed by their imaginary parts, so C1 = Re(M) B and
+// C2 = Im(M) B give Re = C1[:, re] - C2[:, im] and Im = C1[:, im] + C2[:, re] with
+// no padding; lane l, register r of the 16 x 16 result holds row l % 16, column
+// 4 r + l / 16, so every lane combines its own registers.  Tiles are zero-padded
+// to 64 x 64 and Zs to BM_MAX_NRHS columns.  Needs all 64 lanes of every wavefront.
+typedef double tv_dbl4 __attribute__((ext_vector_type(4)));
+__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int nrhs,
+                                cplx (&acc)[TS_RG], double sign) {
+  const int lane = threadIdx.x & 63, fi = lane & 15, fq = lane >> 4;
+  const int row = 16 * (threadIdx.x >> 6) + fi;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) m[v] = cscale(M[rr][s0 + v], sign);
-#pragma unroll
-    for (int u = 0; u < TS_RG; ++u) {
-      if (u < nper) {
-        cplx z[8];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) z[v] = Zs[s0 + v][rg + 4 * u];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u] = cadd(acc[u], cmul(m[v], z[v]));
+  for (int b = 0; b < BM_MAX_NRHS / 8; ++b) {
+    if (8 * b < nrhs) {
+      tv_dbl4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
+      const int zc = 8 * b + (fi & 7);
+#pragma unroll 4
+      for (int k4 = 0; k4 < TS_NB; k4 += 4) {
+        const cplx m = M[row][k4 + fq];
+        const cplx z = Zs[k4 + fq][zc];
+        const double bz = (fi < 8) ? z.x : z.y;
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(bz, m.x, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bz, m.y, c2, 0, 0, 0);
       }
+      acc[2 * b] = cadd(acc[2 * b], cscale(cmk(c1[0] - c2[2], c1[2] + c2[0]), sign));
+      acc[2 * b + 1] = cadd(acc[2 * b + 1], cscale(cmk(c1[1] - c2[3], c1[3] + c2[1]), sign));
     }
   }
 }
@@ -210,7 +219,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   const int b = LOWER ? t : nblk - 1 - t;
   const int o = b * TS_NB;
   const int nb = (n - o < TS_NB) ? n - o : TS_NB;
-  const int rr = threadIdx.x % TS_NB, rg = threadIdx.x / TS_NB;  // row, right-hand-side group
+  // row and right-hand-side group of the thread, in the matrix cores' result layout
+  const int rr = 16 * (threadIdx.x >> 6) + (threadIdx.x & 15), rg = (threadIdx.x >> 4) & 3;
   const int nper = (nrhs + 3) / 4;
   cplx acc[TS_RG];
 #pragma unroll
@@ -220,7 +230,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   }
   const int ndep = LOWER ? b : nblk - 1 - b;
   const cplx *Di = dinv + (size_t)b * 2 * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
-  cplx lt[16];  // this thread's 16 elements of the next 64 x 64 tile (column-major order)
+  // this thread's 16 elements of the next 64 x 64 tile (column-major order), all
+  // loads in flight together: an element outside a ragged tile reads the tile's
+  // first element and is replaced by zero when the tile goes to LDS
+  st_v2 lt[16];
   auto fetch_tile = [&](int k) {
     const int ko = k * TS_NB;
     const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
@@ -228,12 +241,12 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
     for (int e = 0; e < 16; ++e) {
       const int idx = threadIdx.x + 256 * e;
       const int r = idx % TS_NB, c = idx / TS_NB;
-      lt[e] = (r < nb && c < kn) ? LU[(o + r) + (long)(ko + c) * ld] : cmk(0, 0);
+      lt[e] = st_ld(LU, (r < nb && c < kn) ? (o + r) + (long)(ko + c) * ld : o + (long)ko * ld);
     }
   };
   auto fetch_dinv = [&]() {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lt[e] = Di[threadIdx.x + 256 * e];
+    for (int e = 0; e < 16; ++e) lt[e] = st_ld(Di, threadIdx.x + 256 * e);
   };
   if (ndep > 0) fetch_tile(LOWER ? 0 : nblk - 1);
   else fetch_dinv();
@@ -244,7 +257,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int idx = threadIdx.x + 256 * e;
-      Ls[idx % TS_NB][idx / TS_NB] = lt[e];
+      const int r = idx % TS_NB, c = idx / TS_NB;
+      Ls[r][c] = (r < nb && c < kn) ? cmk(lt[e].x, lt[e].y) : cmk(0, 0);
     }
     if (d + 1 < ndep) fetch_tile(LOWER ? d + 1 : nblk - 2 - d);
     else fetch_dinv();
@@ -291,14 +305,14 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
       }
     }
     __syncthreads();
-    block_mv(Ls, Z, rr, rg, nper, acc, -1.0);
+    block_mv(Ls, Z, nrhs, acc, -1.0);
     __syncthreads();
   }
   // diagonal block: x_b = inv(D_b) acc (the inverse is in lt)
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int idx = threadIdx.x + 256 * e;
-    Ls[idx % TS_NB][idx / TS_NB] = lt[e];
+    Ls[idx % TS_NB][idx / TS_NB] = cmk(lt[e].x, lt[e].y);
   }
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u)
@@ -307,7 +321,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   cplx xv[TS_RG];
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u) xv[u] = cmk(0, 0);
-  block_mv(Ls, Z, rr, rg, nper, xv, 1.0);
+  block_mv(Ls, Z, nrhs, xv, 1.0);
   cplx *zo = zbuf + (size_t)b * TS_NB * BM_MAX_NRHS;
 #pragma unroll
   for (int u = 0; u < TS_RG; ++u) {
