@@ -13,6 +13,11 @@
 //                   on s in [0, 6.4] is accurate to ~1e-16 for |z| >= 3 in the sector.
 //                   J = (H^(1) + H^(2))/2 with H^(2)(z) = conj(H^(1)(conj z)).
 //   |z| >= 25       Hankel's asymptotic expansion (DLMF 10.17.5), terms until < 1e-17.
+//   real z >= 3     (real wavenumbers) the normalised function F_nu(1/z) of
+//                   H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} F_nu, the same
+//                   integral as a function of t = 1/z, from its Chebyshev series on
+//                   t in [0, 1/3] (degree 26, generated from 40-digit values by
+//                   gen_hankel_cheb.py): about one ulp, a tenth of the integral's cost.
 //
 // Wide domain (bm_hankel01_wide): wavenumbers in the lower half plane beyond that
 // sector (Im k < -Re k / 2), where the complex resonances and fictitious
@@ -25,6 +30,8 @@
 #pragma once
 
 #include "bm_internal.h"
+
+#include "bm_hankel_cheb.h"
 
 #define BM_HQ 32           // trapezoid nodes s_q = q * 0.2, q = 0..32
 #define BM_HSTEP 0.2
@@ -133,6 +140,36 @@ __device__ inline void bm_hankel_asymptotic(cplx z, bm_hk4 &o) {
   o.j1 = cscale(cadd(H11, H21), 0.5);
 }
 
+// H^(1)_0, H^(1)_1, J0, J1 at real x >= 3 from the Chebyshev series of F_0, F_1
+// (Clenshaw's recurrence in u = 6/x - 1; the coefficients are the same for every
+// lane, so they come from the scalar cache).
+__device__ inline void bm_hankel_real(double x, bm_hk4 &o) {
+  const double t = 1.0 / x;
+  const double u = 6.0 * t - 1.0, u2 = 2.0 * u;
+  double b1[4] = {0.0, 0.0, 0.0, 0.0}, b2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = BM_HC_DEG; j >= 1; --j) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double bn = fma(u2, b1[q], bm_hc[j][q] - b2[q]);
+      b2[q] = b1[q];
+      b1[q] = bn;
+    }
+  }
+  double f[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) f[q] = fma(u, b1[q], bm_hc[0][q] - b2[q]);
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  // sqrt(2/(pi x)) e^{i(x - pi/4)} = sqrt(1/(pi x)) ((cos x + sin x) + i (sin x - cos x))
+  const double a = sqrt(t / BM_PI);
+  const cplx e = cmk(a * (cs + sn), a * (sn - cs));
+  o.h0 = cmul(e, cmk(f[0], f[1]));
+  o.h1 = cmul(cmk(e.y, -e.x), cmk(f[2], f[3]));  // extra e^{-i pi/2}
+  o.j0 = cmk(o.h0.x, 0.0);
+  o.j1 = cmk(o.h1.x, 0.0);
+}
+
 // Largest |z| of the wide domain
 #define BM_WIDE_ZMAX 6.0
 
@@ -154,6 +191,8 @@ __device__ inline bm_hk4 bm_hankel01(cplx z) {
   const double az2 = cabs2(z);
   if (az2 < 9.0) {
     bm_hankel_series<18>(z, o);
+  } else if (z.y == 0.0 && z.x > 0.0) {
+    bm_hankel_real(z.x, o);
   } else if (az2 < 625.0) {
     bm_hankel_integral(z, o.h0, o.h1);
     if (z.y == 0.0) {
