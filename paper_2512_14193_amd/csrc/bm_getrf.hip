@@ -907,22 +907,35 @@ __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, lo
   const int b = blockIdx.x;
   const int o = b * BM_DIAG_NB;
   const int nb = (n - o < BM_DIAG_NB) ? n - o : BM_DIAG_NB;
-  for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) {
-    const int r = idx % TI_N, c = idx / TI_N;
-    Ms[r + c * (TI_N + 1)] = (r < nb && c < nb) ? LU[(o + r) + (long)(o + c) * ld] : cmk(r == c ? 1.0 : 0.0, 0.0);
+  {
+    // the block, every load of a thread in flight together (entries outside a ragged
+    // block read its first element and are replaced by the identity's)
+    constexpr int LPT = TI_N * TI_N / 256;
+    st_v2 v[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
+      v[q] = st_ld(LU, (r < nb && c < nb) ? (o + r) + (long)(o + c) * ld : o + (long)o * ld);
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
+      Ms[r + c * (TI_N + 1)] = (r < nb && c < nb) ? cmk(v[q].x, v[q].y) : cmk(r == c ? 1.0 : 0.0, 0.0);
+    }
   }
   __syncthreads();
-  cplx *Li = dinv + (size_t)b * 2 * TI_N * TI_N, *Ui = Li + TI_N * TI_N;
-  tri_inv64<true>(Ms, TI_N + 1, Xs, TI_N + 1, T);
-  for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) Li[idx] = Xs[idx % TI_N + (idx / TI_N) * (TI_N + 1)];
-  __syncthreads();
-  tri_inv64<false>(Ms, TI_N + 1, Xs, TI_N + 1, T);
-  for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) Ui[idx] = Xs[idx % TI_N + (idx / TI_N) * (TI_N + 1)];
+  // workgroup (b, 0) inverts the unit lower triangle, (b, 1) the upper one
+  cplx *Xo = dinv + (size_t)b * 2 * TI_N * TI_N + (blockIdx.y ? TI_N * TI_N : 0);
+  if (blockIdx.y == 0)
+    tri_inv64<true>(Ms, TI_N + 1, Xs, TI_N + 1, T);
+  else
+    tri_inv64<false>(Ms, TI_N + 1, Xs, TI_N + 1, T);
+  for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) Xo[idx] = Xs[idx % TI_N + (idx / TI_N) * (TI_N + 1)];
 }
 
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv) {
   const int nblk = (n + BM_DIAG_NB - 1) / BM_DIAG_NB;
-  hipLaunchKernelGGL(diag_inv_kernel, dim3(nblk), dim3(256), TI_LDS, s, n, LU, (long)ld, dinv);
+  hipLaunchKernelGGL(diag_inv_kernel, dim3(nblk, 2), dim3(256), TI_LDS, s, n, LU, (long)ld, dinv);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
