@@ -8,7 +8,8 @@
 // Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 64 x 64 tile of C
 // (accumulators in VGPRs); each wave owns 32 x 32 = 2 x 2 blocks of 16 x 16
 // (v_mfma_f64_16x16x4f64 results).  Operands are staged through LDS in k-slices
-// of GM_BK complex values, double buffered, and the fragments of the next k-quad
+// of 12 (deep products) or 8 (shallow) complex values, double buffered, and the
+// fragments of the next k-quad
 // are read from LDS during the MFMAs of this one.
 //
 // Complex products: for shallow products (k < GM_3M_MIN_K: the trailing updates
@@ -30,10 +31,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 #define GM_BM 64
 #define GM_BN 64
-#ifndef GM_BK
-#define GM_BK 8
+// complex k per stage: 12 for the deep three-multiplication products (8 and 16
+// measured slower there; 16 leaves one workgroup per CU), 8 for the k = 64 updates
+// of the LU (a multiple of the depth)
+#ifndef GM_BK3
+#define GM_BK3 12
 #endif
-#define GM_LPT (GM_BK * GM_BM / 256)  // complex values of each operand loaded per thread and stage
+#ifndef GM_BK4
+#define GM_BK4 8
+#endif
 #ifndef BM_SHALLOW_GEMM
 #define BM_SHALLOW_GEMM 1
 #endif
@@ -49,6 +55,8 @@ template <bool BETA0, bool M3>
 __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
                                                     long lda, const cplx *__restrict__ B, long ldb, cplx beta,
                                                     cplx *__restrict__ C, long ldc, int tiles_m) {
+  constexpr int GM_BK = M3 ? GM_BK3 : GM_BK4;
+  constexpr int GM_LPT = GM_BK * GM_BM / 256;  // complex values of each operand loaded per thread and stage
   __shared__ cplx As[2][GM_BK][GM_BM];
   __shared__ cplx Bs[2][GM_BK][GM_BN + 1];
   __shared__ double Ass[2][M3 ? GM_BK : 1][M3 ? GM_BM : 1];      // Ar + Ai
@@ -203,7 +211,7 @@ if constexpr (M3) {
 // Shallow, narrow products (k <= 64, n <= 64: the update of the next panel's
 // columns in the LU, on its critical path): 32 x 32 output tiles (four times the
 // workgroups of the 64 x 64 kernel) and the whole depth staged in one step, so a
-// workgroup waits for one round of global loads instead of k / GM_BK.
+// workgroup waits for one round of global loads instead of one per stage.
 #define GS_T 32
 #define GS_K 64
 __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k, cplx alpha,
