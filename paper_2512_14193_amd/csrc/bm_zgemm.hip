@@ -8,16 +8,15 @@
 // Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 64 x 64 tile of C
 // (accumulators in VGPRs); each wave owns 32 x 32 = 2 x 2 blocks of 16 x 16
 // (v_mfma_f64_16x16x4f64 results).  Operands are staged through LDS in k-slices
-// of 12 (deep products) or 8 (shallow) complex values, double buffered, and the
-// fragments of the next k-quad
-// are read from LDS during the MFMAs of this one.
+// of 16 (deep products) or 8 (shallow) complex values, double buffered, and the
+// fragments of the next k-quad are read from LDS during the MFMAs of this one.
 //
 // Complex products: for shallow products (k < GM_3M_MIN_K: the trailing updates
 // of the LU, bound by memory traffic) four real MFMAs per complex multiply-add,
 // Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br, four workgroups per CU.  For deep
 // ones (the Schur complement) Gauss's form with three: T1 = Ar Br, T2 = Ai Bi,
-// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2 (the sums staged in
-// LDS), two workgroups per CU.  Its rounding error stays at the FP64 level,
+// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2 (the sums formed from
+// the operand fragments in registers), two workgroups per CU.  Its rounding error stays at the FP64 level,
 // bounded by (|Ar| + |Ai|)(|Br| + |Bi|) sums instead of |A||B| ones.
 //
 // MFMA operand order: the B fragment is fed as the MFMA's first operand and the A
@@ -31,11 +30,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 #define GM_BM 64
 #define GM_BN 64
-// complex k per stage: 12 for the deep three-multiplication products (8 and 16
-// measured slower there; 16 leaves one workgroup per CU), 8 for the k = 64 updates
-// of the LU (a multiple of the depth)
+// complex k per stage: 16 for the deep three-multiplication products (the most
+// that keeps two workgroups per CU in LDS: 65 KB each), 8 for the k = 64 updates
+// of the LU
 #ifndef GM_BK3
-#define GM_BK3 12
+#define GM_BK3 16
 #endif
 #ifndef GM_BK4
 #define GM_BK4 8
@@ -59,8 +58,6 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
   constexpr int GM_LPT = GM_BK * GM_BM / 256;  // complex values of each operand loaded per thread and stage
   __shared__ cplx As[2][GM_BK][GM_BM];
   __shared__ cplx Bs[2][GM_BK][GM_BN + 1];
-  __shared__ double Ass[2][M3 ? GM_BK : 1][M3 ? GM_BM : 1];      // Ar + Ai
-  __shared__ double Bss[2][M3 ? GM_BK : 1][M3 ? GM_BN + 1 : 1];  // Br + Bi
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -89,10 +86,6 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
     for (int u = 0; u < GM_LPT; ++u) {
       As[buf][a_k + 4 * u][a_r] = ra[u];
       Bs[buf][b_k + u][b_c] = rb[u];
-      if constexpr (M3) {
-        Ass[buf][a_k + 4 * u][a_r] = ra[u].x + ra[u].y;
-        Bss[buf][b_k + u][b_c] = rb[u].x + rb[u].y;
-      }
     }
   };
 
@@ -123,11 +116,11 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx
     for (int a = 0; a < 2; ++a) av[slot][a] = As[buf][k4 + fq][wm * 32 + a * 16 + fi];
 #pragma unroll
     for (int b = 0; b < 2; ++b) bv[slot][b] = Bs[buf][k4 + fq][wn * 32 + b * 16 + fi];
-    if constexpr (M3) {
+    if constexpr (M3) {  // the sums of the three-multiplication form, from the fragments
 #pragma unroll
-      for (int a = 0; a < 2; ++a) as[slot][a] = Ass[buf][k4 + fq][wm * 32 + a * 16 + fi];
+      for (int a = 0; a < 2; ++a) as[slot][a] = av[slot][a].x + av[slot][a].y;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bs[slot][b] = Bss[buf][k4 + fq][wn * 32 + b * 16 + fi];
+      for (int b = 0; b < 2; ++b) bs[slot][b] = bv[slot][b].x + bv[slot][b].y;
     }
   };
   for (int it = 0; it < nk; ++it) {
