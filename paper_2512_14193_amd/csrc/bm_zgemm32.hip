@@ -18,8 +18,8 @@
 //   T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi),
 //   Re = T1 - T2,  Im = T3 - T1 - T2,
 // three real MFMAs per complex multiply-add instead of four (Re += Ar Br - Ai Bi,
-// Im += Ar Bi + Ai Br), with the sums Ar + Ai and Br + Bi formed in FP32 while
-// staging.  Its rounding error in Im is bounded by (|Ar| + |Ai|)(|Br| + |Bi|)
+// Im += Ar Bi + Ai Br), with the sums Ar + Ai and Br + Bi formed in FP32 from the
+// operand fragments (staging them as a third LDS plane measured 5% slower).  Its rounding error in Im is bounded by (|Ar| + |Ai|)(|Br| + |Bi|)
 // instead of |A||B| terms: the same order in FP32, and the refinement of the
 // mixed-precision solve removes it either way.
 //
@@ -43,7 +43,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #ifndef G2_OCC
 #define G2_OCC 2  // workgroups per CU
 #endif
-#define G2_NP (G2_3M ? 3 : 2)  // operand planes in LDS: (re, im[, re + im])
+#define G2_NP (G2_3M ? 3 : 2)  // operand planes of the products: (re, im[, re + im])
+#define G2_LP 2                // planes held in LDS (re, im); the sums come from the fragments
 
 __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -54,8 +55,8 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
                                                            const cplx *__restrict__ A, long lda,
                                                            const cplx *__restrict__ B, long ldb, cplx beta,
                                                            cplx *__restrict__ C, long ldc, int tiles_m) {
-  __shared__ float As[2][G2_NP][G2_BK][G2_BM];
-  __shared__ float Bs[2][G2_NP][G2_BK][G2_BN];
+  __shared__ float As[2][G2_LP][G2_BK][G2_BM];
+  __shared__ float Bs[2][G2_LP][G2_BK][G2_BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -88,10 +89,6 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
       As[buf][1][ka][a_r] = xi;
       Bs[buf][0][kb][b_c] = yr;
       Bs[buf][1][kb][b_c] = yi;
-      if (G2_3M) {
-        As[buf][2][ka][a_r] = xr + xi;
-        Bs[buf][2][kb][b_c] = yr + yi;
-      }
     }
   };
 
@@ -119,11 +116,17 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
   float av[2][G2_NP][2], bv[2][G2_NP][2];
   auto fload = [&](int buf, int k2, int slot) {
 #pragma unroll
-    for (int p = 0; p < G2_NP; ++p) {
+    for (int p = 0; p < G2_LP; ++p) {
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[slot][p][a] = As[buf][p][k2 + fh][wm * 64 + a * 32 + fi];
 #pragma unroll
       for (int b = 0; b < 2; ++b) bv[slot][p][b] = Bs[buf][p][k2 + fh][wn * 64 + b * 32 + fi];
+    }
+    if (G2_NP == 3) {  // the FP32 sums re + im of the three-multiplication form
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[slot][G2_NP - 1][a] = av[slot][0][a] + av[slot][1][a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[slot][G2_NP - 1][b] = bv[slot][0][b] + bv[slot][1][b];
     }
   };
   for (int it = 0; it < nk; ++it) {
