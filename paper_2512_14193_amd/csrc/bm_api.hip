@@ -77,7 +77,7 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
   }
   ok = ok && hipMalloc(&p->lu, sizeof(cplx) * nf * nf) == hipSuccess;
   ok = ok && hipMalloc(&p->ipiv, sizeof(int32_t) * nf) == hipSuccess;
-  ok = ok && hipMalloc(&p->dinv, sizeof(cplx) * nblk * 2 * BM_DIAG_NB * BM_DIAG_NB) == hipSuccess;
+  ok = ok && hipMalloc(&p->dinv, sizeof(cplx) * nblk * BM_DINV_TILES * BM_DIAG_NB * BM_DIAG_NB) == hipSuccess;
   ok = ok && hipMalloc(&p->perm, sizeof(int32_t) * nf) == hipSuccess;
   ok = ok && hipMalloc(&p->work_g, sizeof(cplx) * nf * BM_MAX_NRHS) == hipSuccess;
   if (formulation == BM_MIXED) {

@@ -898,8 +898,14 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
 }
 
 // ---------------------------------------------------------------------------
-// solve support: inverses of the 64 x 64 diagonal blocks of L (unit lower) and U
-// dinv layout: block b at dinv + b * 2 * 64 * 64: [Linv (col-major 64x64), Uinv]
+// solve support: inverses of the 64 x 64 diagonal blocks of L (unit lower) and U,
+// and each inverse times the off-diagonal block the triangular solve meets last
+//   WL_b = Linv_b L(b, b - 1),  WU_b = Uinv_b U(b, b + 1)
+// so that the solve of block b can apply its inverse before the block it depends
+// on last is known: x_b = inv(D_b) r_b - W_b x_{b -+ 1}, with r_b the right-hand side
+// less every other off-diagonal product.
+// dinv layout: block b at dinv + b * 4 * 64 * 64: [Linv, Uinv, WL, WU] (col-major 64x64;
+// a tile that does not exist, WL_0 or WU_last, is not written)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv) {
   extern __shared__ cplx sm[];
@@ -925,12 +931,56 @@ __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, lo
   }
   __syncthreads();
   // workgroup (b, 0) inverts the unit lower triangle, (b, 1) the upper one
-  cplx *Xo = dinv + (size_t)b * 2 * TI_N * TI_N + (blockIdx.y ? TI_N * TI_N : 0);
-  if (blockIdx.y == 0)
+  const int up = blockIdx.y;
+  cplx *Xo = dinv + (size_t)b * BM_DINV_TILES * TI_N * TI_N + (size_t)up * TI_N * TI_N;
+  if (!up)
     tri_inv64<true>(Ms, TI_N + 1, Xs, TI_N + 1, T);
   else
     tri_inv64<false>(Ms, TI_N + 1, Xs, TI_N + 1, T);
   for (int idx = threadIdx.x; idx < TI_N * TI_N; idx += 256) Xo[idx] = Xs[idx % TI_N + (idx / TI_N) * (TI_N + 1)];
+  // W = inverse times the off-diagonal block: L(b, b - 1) (rows of a ragged last
+  // block b beyond n are zero) or U(b, b + 1) (columns beyond n are zero)
+  const int nblk = (n + BM_DIAG_NB - 1) / BM_DIAG_NB;
+  if (up ? b + 1 >= nblk : b == 0) return;
+  const int co = up ? o + BM_DIAG_NB : o - BM_DIAG_NB;
+  const int cn = (n - co < BM_DIAG_NB) ? n - co : BM_DIAG_NB;
+  {
+    constexpr int LPT = TI_N * TI_N / 256;
+    st_v2 v[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
+      v[q] = st_ld(LU, (r < nb && c < cn) ? (o + r) + (long)(co + c) * ld : o + (long)co * ld);
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
+      Ms[r + c * (TI_N + 1)] = (r < nb && c < cn) ? cmk(v[q].x, v[q].y) : cmk(0, 0);
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, fi = lane & 15, fq = lane >> 4, row = 16 * (threadIdx.x >> 6) + fi;
+  st_v2 xt[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const cplx x = Xs[row + (4 * s + fq) * (TI_N + 1)];
+    xt[s].x = x.x;
+    xt[s].y = x.y;
+  }
+  cplx *Wo = Xo + 2 * TI_N * TI_N;
+#pragma unroll 1
+  for (int g = 0; g < TI_N / 8; ++g) {
+    double bz[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const cplx m = Ms[(4 * s + fq) + (8 * g + (fi & 7)) * (TI_N + 1)];
+      bz[s] = (fi < 8) ? m.x : m.y;
+    }
+    cplx o0 = cmk(0, 0), o1 = cmk(0, 0);
+    tile_mv8(xt, bz, o0, o1, 1.0);
+    Wo[row + (8 * g + fq) * TI_N] = o0;
+    Wo[row + (8 * g + 4 + fq) * TI_N] = o1;
+  }
 }
 
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv) {

@@ -109,6 +109,42 @@ __device__ inline double l1abs(cplx v) { return fabs(v.x) + fabs(v.y); }
 typedef double st_v2 __attribute__((ext_vector_type(2)));
 __device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
 __device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
+// Product of a 64 x 64 complex tile with a group of eight complex columns on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64), both operands in registers, for a
+// workgroup whose wavefront w owns rows 16 w .. 16 w + 15.  Lane (fi, fq) =
+// (l % 16, l / 16) holds
+//   t[s]  = M(16 w + fi, 4 s + fq), s = 0..15  (the MFMA's row operand), and
+//   bz[s] = Re Z(4 s + fq, fi % 8) for fi < 8, Im Z(4 s + fq, fi % 8) otherwise:
+// the sixteen real columns [Re Z | Im Z] of the group.  C1 = Re(M) [Re Z | Im Z]
+// and C2 = Im(M) [Re Z | Im Z] are accumulated in two chains each (even and odd
+// s); lane l, register r of a 16 x 16 result holds row l % 16 and real column
+// 4 r + l / 16, so the lane forms its own complex outputs
+//   o0 += sign (M Z)(16 w + fi, fq),  o1 += sign (M Z)(16 w + fi, 4 + fq).
+// Needs all 64 lanes of the wavefront.
+typedef double tv_dbl4 __attribute__((ext_vector_type(4)));
+__device__ inline void tile_mv8(const st_v2 (&t)[16], const double (&bz)[16], cplx &o0, cplx &o1, double sign) {
+  tv_dbl4 c1[2], c2[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c1[h][r] = c2[h][r] = 0.0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    c1[s & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bz[s], t[s].x, c1[s & 1], 0, 0, 0);
+    c2[s & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bz[s], t[s].y, c2[s & 1], 0, 0, 0);
+  }
+  double a[4], b[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    a[r] = c1[0][r] + c1[1][r];
+    b[r] = c2[0][r] + c2[1][r];
+  }
+  o0.x += sign * (a[0] - b[2]);
+  o0.y += sign * (a[2] + b[0]);
+  o1.x += sign * (a[1] - b[3]);
+  o1.y += sign * (a[3] + b[1]);
+}
+
 // candidate order: larger value wins, then the smaller row
 __device__ inline bool better(double v, long g, double bv, long bg) {
   return (v > bv) || (v == bv && g >= 0 && (bg < 0 || g < bg));
@@ -144,7 +180,7 @@ struct bm_problem {
   cplx *lu;             // factor storage: U33 (mixed, N x N) or the ordinary 2N x 2N matrix
   int32_t *ipiv;        // nf, 0-based LAPACK-style interchanges
   int32_t *perm;        // nf: row perm[i] of the factored matrix is row i of P A
-  cplx *dinv;           // inverses of the 64 x 64 diagonal blocks of L and U
+  cplx *dinv;           // per 64-row block: inverse diagonal blocks of L and U and W (BM_DINV_TILES)
   cplx *work_g;         // nf x BM_MAX_NRHS: permuted right-hand sides
   cplx *work_p;         // split-K partial sums of the skinny GEMMs
   int32_t *dev_err;     // device-side flags: [0] error (bounded wait), [1] getrf info,
@@ -194,6 +230,9 @@ int bm_check_params(const bm_params *prm);
 int bm_fill_u64(hipStream_t s, void *p, size_t n, unsigned long long v);
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                  bm_getrf_ws *w, int gemm32);
+// Per 64-row block b, BM_DINV_TILES column-major 64 x 64 tiles at dinv + b * BM_DINV_TILES * 4096:
+//   Linv_b, Uinv_b, WL_b = Linv_b L(b, b - 1) (b > 0), WU_b = Uinv_b U(b, b + 1) (b < last)
+#define BM_DINV_TILES 4
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);
 
 // solve support (bm_solve.hip): the composed row permutation, gathers, the skinny

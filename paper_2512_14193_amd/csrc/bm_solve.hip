@@ -160,58 +160,29 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 
 // ---------------------------------------------------------------------------
 // blocked triangular solve with the inverted 64 x 64 diagonal blocks
-//   lower (unit):  x_b = Linv_b (c_b - sum_{k<b} L_bk x_k)
-//   upper:         x_b = Uinv_b (c_b - sum_{k>b} U_bk x_k)
+//   lower (unit):  x_b = Linv_b (c_b - sum_{k<b-1} L_bk x_k) - WL_b x_{b-1}
+//   upper:         x_b = Uinv_b (c_b - sum_{k>b+1} U_bk x_k) - WU_b x_{b+1}
+// with WL_b = Linv_b L_{b,b-1} and WU_b = Uinv_b U_{b,b+1} formed beside the
+// inverses, so that only one block product lies between the arrival of the block
+// solved last before b and the publication of x_b.
 // One workgroup per block.  Blocks take tickets in launch order, so a workgroup
 // only waits for blocks held by workgroups that started before it.  A solved block
 // is published to zbuf (pre-filled with an all-ones pattern) with agent-scope
-// stores and consumers poll its words until none is the pattern: the data is the
-// synchronisation.  The next off-diagonal tile (and, before the last dependency,
-// the inverse diagonal block) is fetched into registers while the current one is
-// consumed.
+// stores, and every lane polls the words it uses as a matrix-core operand until
+// none is the pattern: the data is the synchronisation, and a wavefront goes on
+// as soon as its own operands are there.  The operand tiles (off-diagonal blocks,
+// inverse, W) are loaded from global memory straight into the registers of the
+// MFMA row operand, one tile ahead of its use.
 // ---------------------------------------------------------------------------
 #define TS_NB BM_DIAG_NB
-#define TS_RG (BM_MAX_NRHS / 4)  // right-hand sides per thread
 #define ZSENT 0xFFFFFFFFFFFFFFFFULL
 
-// acc[u] += sign * (M Zs)[rr][rg + 4u] on the FP64 matrix cores, for the thread
-// with row rr = 16 w + (l % 16) and right-hand-side group rg = l / 16 (w = wavefront,
-// l = lane).  Per group of eight right-hand sides the B operand's 16 columns are
-// their real parts followed by their imaginary parts, so C1 = Re(M) B and
-// C2 = Im(M) B give Re = C1[:, re] - C2[:, im] and Im = C1[:, im] + C2[:, re] with
-// no padding; lane l, register r of the 16 x 16 result holds row l % 16, column
-// 4 r + l / 16, so every lane combines its own registers.  Tiles are zero-padded
-// to 64 x 64 and Zs to BM_MAX_NRHS columns.  Needs all 64 lanes of every wavefront.
-typedef double tv_dbl4 __attribute__((ext_vector_type(4)));
-__device__ inline void block_mv(const cplx (*M)[TS_NB + 1], const cplx (*Zs)[BM_MAX_NRHS + 1], int nrhs,
-                                cplx (&acc)[TS_RG], double sign) {
-  const int lane = threadIdx.x & 63, fi = lane & 15, fq = lane >> 4;
-  const int row = 16 * (threadIdx.x >> 6) + fi;
-#pragma unroll
-  for (int b = 0; b < BM_MAX_NRHS / 8; ++b) {
-    if (8 * b < nrhs) {
-      tv_dbl4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
-      const int zc = 8 * b + (fi & 7);
-#pragma unroll 4
-      for (int k4 = 0; k4 < TS_NB; k4 += 4) {
-        const cplx m = M[row][k4 + fq];
-        const cplx z = Zs[k4 + fq][zc];
-        const double bz = (fi < 8) ? z.x : z.y;
-        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(bz, m.x, c1, 0, 0, 0);
-        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bz, m.y, c2, 0, 0, 0);
-      }
-      acc[2 * b] = cadd(acc[2 * b], cscale(cmk(c1[0] - c2[2], c1[2] + c2[0]), sign));
-      acc[2 * b + 1] = cadd(acc[2 * b + 1], cscale(cmk(c1[1] - c2[3], c1[3] + c2[1]), sign));
-    }
-  }
-}
-
-template <bool LOWER>
+// NG groups of eight right-hand sides (nrhs <= 8 NG): each lane holds 2 NG of them
+template <bool LOWER, int NG>
 __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long ld, const cplx *dinv, cplx *X, long ldx,
                                                    int nrhs, int32_t *ticket, cplx *zbuf, int32_t *dev_err) {
   __shared__ int s_t;
-  __shared__ cplx Ls[TS_NB][TS_NB + 1];
-  __shared__ cplx Z[TS_NB][BM_MAX_NRHS + 1];
+  __shared__ cplx Z[TS_NB][8 * NG + 1];
   const int nblk = (n + TS_NB - 1) / TS_NB;
   if (threadIdx.x == 0) s_t = atomicAdd(ticket, 1);
   __syncthreads();
@@ -219,116 +190,134 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   const int b = LOWER ? t : nblk - 1 - t;
   const int o = b * TS_NB;
   const int nb = (n - o < TS_NB) ? n - o : TS_NB;
-  // row and right-hand-side group of the thread, in the matrix cores' result layout
-  const int rr = 16 * (threadIdx.x >> 6) + (threadIdx.x & 15), rg = (threadIdx.x >> 4) & 3;
-  const int nper = (nrhs + 3) / 4;
-  cplx acc[TS_RG];
+  // lane (fi, fq) of wavefront w: row rr of the block; its right-hand sides are
+  // fq + 4 u (u = 2 g and 2 g + 1 for the group g of eight), as tile_mv8 leaves them
+  const int lane = threadIdx.x & 63, fi = lane & 15, fq = lane >> 4;
+  const int rr = 16 * (threadIdx.x >> 6) + fi;
+  cplx acc[2 * NG], xv[2 * NG];
 #pragma unroll
-  for (int u = 0; u < TS_RG; ++u) {
-    const int rs = rg + 4 * u;
-    acc[u] = (u < nper && rr < nb && rs < nrhs) ? X[(o + rr) + (long)rs * ldx] : cmk(0, 0);
+  for (int u = 0; u < 2 * NG; ++u) {
+    const int rs = fq + 4 * u;
+    acc[u] = (rr < nb && rs < nrhs) ? X[(o + rr) + (long)rs * ldx] : cmk(0, 0);
+    xv[u] = cmk(0, 0);
   }
   const int ndep = LOWER ? b : nblk - 1 - b;
-  const cplx *Di = dinv + (size_t)b * 2 * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
-  // this thread's 16 elements of the next 64 x 64 tile (column-major order), all
-  // loads in flight together: an element outside a ragged tile reads the tile's
-  // first element and is replaced by zero when the tile goes to LDS
-  st_v2 lt[16];
-  auto fetch_tile = [&](int k) {
-    const int ko = k * TS_NB;
-    const int kn = (n - ko < TS_NB) ? n - ko : TS_NB;
+  // operand tiles in the order they are used: the off-diagonal blocks of every
+  // dependency but the last (in the order the dependencies are solved), the
+  // inverse diagonal block, then W if there is a dependency
+  const int nd1 = ndep > 0 ? ndep - 1 : 0;
+  const int nitems = nd1 + 1 + (ndep > 0);
+  const cplx *Dt = dinv + (size_t)b * BM_DINV_TILES * TS_NB * TS_NB + (LOWER ? 0 : TS_NB * TS_NB);
+  auto dep_block = [&](int i) { return LOWER ? i : nblk - 1 - i; };
+  auto load_item = [&](int i, st_v2(&tl)[16]) {
+    if (i < nd1) {
+      // rows beyond a ragged block b and columns beyond a ragged block k read the
+      // tile's first element: the rows are never published and the columns meet
+      // zero operands
+      const int ko = dep_block(i) * TS_NB, kn = (n - ko < TS_NB) ? n - ko : TS_NB;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int r = idx % TS_NB, c = idx / TS_NB;
-      lt[e] = st_ld(LU, (r < nb && c < kn) ? (o + r) + (long)(ko + c) * ld : o + (long)ko * ld);
+      for (int s = 0; s < 16; ++s) {
+        const int c = 4 * s + fq;
+        tl[s] = st_ld(LU, (rr < nb && c < kn) ? (o + rr) + (long)(ko + c) * ld : o + (long)ko * ld);
+      }
+    } else {
+      const cplx *D = Dt + (i > nd1 ? 2 * TS_NB * TS_NB : 0);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) tl[s] = st_ld(D, rr + (4 * s + fq) * TS_NB);
     }
   };
-  auto fetch_dinv = [&]() {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) lt[e] = st_ld(Di, threadIdx.x + 256 * e);
-  };
-  if (ndep > 0) fetch_tile(LOWER ? 0 : nblk - 1);
-  else fetch_dinv();
   bool ok = true;
-  for (int d = 0; d < ndep; ++d) {
-    const int k = LOWER ? d : nblk - 1 - d;  // dependencies in the order they are solved
+  // The B operand of group g from solved block k.  A solved block is published in
+  // the order its consumers read it: word (16 g + s) * 64 + l holds lane l's operand
+  // of step s (row 4 s + l / 16 % 4, right-hand side 8 g + l % 8, real part for
+  // l % 16 < 8), so each load instruction of a wavefront reads 512 contiguous
+  // bytes.  Waits until every word the lane uses is published (rows beyond a ragged
+  // block and absent right-hand sides are zero).
+  auto poll = [&](int k, int g, double(&bz)[16]) {
+    const unsigned long long *zw =
+        (const unsigned long long *)(zbuf + (size_t)k * TS_NB * BM_MAX_NRHS) + (size_t)g * 16 * 64 + lane;
     const int kn = (n - k * TS_NB < TS_NB) ? n - k * TS_NB : TS_NB;
+    const bool colok = 8 * g + (fi & 7) < nrhs;
+    unsigned long long v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int r = idx % TS_NB, c = idx / TS_NB;
-      Ls[r][c] = (r < nb && c < kn) ? cmk(lt[e].x, lt[e].y) : cmk(0, 0);
-    }
-    if (d + 1 < ndep) fetch_tile(LOWER ? d + 1 : nblk - 2 - d);
-    else fetch_dinv();
-    {
-      // poll the solved block k: every load of the round is issued before any is checked
-      const unsigned long long *zb = (const unsigned long long *)(zbuf + (size_t)k * TS_NB * BM_MAX_NRHS);
-      unsigned long long zx[TS_NB * BM_MAX_NRHS / 256], zy[TS_NB * BM_MAX_NRHS / 256];
-      bool need[TS_NB * BM_MAX_NRHS / 256];
+    for (int s = 0; s < 16; ++s) v[s] = ld_agent(zw + 64 * s);
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      bool all = true;
 #pragma unroll
-      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
-        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
-        need[e] = (sr < kn && c < nrhs);
-        if (need[e]) {
-          zx[e] = ld_agent(zb + 2 * idx);
-          zy[e] = ld_agent(zb + 2 * idx + 1);
+      for (int s = 0; s < 16; ++s) {
+        if (colok && 4 * s + fq < kn && v[s] == ZSENT) {
+          all = false;
+          v[s] = ld_agent(zw + 64 * s);
         }
       }
-      const unsigned long long t0 = wall_clock64();
-      for (;;) {
-        bool all = true;
+      if (all) break;
+      if (!ok || wait_expired(t0)) {
+        if (ok) atomicOr(dev_err, 1);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
 #pragma unroll
-        for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
-          if (need[e] && (zx[e] == ZSENT || zy[e] == ZSENT)) {
-            all = false;
-            const int idx = threadIdx.x + 256 * e;
-            zx[e] = ld_agent(zb + 2 * idx);
-            zy[e] = ld_agent(zb + 2 * idx + 1);
+    for (int s = 0; s < 16; ++s) bz[s] = (colok && 4 * s + fq < kn) ? __longlong_as_double((long long)v[s]) : 0.0;
+  };
+  auto run_item = [&](int i, const st_v2(&tl)[16]) {
+    if (i < nd1 || i > nd1) {
+      // acc -= M_bk x_k (a dependency but the last), or xv -= W_b x_k (the last one)
+      const int k = (i < nd1) ? dep_block(i) : (LOWER ? b - 1 : b + 1);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (8 * g < nrhs) {
+          double bz[16];
+          poll(k, g, bz);
+          if (i < nd1)
+            tile_mv8(tl, bz, acc[2 * g], acc[2 * g + 1], -1.0);
+          else
+            tile_mv8(tl, bz, xv[2 * g], xv[2 * g + 1], -1.0);
+        }
+      }
+    } else {
+      // xv = inv(D_b) acc: the residual of the whole block goes through LDS
+#pragma unroll
+      for (int u = 0; u < 2 * NG; ++u) Z[rr][fq + 4 * u] = (rr < nb) ? acc[u] : cmk(0, 0);
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (8 * g < nrhs) {
+          double bz[16];
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const cplx z = Z[4 * s + fq][8 * g + (fi & 7)];
+            bz[s] = (fi < 8) ? z.x : z.y;
           }
+          tile_mv8(tl, bz, xv[2 * g], xv[2 * g + 1], 1.0);
         }
-        if (all) break;
-        if (!ok || wait_expired(t0)) {
-          if (ok) atomicOr(dev_err, 1);
-          ok = false;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-#pragma unroll
-      for (int e = 0; e < TS_NB * BM_MAX_NRHS / 256; ++e) {
-        const int idx = threadIdx.x + 256 * e, sr = idx % TS_NB, c = idx / TS_NB;
-        // rows beyond a ragged block are zero so that the fixed-size products stay exact
-        Z[sr][c] = need[e] ? cmk(__longlong_as_double((long long)zx[e]), __longlong_as_double((long long)zy[e]))
-                           : cmk(0, 0);
       }
     }
-    __syncthreads();
-    block_mv(Ls, Z, nrhs, acc, -1.0);
-    __syncthreads();
+  };
+  // the next item's tile is loaded before the current item waits for its block
+  st_v2 ta[16], tb[16];
+  load_item(0, ta);
+  for (int i = 0; i < nitems; i += 2) {
+    if (i + 1 < nitems) load_item(i + 1, tb);
+    run_item(i, ta);
+    if (i + 1 < nitems) {
+      if (i + 2 < nitems) load_item(i + 2, ta);
+      run_item(i + 1, tb);
+    }
   }
-  // diagonal block: x_b = inv(D_b) acc (the inverse is in lt)
+  // publication: row rr, right-hand side 8 g + c of the group -> words
+  // (16 g + rr / 4) * 64 + 16 (rr % 4) + c (+ 8 for the imaginary part)
+  unsigned long long *zo = (unsigned long long *)(zbuf + (size_t)b * TS_NB * BM_MAX_NRHS);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int idx = threadIdx.x + 256 * e;
-    Ls[idx % TS_NB][idx / TS_NB] = cmk(lt[e].x, lt[e].y);
-  }
-#pragma unroll
-  for (int u = 0; u < TS_RG; ++u)
-    if (rg + 4 * u < BM_MAX_NRHS) Z[rr][rg + 4 * u] = (u < nper && rg + 4 * u < nrhs) ? acc[u] : cmk(0, 0);
-  __syncthreads();
-  cplx xv[TS_RG];
-#pragma unroll
-  for (int u = 0; u < TS_RG; ++u) xv[u] = cmk(0, 0);
-  block_mv(Ls, Z, nrhs, xv, 1.0);
-  cplx *zo = zbuf + (size_t)b * TS_NB * BM_MAX_NRHS;
-#pragma unroll
-  for (int u = 0; u < TS_RG; ++u) {
-    const int rs = rg + 4 * u;
-    if (u < nper && rs < nrhs && rr < nb) {
+  for (int u = 0; u < 2 * NG; ++u) {
+    const int rs = fq + 4 * u;
+    if (rs < nrhs && rr < nb) {
       X[(o + rr) + (long)rs * ldx] = xv[u];
-      st_cplx_agent(zo + rr + rs * TS_NB, xv[u]);
+      unsigned long long *q = zo + (size_t)(16 * (u >> 1) + (rr >> 2)) * 64 + 16 * (rr & 3) + (rs & 7);
+      st_agent(q, (unsigned long long)__double_as_longlong(xv[u].x));
+      st_agent(q + 8, (unsigned long long)__double_as_longlong(xv[u].y));
     }
   }
 }
@@ -341,12 +330,13 @@ int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *
   int rc = bm_fill_u64(s, w->solve_sync, 4, 0ull);  // 8 int32 ticket words
   if (!rc) rc = bm_fill_u64(s, w->zbuf, 2 * (size_t)nblk * TS_NB * BM_MAX_NRHS, ~0ull);
   if (rc) return rc;
-  if (lower)
-    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
-                       w->solve_sync, w->zbuf, dev_err);
-  else
-    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
-                       w->solve_sync, w->zbuf, dev_err);
+  typedef void (*trsv_fn)(int, const cplx *, long, const cplx *, cplx *, long, int, int32_t *, cplx *, int32_t *);
+  static const trsv_fn fns[2][3] = {{trsv_kernel<false, 1>, trsv_kernel<false, 2>, trsv_kernel<false, 4>},
+                                    {trsv_kernel<true, 1>, trsv_kernel<true, 2>, trsv_kernel<true, 4>}};
+  const int gi = (nrhs <= 8) ? 0 : (nrhs <= 16) ? 1 : 2;
+  static_assert(BM_MAX_NRHS <= 32, "the triangular solves take at most four groups of eight right-hand sides");
+  hipLaunchKernelGGL(fns[lower ? 1 : 0][gi], dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
+                     w->solve_sync, w->zbuf, dev_err);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
