@@ -62,10 +62,18 @@
 #endif
 #define REC_STRIDE 256
 #if BM_REC_SPREAD
-#define SLOT_ELEMS ((size_t)LU_NB * (PANEL_PMAX + 1) * REC_STRIDE)  // complex values per slot buffer
+#define SLOT_REC_ELEMS ((size_t)LU_NB * (PANEL_PMAX + 1) * REC_STRIDE)  // records of a slot buffer
 #else
-#define SLOT_ELEMS ((size_t)LU_NB * (PANEL_PMAX * (LU_NB + 1) + LU_NB))
+#define SLOT_REC_ELEMS ((size_t)LU_NB * (PANEL_PMAX * (LU_NB + 1) + LU_NB))
 #endif
+// BM_HDR_PACKED = 1 keeps the P headers (value, row) of a column side by side after
+// the records (16 bytes each: one poll instruction reads P / 8 cache lines instead of
+// P lines); 0 keeps each header at the front of its record.
+#ifndef BM_HDR_PACKED
+#define BM_HDR_PACKED 1
+#endif
+#define SLOT_HDR ((int)SLOT_REC_ELEMS)  // header of column c, workgroup g: SLOT_HDR + c P + g
+#define SLOT_ELEMS (SLOT_REC_ELEMS + (size_t)LU_NB * PANEL_PMAX)  // complex values per slot buffer
 
 // 16-byte agent-coherent loads and stores of the exchange records: buffer
 // instructions with the sc1 cache-policy bit (agent scope on gfx94x / gfx950).
@@ -190,6 +198,7 @@ __device__ inline cplx pivot_recip(cplx u) {
 // Exchange layout per column c (rs = record stride, cstride = complex values per column):
 //   slots[c * cstride + g * rs]  record of workgroup g: (value, row), then the row
 //   slots[c * cstride + P * rs]  the diagonal row j + c, by its owner
+//   slots[SLOT_HDR + c * P + g]  the header (value, row) of workgroup g when packed
 template <int RPL>
 __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
                                                     int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
@@ -205,6 +214,10 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
   const int rstr = BM_REC_SPREAD ? REC_STRIDE : rec;
   const int cstride = BM_REC_SPREAD ? (P + 1) * REC_STRIDE : P * rec + jb;
   const __amdgpu_buffer_rsrc_t rs = rec_rsrc(slots);
+  // element of the header of workgroup t for column cc
+  auto hdr_el = [&](int cc, int t) __attribute__((always_inline)) {
+    return BM_HDR_PACKED ? SLOT_HDR + cc * P + t : cc * cstride + t * rstr;
+  };
   const long r0 = (long)j + (long)g * RPW;  // first row of the workgroup
   const int nv = (N - r0 >= RPW) ? RPW : ((N - r0 > 0) ? (int)(N - r0) : 0);
   bool ok = true;
@@ -257,7 +270,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
     };
     // records of column cc: the header (value, row) as soon as the candidate is known
     auto publish_head = [&](int cc, double v, int lr) __attribute__((always_inline)) {
-      if (lane == 0) rec_store(rs, cc * cstride + g * rstr, (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
+      if (lane == 0) rec_store(rs, hdr_el(cc, g), (lr >= 0) ? cmk(v, (double)(r0 + lr)) : cmk(-1.0, -1.0));
     };
     // then (for column 0) the candidate row lr and the diagonal row; columns > cc
     // still owe the update of pivot cc - 1 (multipliers in column cc - 1, pivot row pr)
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       const int base = c * cstride;
       // receive the headers (lanes < P)
       bm_v4i vh;
-      const int eh = (lane < P) ? base + lane * rstr : -1;
+      const int eh = (lane < P) ? hdr_el(c, lane) : -1;
       if (eh >= 0) vh = rec_load(rs, eh);
       {
         const unsigned long long t0 = wall_clock64();
@@ -333,12 +346,12 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       } else {
         // more than 64 workgroups: the headers again through the record buffer
         double lv = -1.0;
-        for (int t = lane; t < P; t += 64) lv = fmax(lv, rec_poll(rs, base + t * rstr, dev_err, ok).x);
+        for (int t = lane; t < P; t += 64) lv = fmax(lv, rec_poll(rs, hdr_el(c, t), dev_err, ok).x);
         lv = wave_max_f64(lv);
         int li = 0x7fffffff;
         if (lv >= 0.0)
           for (int t = lane; t < P; t += 64)
-            if (rec_poll(rs, base + t * rstr, dev_err, ok).x == lv) {
+            if (rec_poll(rs, hdr_el(c, t), dev_err, ok).x == lv) {
               li = t;
               break;
             }
@@ -346,7 +359,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         if (li != 0x7fffffff) {
           ww = li;
           vw = lv;
-          pw = (long)rec_poll(rs, base + li * rstr, dev_err, ok).y;
+          pw = (long)rec_poll(rs, hdr_el(c, li), dev_err, ok).y;
         }
       }
       if (ww < 0) {  // no comparable candidate (a column of NaNs): keep the diagonal row, report it
@@ -583,6 +596,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       ns[2 * (size_t)el] = SENT;
       ns[2 * (size_t)el + 1] = SENT;
     }
+    if (BM_HDR_PACKED)
+      for (int idx = g * SNT + tid; idx < 2 * next_jb * next_P; idx += P * SNT) ns[2 * (size_t)SLOT_HDR + idx] = SENT;
   }
 }
 
@@ -842,6 +857,8 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     const int jb0 = (n < LU_NB) ? n : LU_NB;
     const size_t cstr0 = BM_REC_SPREAD ? (size_t)(shape[1] + 1) * REC_STRIDE : (size_t)shape[1] * (jb0 + 1) + jb0;
     if (int rc0 = bm_fill_u64(s, w->slots, 2 * (size_t)jb0 * cstr0, ~0ull)) return rc0;
+    if (BM_HDR_PACKED)
+      if (int rc0 = bm_fill_u64(s, w->slots + SLOT_HDR, 2 * (size_t)jb0 * shape[1], ~0ull)) return rc0;
   }
   const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
