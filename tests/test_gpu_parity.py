@@ -150,6 +150,16 @@ def test_solve_general_rhs_ragged(form):
     assert rel_cols(X, Xo) < 1e-10
 
 
+@pytest.mark.parametrize("form", ["mixed", "ordinary"])
+@pytest.mark.parametrize("R", [9, 13, 16, 20])
+def test_solve_rhs_group_counts(form, R):
+    """The triangular solves take the right-hand sides in groups of eight (one, two or
+    four groups per launch); partly filled groups on ragged 64-row blocks (N = 296)."""
+    bnd, ph = I.star(296), I.Physics.from_wavenumbers(5.0, 8.0)
+    P, X, Xo = _solve_case(bnd, ph, form, R, True, 100 + R)
+    assert rel_cols(X, Xo) < 1e-10
+
+
 def test_disk_matches_bessel_fourier():
     from tests.test_oracle_solution import disk_series
     w = I.workload("disk256")
