@@ -15,8 +15,8 @@
 //     column.
 //  2. swap_trsm_kernel: the panel's row interchanges, composed into one permutation
 //     of at most 2 jb rows, on every column outside the panel; for the columns right
-//     of the panel also U12 = L11^{-1} A12 by forward substitution, one wavefront per
-//     two columns with lane = row.
+//     of the panel also U12 = L11^{-1} A12 by forward substitution, one or two
+//     columns per wavefront with lane = row.
 //  3. trailing update A22 -= L21 U12 with the MFMA GEMM.
 //  Steps 2 and 3 run first for the next panel's columns only; for all other
 //  columns they run on a second stream while the next panel is factored
@@ -605,10 +605,13 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 // 2. row interchanges outside the panel, and U12 = L11^{-1} A12
 //
 // Workgroups [0, nleft): SWAP_COLS columns each of [0, lcols), interchanges only.
-// Workgroups [nleft, ...): ST_CW columns each of [c0, c1): interchanges, then
+// Workgroups [nleft, ...): CW columns each of [c0, c1): interchanges, then
 // forward substitution with the unit lower L11 (in LDS) on rows j .. j + jb - 1,
-// lane = row, two columns per wavefront, the solved value of row c broadcast from
-// lane c by readlane.
+// lane = row, CW / 4 columns per wavefront, the solved value of row c broadcast
+// from lane c by readlane.  The substitution is a chain of jb - 1 dependent steps
+// whose length is set by the instructions each SIMD issues per step, so the launch
+// on the path to the next panel takes one column per wavefront (CW = 4) and the
+// launches beside the next panel two (CW = 8, half the workgroups).
 // The kernel sits on the path from one panel to the next, so its global loads are
 // issued in batches (each thread's loads of a phase are in flight together):
 // the interchange pairs with L11 and the block rows, then the interchange
@@ -621,10 +624,12 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #define BM_LU_EVENT_FLAGS hipEventDisableSystemFence
 #endif
 #define SWAP_COLS 16
-#define ST_CW 8
+#define ST_CW_NEXT 4  // columns per workgroup, next panel's columns
+#define ST_CW_REST 8  // columns per workgroup, the other columns
 #define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
-#define ST_LDS ((size_t)(LU_NB * LU_NB + ST_CW * LU_NB) * sizeof(cplx))
+#define ST_LDS(cw) ((size_t)(LU_NB * LU_NB + (cw) * LU_NB) * sizeof(cplx))
 
+template <int CW>
 __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int lcols, int c0, int c1,
                                                         const int32_t *swp, int nleft) {
   extern __shared__ cplx sm[];
@@ -652,11 +657,13 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     }
     return;
   }
-  const int cw0 = c0 + ((int)blockIdx.x - nleft) * ST_CW;
-  const int ncw = (c1 - cw0 < ST_CW) ? c1 - cw0 : ST_CW;
+  static_assert(CW % 4 == 0 && CW * LU_NB % 256 == 0 && ST_NPAIR * CW % 256 == 0, "column split");
+  constexpr int CPW = CW / 4;  // columns per wavefront
+  const int cw0 = c0 + ((int)blockIdx.x - nleft) * CW;
+  const int ncw = (c1 - cw0 < CW) ? c1 - cw0 : CW;
   cplx *Ls = sm;                 // L11, column-major, ld LU_NB
-  cplx *X = Ls + LU_NB * LU_NB;  // rows j .. j + jb - 1 of the columns, [ST_CW][LU_NB]
-  constexpr int LPT_L = LU_NB * LU_NB / 256, LPT_X = ST_CW * LU_NB / 256, LPT_S = ST_NPAIR * ST_CW / 256;
+  cplx *X = Ls + LU_NB * LU_NB;  // rows j .. j + jb - 1 of the columns, [CW][LU_NB]
+  constexpr int LPT_L = LU_NB * LU_NB / 256, LPT_X = CW * LU_NB / 256, LPT_S = ST_NPAIR * CW / 256;
   // phase 1: the pairs, L11 and the block rows, all in flight together
   const long a0 = (long)j + (long)j * lda;  // L11's first element: the address of items outside the block
   const int pr_v = swp[1 + ((tid < 2 * np) ? tid : 0)];
@@ -702,10 +709,13 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
-  const int ca = 2 * wave, cb = 2 * wave + 1;
   const bool row_ok = lane < jb;
-  cplx xa = (row_ok && ca < ncw) ? X[ca * LU_NB + lane] : cmk(0, 0);
-  cplx xb = (row_ok && cb < ncw) ? X[cb * LU_NB + lane] : cmk(0, 0);
+  cplx xs[CPW];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int cl = CPW * wave + q;
+    xs[q] = (row_ok && cl < ncw) ? X[cl * LU_NB + lane] : cmk(0, 0);
+  }
   // the multipliers of eight steps are read from LDS ahead of them, so that a step's
   // chain is only the broadcast of row c and one complex multiply-add
   for (int c0 = 0; c0 < jb - 1; c0 += 8) {
@@ -722,15 +732,17 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
       const int c = c0 + u;
       if (c < jb - 1) {
         const cplx l = cmk(lvv[u].x, lvv[u].y);
-        const cplx ya = readlane_c(xa, c), yb = readlane_c(xb, c);
-        xa = cfms(xa, l, ya);
-        xb = cfms(xb, l, yb);
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) xs[q] = cfms(xs[q], l, readlane_c(xs[q], c));
       }
     }
   }
   if (row_ok) {
-    if (ca < ncw) A[(j + lane) + (long)(cw0 + ca) * lda] = xa;
-    if (cb < ncw) A[(j + lane) + (long)(cw0 + cb) * lda] = xb;
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int cl = CPW * wave + q;
+      if (cl < ncw) A[(j + lane) + (long)(cw0 + cl) * lda] = xs[q];
+    }
   }
 }
 
@@ -828,8 +840,10 @@ int bm_getrf_prepare() {
     for (int k = 0; k < 2; ++k)
       BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)PANEL_LDS_ALLOC));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)ST_LDS));
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel<ST_CW_NEXT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_NEXT)));
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel<ST_CW_REST>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_REST)));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)TI_LDS));
     panel_attr_done[dev] = 1;
@@ -889,11 +903,16 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
     if (pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
-    auto update = [&](hipStream_t st, int lcols, int c0, int c1) -> int {
-      const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 - c0 + ST_CW - 1) / ST_CW;
+    auto update = [&](hipStream_t st, int lcols, int c0, int c1, bool next) -> int {
+      const int cw = next ? ST_CW_NEXT : ST_CW_REST;
+      const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 - c0 + cw - 1) / cw;
       if (nleft + nright > 0) {
-        hipLaunchKernelGGL(swap_trsm_kernel, dim3(nleft + nright), dim3(256), ST_LDS, st, A, ldal, j, jb, lcols, c0,
-                           c1, (const int32_t *)swp, nleft);
+        if (next)
+          hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_NEXT>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A,
+                             ldal, j, jb, lcols, c0, c1, (const int32_t *)swp, nleft);
+        else
+          hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_REST>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A,
+                             ldal, j, jb, lcols, c0, c1, (const int32_t *)swp, nleft);
         BM_HIP_TRY(hipGetLastError());
       }
       if (nr > 0 && c1 > c0)
@@ -902,11 +921,11 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
                                                                 A + jn + (long)c0 * lda, lda);
       return BM_OK;
     };
-    int rc = update(s, 0, jn, jn + jbn);
+    int rc = update(s, 0, jn, jn + jbn, true);
     if (rc) return rc;
     BM_HIP_TRY(hipEventRecord(w->e_next, s));
     BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
-    rc = update(w->aux, j, jn + jbn, n);
+    rc = update(w->aux, j, jn + jbn, n, false);
     if (rc) return rc;
     BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
   }
