@@ -395,44 +395,76 @@ int bm_launch_rhs_plane_wave(bm_problem *p, int nrhs, const double *theta, cplx 
 
 // ---------------------------------------------------------------------------
 // Far field: F[a, r] = (2pi/N) sum_j [-i k0 (n_j . xh) u_jr - eps0 |x'_j| q_jr] exp(-i k0 xh . x_j)
-// One workgroup per observation angle; deterministic tree reduction.
+// One workgroup of FF_NT threads per observation angle, two nodes per thread and
+// step with their loads in flight together; the sums are reduced in a fixed order
+// (butterfly within each wavefront, then the wavefronts' partials in index order),
+// so the result does not depend on timing.
 // ---------------------------------------------------------------------------
 #define FF_RMAX 8
-__global__ __launch_bounds__(256) void far_field_kernel(int N, int nrhs, const double2 *x, const double2 *dx,
-                                                        cplx k0, double eps0, const cplx *X, long ldx,
-                                                        const double *theta, cplx *F, long ldf) {
+#define FF_NT 512
+__device__ inline double ff_xor(double v, int m) {
+  const int lo = __shfl_xor(__double2loint(v), m), hi = __shfl_xor(__double2hiint(v), m);
+  return __hiloint2double(hi, lo);
+}
+__global__ __launch_bounds__(FF_NT) void far_field_kernel(int N, int nrhs, const double2 *x, const double2 *dx,
+                                                          cplx k0, double eps0, const cplx *X, long ldx,
+                                                          const double *theta, cplx *F, long ldf) {
   const int a = blockIdx.x;
   double s, c;
   sincos(theta[a], &s, &c);
   cplx acc[FF_RMAX];
 #pragma unroll
   for (int r = 0; r < FF_RMAX; ++r) acc[r] = cmk(0, 0);
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    const double2 xj = x[j], aj = dx[j];
-    const double sj = sqrt(aj.x * aj.x + aj.y * aj.y);
-    const double nx = aj.y * c - aj.x * s;  // n_j . xh
-    const cplx e = cexp_d(cmul(cmk(0.0, -(c * xj.x + s * xj.y)), k0));
-    const cplx cu = cmul(cmk(0.0, -nx), k0);  // -i k0 (n.xh)
+  for (int j0 = threadIdx.x; j0 < N; j0 += 2 * FF_NT) {
+    // both nodes' values first (a second node past N repeats the first and is not added)
+    int jj[2];
+    double2 xj[2], aj[2];
+    cplx u[2][FF_RMAX], q[2][FF_RMAX];
 #pragma unroll
-    for (int r = 0; r < FF_RMAX; ++r) {
-      if (r < nrhs) {
-        const cplx u = X[j + (long)r * ldx], q = X[N + j + (long)r * ldx];
-        const cplx v = csub(cmul(cu, u), cscale(q, eps0 * sj));
+    for (int h = 0; h < 2; ++h) {
+      jj[h] = (j0 + h * FF_NT < N) ? j0 + h * FF_NT : j0;
+      xj[h] = x[jj[h]];
+      aj[h] = dx[jj[h]];
+#pragma unroll
+      for (int r = 0; r < FF_RMAX; ++r) {
+        const int rr = (r < nrhs) ? r : 0;
+        u[h][r] = X[jj[h] + (long)rr * ldx];
+        q[h][r] = X[N + jj[h] + (long)rr * ldx];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && j0 + FF_NT >= N) break;
+      const double sj = sqrt(aj[h].x * aj[h].x + aj[h].y * aj[h].y);
+      const double nx = aj[h].y * c - aj[h].x * s;  // n_j . xh
+      const cplx e = cexp_d(cmul(cmk(0.0, -(c * xj[h].x + s * xj[h].y)), k0));
+      const cplx cu = cmul(cmk(0.0, -nx), k0);  // -i k0 (n.xh)
+#pragma unroll
+      for (int r = 0; r < FF_RMAX; ++r) {
+        const cplx v = csub(cmul(cu, u[h][r]), cscale(q[h][r], eps0 * sj));
         acc[r] = cadd(acc[r], cmul(v, e));
       }
     }
   }
-  __shared__ cplx red[256];
-  const double h = 2.0 * BM_PI / N;
-  for (int r = 0; r < nrhs && r < FF_RMAX; ++r) {
-    red[threadIdx.x] = acc[r];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
-      __syncthreads();
+  // butterfly over the 64 lanes of each wavefront (every lane ends with the sum)
+#pragma unroll
+  for (int r = 0; r < FF_RMAX; ++r)
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      acc[r].x += ff_xor(acc[r].x, m);
+      acc[r].y += ff_xor(acc[r].y, m);
     }
-    if (threadIdx.x == 0) F[a + (long)r * ldf] = cscale(red[0], h);
-    __syncthreads();
+  __shared__ cplx red[FF_NT / 64][FF_RMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < FF_RMAX; ++r) red[wave][r] = acc[r];
+  __syncthreads();
+  if ((int)threadIdx.x < nrhs && (int)threadIdx.x < FF_RMAX) {
+    const int r = threadIdx.x;
+    cplx t = red[0][r];
+    for (int w = 1; w < FF_NT / 64; ++w) t = cadd(t, red[w][r]);
+    F[a + (long)r * ldf] = cscale(t, 2.0 * BM_PI / N);
   }
 }
 
@@ -440,7 +472,7 @@ int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int
                         cplx *F, int64_t ldf) {
   for (int r0 = 0; r0 < nrhs; r0 += FF_RMAX) {
     const int nr = (nrhs - r0 < FF_RMAX) ? nrhs - r0 : FF_RMAX;
-    hipLaunchKernelGGL(far_field_kernel, dim3(nang), dim3(256), 0, p->stream, p->n, nr, (const double2 *)p->geo,
+    hipLaunchKernelGGL(far_field_kernel, dim3(nang), dim3(FF_NT), 0, p->stream, p->n, nr, (const double2 *)p->geo,
                        (const double2 *)(p->geo + 2 * p->n), p->phys.k0, p->phys.eps0, X + (long)r0 * ldx,
                        (long)ldx, theta, F + (long)r0 * ldf, (long)ldf);
     BM_HIP_TRY(hipGetLastError());
