@@ -50,8 +50,11 @@ __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+#ifndef GM_OCC
+#define GM_OCC 2  // workgroups per CU the register allocation is bounded for
+#endif
 template <bool BETA0, bool M3>
-__global__ __launch_bounds__(256, 2) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
+__global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
                                                     long lda, const cplx *__restrict__ B, long ldb, cplx beta,
                                                     cplx *__restrict__ C, long ldc, int tiles_m) {
   constexpr int GM_BK = M3 ? GM_BK3 : GM_BK4;
