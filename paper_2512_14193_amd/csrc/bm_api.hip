@@ -256,6 +256,7 @@ static int solve_pass(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, cplx *
     if (rc) return rc;
   }
   rc = bm_launch_gather(p->stream, nf, nr, p->perm, X3, ldx, Y, nf);
+  if (!rc) rc = bm_trsv_reset(p->stream, p->gws, nf);
   if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
   if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
   if (rc) return rc;

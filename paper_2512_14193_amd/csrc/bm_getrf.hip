@@ -757,8 +757,7 @@ bm_getrf_ws *bm_getrf_ws_create(int n) {
   const int nblk = (n + BM_DIAG_NB - 1) / BM_DIAG_NB;
   bool ok = hipMalloc(&w->slots, sizeof(cplx) * 2 * SLOT_ELEMS) == hipSuccess;
   ok = ok && hipMalloc(&w->swp, sizeof(int32_t) * (size_t)w->npanel * SWP_STRIDE) == hipSuccess;
-  ok = ok && hipMalloc(&w->solve_sync, sizeof(int32_t) * 8) == hipSuccess;
-  ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS) == hipSuccess;
+  ok = ok && hipMalloc(&w->zbuf, sizeof(cplx) * (1 + 2 * (size_t)nblk * BM_DIAG_NB * BM_MAX_NRHS)) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) == hipSuccess;
   // the lookahead events only order the two streams of this device: no system-scope
   // fence (the host never inspects them)
@@ -775,7 +774,6 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   if (!w) return;
   (void)hipFree(w->slots);
   (void)hipFree(w->swp);
-  (void)hipFree(w->solve_sync);
   (void)hipFree(w->zbuf);
   if (w->aux) {
     (void)hipStreamSynchronize(w->aux);
@@ -827,8 +825,8 @@ static bool panel_shape(int R, int ncu, int *rpl, int *P_out) {
 
 size_t bm_getrf_ws_bytes(int n) {
   const size_t npanel = (size_t)(n + LU_NB - 1) / LU_NB, nblk = (size_t)(n + BM_DIAG_NB - 1) / BM_DIAG_NB;
-  return sizeof(cplx) * 2 * SLOT_ELEMS + sizeof(int32_t) * npanel * SWP_STRIDE + sizeof(int32_t) * 8 +
-         sizeof(cplx) * nblk * BM_DIAG_NB * BM_MAX_NRHS;
+  return sizeof(cplx) * 2 * SLOT_ELEMS + sizeof(int32_t) * npanel * SWP_STRIDE +
+         sizeof(cplx) * (1 + 2 * nblk * BM_DIAG_NB * BM_MAX_NRHS);
 }
 
 // Dynamic-LDS limits of the factorisation kernels on the current device (once per

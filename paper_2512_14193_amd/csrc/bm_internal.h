@@ -72,8 +72,7 @@ struct bm_getrf_ws {
   int n, npanel;
   cplx *slots;         // 2 buffers of per-column exchange records (candidates and diagonal row)
   int32_t *swp;        // per panel: count, then (dst, src) pairs
-  int32_t *solve_sync; // ticket counter of the blocked triangular solves
-  cplx *zbuf;          // solved blocks published by the triangular solves
+  cplx *zbuf;          // triangular solves: [ticket counters][lower solve's blocks][upper solve's blocks]
   hipStream_t aux;     // second stream: the trailing update of panel k runs beside panel k + 1
   hipEvent_t e_next, e_rest;
 };
@@ -243,6 +242,8 @@ int bm_launch_gather(hipStream_t s, int nf, int nrhs, const int32_t *perm, const
 size_t bm_gemv_work_elems(int m, int k);
 int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64_t lda, const cplx *B, int64_t ldb,
                        cplx *C, int64_t ldc, cplx *work);
+// bm_trsv_reset fills the solves' exchange buffer once for a lower and an upper solve
+int bm_trsv_reset(hipStream_t s, bm_getrf_ws *w, int n);
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
 // refinement support: R = B - [X(0:n12, :); 0] (rows), X += D, per-column squared norms

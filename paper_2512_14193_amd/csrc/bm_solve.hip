@@ -170,7 +170,9 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 // inverses, so that only one block product lies between the arrival of the block
 // solved last before b and the publication of x_b.
 // One workgroup per block.  Blocks take tickets in launch order, so a workgroup
-// only waits for blocks held by workgroups that started before it.  A solved block
+// only waits for blocks held by workgroups that started before it.  The ticket
+// counters and both solves' block areas share one buffer that a single fill with
+// the all-ones pattern prepares (a counter then starts at -1).  A solved block
 // is published to zbuf (pre-filled with an all-ones pattern) with agent-scope
 // stores, and every lane polls the words it uses as a matrix-core operand until
 // none is the pattern: the data is the synchronisation, and a wavefront goes on
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   __shared__ int s_t;
   __shared__ cplx Z[TS_NB][8 * NG + 1];
   const int nblk = (n + TS_NB - 1) / TS_NB;
-  if (threadIdx.x == 0) s_t = atomicAdd(ticket, 1);
+  if (threadIdx.x == 0) s_t = atomicAdd(ticket, 1) + 1;  // the counter starts at -1
   __syncthreads();
   const int t = s_t;
   const int b = LOWER ? t : nblk - 1 - t;
@@ -326,21 +328,28 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
   }
 }
 
+// Layout of w->zbuf: one complex value holding the two ticket counters (lower,
+// upper), then the lower solve's blocks, then the upper solve's.
+int bm_trsv_reset(hipStream_t s, bm_getrf_ws *w, int n) {
+  const int nblk = (n + TS_NB - 1) / TS_NB;
+  return bm_fill_u64(s, w->zbuf, 2 * (1 + 2 * (size_t)nblk * TS_NB * BM_MAX_NRHS), ~0ull);
+}
+
+// Needs bm_trsv_reset on the same stream since the last solve of the same kind.
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
   if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
   if (nrhs <= 0 || n <= 0) return BM_OK;
   const int nblk = (n + TS_NB - 1) / TS_NB;
-  int rc = bm_fill_u64(s, w->solve_sync, 4, 0ull);  // 8 int32 ticket words
-  if (!rc) rc = bm_fill_u64(s, w->zbuf, 2 * (size_t)nblk * TS_NB * BM_MAX_NRHS, ~0ull);
-  if (rc) return rc;
+  int32_t *ticket = (int32_t *)w->zbuf + (lower ? 0 : 1);
+  cplx *zb = w->zbuf + 1 + (lower ? 0 : (size_t)nblk * TS_NB * BM_MAX_NRHS);
   typedef void (*trsv_fn)(int, const cplx *, long, const cplx *, cplx *, long, int, int32_t *, cplx *, int32_t *);
   static const trsv_fn fns[2][3] = {{trsv_kernel<false, 1>, trsv_kernel<false, 2>, trsv_kernel<false, 4>},
                                     {trsv_kernel<true, 1>, trsv_kernel<true, 2>, trsv_kernel<true, 4>}};
   const int gi = (nrhs <= 8) ? 0 : (nrhs <= 16) ? 1 : 2;
   static_assert(BM_MAX_NRHS <= 32, "the triangular solves take at most four groups of eight right-hand sides");
   hipLaunchKernelGGL(fns[lower ? 1 : 0][gi], dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
-                     w->solve_sync, w->zbuf, dev_err);
+                     ticket, zb, dev_err);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
