@@ -159,8 +159,8 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, i
 /* Precision of the following bm_block_lu calls and of the solves with their
  * factors.  BM_PREC_MIXED (mixed formulation only): U33 = -Bot * Top runs on the
  * FP32 matrix cores (operands rounded to complex64, FP32 accumulation, FP64
- * storage); the LU of U33 stays FP64 (its trailing updates are bound by memory
- * traffic, not by the matrix cores).  bm_solve then refines
+ * storage), and so do the LU's trailing updates beyond the next panel (its panels,
+ * the next panel's update and the factors' storage stay FP64).  bm_solve then refines
  * every right-hand side, x <- x + F^{-1} (b - A x) with the FP64 blocks of the
  * exact mixed system in the residual and the mixed-precision factors F, until
  * ||b - A x||_2 <= tol ||b||_2 or max_iter steps; it synchronises the stream

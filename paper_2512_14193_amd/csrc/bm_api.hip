@@ -227,9 +227,9 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
     if (rc) return rc;
   }
   phase_begin(p, BM_PH_LU);
-  // (the trailing updates of the LU have k = 64 and are bound by memory traffic, not
-  // by the matrix cores, so they stay FP64 in either precision)
-  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, 0);
+  // (mixed precision: the trailing updates beside the next panel run on the FP32
+  // matrix cores; the panels, the next panel's own update and the storage stay FP64)
+  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec == BM_PREC_MIXED);
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);

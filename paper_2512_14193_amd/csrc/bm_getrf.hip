@@ -914,9 +914,11 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
         BM_HIP_TRY(hipGetLastError());
       }
       if (nr > 0 && c1 > c0)
-        return (gemm32 ? bm_launch_zgemm32 : bm_launch_zgemm)(st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda, lda,
-                                                                A + j + (long)c0 * lda, lda, one,
-                                                                A + jn + (long)c0 * lda, lda);
+        // gemm32: the FP32 matrix cores for the columns beyond the next panel (the
+        // next panel's 64 columns, on the critical path, keep the FP64 shallow kernel)
+        return ((gemm32 && !next) ? bm_launch_zgemm32 : bm_launch_zgemm)(
+            st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda, lda, A + j + (long)c0 * lda, lda, one,
+            A + jn + (long)c0 * lda, lda);
       return BM_OK;
     };
     int rc = update(s, 0, jn, jn + jbn, true);
