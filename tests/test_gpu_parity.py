@@ -100,6 +100,32 @@ def test_zgetrf_vs_numpy(n):
         assert np.all(one(L[k + 1:, k] * U[k, k]) <= one(U[k, k]) * (1 + 1e-13))
 
 
+def test_zgetrf_large():
+    """n = 6244: 98 panels of 128-row workgroups ending on a ragged one, long lookahead
+    updates on the second stream.  The factors solve a system with a known solution
+    (host triangular solves with the returned pivots) and satisfy the partial-pivoting
+    bound."""
+    import scipy.linalg as sla
+    n = 6244
+    rng = np.random.default_rng(6244)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    x = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
+    b = A @ x
+    dA = to_dev(A)
+    piv, info = B.zgetrf(dA)
+    assert info == 0
+    LU = to_np(dA)
+    piv = piv.cpu().numpy()
+    assert np.all((piv >= np.arange(n)) & (piv < n))
+    xs = sla.lu_solve((LU, piv), b)
+    assert np.abs(A @ xs - b).max() < 1e-11 * np.abs(b).max()
+    assert rel_cols(xs, x) < 1e-8
+    one = lambda z: np.abs(z.real) + np.abs(z.imag)  # noqa: E731
+    d = one(np.diag(LU))
+    Lm = np.tril(LU, -1) * np.diag(LU)[None, :]
+    assert np.all(one(Lm) <= d[None, :] * (1 + 1e-13))
+
+
 def test_zgetrf_zero_pivot_info():
     n = 70
     rng = np.random.default_rng(1)
