@@ -90,6 +90,8 @@ def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12):
     refine = P.refine_stats()
     P.set_profiling(False)
     P.sync()  # raises if a kernel reported a device-side error
+    # pivot check on a fresh assembly (the ordinary matrix is factored in place)
+    P.assemble_device(geo, w.physics)
     info = P.block_lu(sync=True)
     if info != 0:
         raise RuntimeError(f"{form}: singular factor, info = {info}")

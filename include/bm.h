@@ -142,7 +142,9 @@ int bm_assemble(bm_problem *p, const bm_geometry *geometry, const bm_params *par
  * (one complex GEMM, m = n = N, k = 2N), then partial-pivot LU of U33;
  * the identity blocks are the pivots of the first 2N columns and the L31, L32,
  * U13, U23 factors are the stored blocks themselves.  Ordinary: partial-pivot LU
- * of the 2N x 2N matrix.  Pivoting: largest |Re| + |Im| in the column.
+ * of the 2N x 2N matrix in place (a second factorisation of an ordinary problem
+ * needs a new bm_assemble: BM_E_STATE otherwise; the mixed blocks stay intact, so a
+ * mixed problem may be factored again).  Pivoting: largest |Re| + |Im| in the column.
  * If `info` is NULL the call is asynchronous.  Otherwise (host pointer) it
  * synchronises the stream and stores the LAPACK-style info: 0, or j > 0 when
  * the pivot of column j (1-based) of the factored matrix is exactly zero.

@@ -7,8 +7,10 @@ the library has not been built this module raises; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -72,6 +74,21 @@ class BMError(RuntimeError):
 
 
 _lib = None
+
+# Handles still open when the interpreter exits are released by an atexit hook,
+# which runs before the HIP runtime's own teardown: no HIP call is made on a
+# runtime that is being destroyed (a handle collected late in finalisation would
+# otherwise synchronise and free streams and memory after it).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -160,6 +177,7 @@ class Problem:
         check(lib().bm_create(self.n, self.form, _stream_handle(self.stream), ctypes.byref(h)), "bm_create")
         self._h = h
         self._keep = []
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -308,6 +326,7 @@ class Server:
         check(lib().bm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bm_server_create")
         self._h = h
         self._keep = {}
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -400,3 +419,4 @@ def zgetrf(A, stream=None):
     info = ctypes.c_int32(0)
     check(lib().bm_zgetrf(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(piv), ctypes.byref(info)), "bm_zgetrf")
     return piv, info.value
+

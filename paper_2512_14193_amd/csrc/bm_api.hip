@@ -51,6 +51,49 @@ static void free_problem(bm_problem *p) {
   delete p;
 }
 
+}  // extern "C"
+
+// Device bytes of every allocation of a problem handle: bm_create allocates
+// exactly these and bm_problem_bytes adds them up (zero: not allocated).
+struct bm_alloc_sizes {
+  size_t geo, wts, top, bot, lu, ipiv, dinv, perm, work_g, work_p, dev_err, ir_r, ir_d, ir_norm;
+};
+
+static bm_alloc_sizes problem_sizes(int n, int formulation) {
+  const size_t N = (size_t)n, nf = (formulation == BM_MIXED) ? N : 2 * N, c = sizeof(cplx);
+  const size_t nblk = (nf + BM_DIAG_NB - 1) / BM_DIAG_NB;
+  const bool mixed = formulation == BM_MIXED;
+  bm_alloc_sizes z;
+  z.geo = sizeof(double) * 8 * N;
+  z.wts = sizeof(double) * 4 * N;
+  z.top = mixed ? c * 2 * N * N : 0;
+  z.bot = mixed ? c * 2 * N * N : 0;
+  z.lu = c * nf * nf;
+  z.ipiv = sizeof(int32_t) * nf;
+  z.dinv = c * nblk * BM_DINV_TILES * BM_DIAG_NB * BM_DIAG_NB;
+  z.perm = sizeof(int32_t) * nf;
+  z.work_g = c * nf * BM_MAX_NRHS;
+  if (mixed) {
+    const size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
+    z.work_p = c * (wp > w2 ? wp : w2);
+  } else {
+    z.work_p = 0;
+  }
+  z.dev_err = sizeof(int32_t) * 4;
+  z.ir_r = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
+  z.ir_d = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
+  z.ir_norm = mixed ? sizeof(double) * 2 * BM_MAX_NRHS : 0;
+  return z;
+}
+
+template <typename T>
+static bool dev_alloc(T **ptr, size_t bytes) {
+  if (bytes == 0) return true;
+  return hipMalloc((void **)ptr, bytes) == hipSuccess;
+}
+
+extern "C" {
+
 int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out) {
   if (!out) return BM_E_ARG;
   *out = nullptr;
@@ -67,33 +110,16 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
     free_problem(p);
     return BM_E_HIP;
   }
-  const size_t N = (size_t)n, nf = (size_t)p->nf;
-  const size_t nblk = (nf + BM_DIAG_NB - 1) / BM_DIAG_NB;
-  bool ok = hipMalloc(&p->geo, sizeof(double) * 8 * N) == hipSuccess;
-  ok = ok && hipMalloc(&p->wts, sizeof(double) * 4 * N) == hipSuccess;
-  if (formulation == BM_MIXED) {
-    ok = ok && hipMalloc(&p->top, sizeof(cplx) * 2 * N * N) == hipSuccess;
-    ok = ok && hipMalloc(&p->bot, sizeof(cplx) * 2 * N * N) == hipSuccess;
-  }
-  ok = ok && hipMalloc(&p->lu, sizeof(cplx) * nf * nf) == hipSuccess;
-  ok = ok && hipMalloc(&p->ipiv, sizeof(int32_t) * nf) == hipSuccess;
-  ok = ok && hipMalloc(&p->dinv, sizeof(cplx) * nblk * BM_DINV_TILES * BM_DIAG_NB * BM_DIAG_NB) == hipSuccess;
-  ok = ok && hipMalloc(&p->perm, sizeof(int32_t) * nf) == hipSuccess;
-  ok = ok && hipMalloc(&p->work_g, sizeof(cplx) * nf * BM_MAX_NRHS) == hipSuccess;
-  if (formulation == BM_MIXED) {
-    size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
-    ok = ok && hipMalloc(&p->work_p, sizeof(cplx) * (wp > w2 ? wp : w2)) == hipSuccess;
-  }
-  ok = ok && hipMalloc(&p->dev_err, sizeof(int32_t) * 4) == hipSuccess;
-  if (formulation == BM_MIXED) {
-    ok = ok && hipMalloc(&p->ir_r, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
-    ok = ok && hipMalloc(&p->ir_d, sizeof(cplx) * 3 * N * BM_MAX_NRHS) == hipSuccess;
-    ok = ok && hipMalloc(&p->ir_norm, sizeof(double) * 2 * BM_MAX_NRHS) == hipSuccess;
-  }
+  const bm_alloc_sizes z = problem_sizes(n, formulation);
+  bool ok = dev_alloc(&p->geo, z.geo) && dev_alloc(&p->wts, z.wts) && dev_alloc(&p->top, z.top) &&
+            dev_alloc(&p->bot, z.bot) && dev_alloc(&p->lu, z.lu) && dev_alloc(&p->ipiv, z.ipiv) &&
+            dev_alloc(&p->dinv, z.dinv) && dev_alloc(&p->perm, z.perm) && dev_alloc(&p->work_g, z.work_g) &&
+            dev_alloc(&p->work_p, z.work_p) && dev_alloc(&p->dev_err, z.dev_err) && dev_alloc(&p->ir_r, z.ir_r) &&
+            dev_alloc(&p->ir_d, z.ir_d) && dev_alloc(&p->ir_norm, z.ir_norm);
   p->prec = BM_PREC_FP64;
   p->ir_tol = 1e-12;
   p->ir_maxit = 10;
-  if (ok) p->gws = bm_getrf_ws_create((int)nf);
+  if (ok) p->gws = bm_getrf_ws_create(p->nf);
   if (!ok || !p->gws) {
     free_problem(p);
     return BM_E_NOMEM;
@@ -161,20 +187,10 @@ int bm_problem_bytes(int32_t n, int32_t formulation, int64_t *bytes) {
   *bytes = 0;
   if (n < 8 || n > 65536 || (n % 2) != 0) return BM_E_ARG;
   if (formulation != BM_MIXED && formulation != BM_ORDINARY) return BM_E_ARG;
-  // the allocations of bm_create, in the same order
-  const size_t N = (size_t)n, nf = (formulation == BM_MIXED) ? N : 2 * N;
-  const size_t nblk = (nf + BM_DIAG_NB - 1) / BM_DIAG_NB, c = sizeof(cplx);
-  size_t b = sizeof(double) * 8 * N + sizeof(double) * 4 * N;
-  if (formulation == BM_MIXED) b += 2 * (c * 2 * N * N);
-  b += c * nf * nf + sizeof(int32_t) * nf + c * nblk * 2 * BM_DIAG_NB * BM_DIAG_NB + sizeof(int32_t) * nf;
-  b += c * nf * BM_MAX_NRHS;
-  if (formulation == BM_MIXED) {
-    const size_t wp = bm_gemv_work_elems(n, 2 * n), w2 = bm_gemv_work_elems(2 * n, n);
-    b += c * (wp > w2 ? wp : w2);
-  }
-  b += sizeof(int32_t) * 2;
-  if (formulation == BM_MIXED) b += 2 * (c * 3 * N * BM_MAX_NRHS) + sizeof(double) * 2 * BM_MAX_NRHS;
-  b += bm_getrf_ws_bytes((int)nf);
+  const bm_alloc_sizes z = problem_sizes(n, formulation);
+  size_t b = z.geo + z.wts + z.top + z.bot + z.lu + z.ipiv + z.dinv + z.perm + z.work_g + z.work_p + z.dev_err +
+             z.ir_r + z.ir_d + z.ir_norm;
+  b += bm_getrf_ws_bytes(formulation == BM_MIXED ? n : 2 * n);
   *bytes = (int64_t)b;
   return BM_OK;
 }
@@ -214,6 +230,9 @@ static int read_dev_err(bm_problem *p, int32_t *info) {
 int bm_block_lu(bm_problem *p, int32_t *info) {
   if (!p) return BM_E_ARG;
   if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
+  // the ordinary matrix is factored in place: a second factorisation needs a new
+  // assembly (the mixed form recomputes U33 from the blocks, which stay intact)
+  if (p->form == BM_ORDINARY && p->state != BM_ST_ASSEMBLED) return BM_E_STATE;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   const int n = p->n, nf = p->nf;
   int rc = BM_OK;

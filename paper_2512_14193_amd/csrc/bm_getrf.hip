@@ -45,33 +45,18 @@
 #define SENT 0xFFFFFFFFFFFFFFFFULL  // empty exchange word (all ones)
 #define SNT 448                   // threads per panel workgroup: one chain + SNB bulk wavefronts
 #define SNB 6
-#ifndef PANEL_RPL1_PMAX
 #define PANEL_RPL1_PMAX 32        // 64 rows per workgroup while P stays within this, else 128
-#endif
 #define PANEL_LDS(rpl) ((size_t)LU_NB * (64 * (rpl) + 1) * sizeof(cplx))
 // LDS requested by every panel launch: more than 160 KB minus any GEMM workgroup's
 // share, so that no workgroup of the concurrent trailing update lands on a CU that
 // runs a panel workgroup (the chain wavefront would lose issue slots)
 #define PANEL_LDS_ALLOC PANEL_LDS(2)
 
-// BM_REC_SPREAD = 1 places the records of one column REC_STRIDE complex values
-// (4 KiB) apart, spreading a column's reads over more memory channels; measured
-// no faster on MI355X than the packed layout, so the packed one is the default.
-#ifndef BM_REC_SPREAD
-#define BM_REC_SPREAD 0
-#endif
-#define REC_STRIDE 256
-#if BM_REC_SPREAD
-#define SLOT_REC_ELEMS ((size_t)LU_NB * (PANEL_PMAX + 1) * REC_STRIDE)  // records of a slot buffer
-#else
+// Slot buffer layout: per column c, the P records of rec = jb + 1 complex values
+// (candidate row, then its value and row index) followed by the diagonal row, and,
+// after all columns' records, the P headers (value, row) of every column side by
+// side (16 bytes each: one poll instruction of the chain reads P / 8 cache lines).
 #define SLOT_REC_ELEMS ((size_t)LU_NB * (PANEL_PMAX * (LU_NB + 1) + LU_NB))
-#endif
-// BM_HDR_PACKED = 1 keeps the P headers (value, row) of a column side by side after
-// the records (16 bytes each: one poll instruction reads P / 8 cache lines instead of
-// P lines); 0 keeps each header at the front of its record.
-#ifndef BM_HDR_PACKED
-#define BM_HDR_PACKED 1
-#endif
 #define SLOT_HDR ((int)SLOT_REC_ELEMS)  // header of column c, workgroup g: SLOT_HDR + c P + g
 #define SLOT_ELEMS (SLOT_REC_ELEMS + (size_t)LU_NB * PANEL_PMAX)  // complex values per slot buffer
 
@@ -211,12 +196,12 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = (int)blockIdx.x;
   const int rec = jb + 1;
-  const int rstr = BM_REC_SPREAD ? REC_STRIDE : rec;
-  const int cstride = BM_REC_SPREAD ? (P + 1) * REC_STRIDE : P * rec + jb;
+  const int rstr = rec;
+  const int cstride = P * rec + jb;
   const __amdgpu_buffer_rsrc_t rs = rec_rsrc(slots);
   // element of the header of workgroup t for column cc
   auto hdr_el = [&](int cc, int t) __attribute__((always_inline)) {
-    return BM_HDR_PACKED ? SLOT_HDR + cc * P + t : cc * cstride + t * rstr;
+    return SLOT_HDR + cc * P + t;
   };
   const long r0 = (long)j + (long)g * RPW;  // first row of the workgroup
   const int nv = (N - r0 >= RPW) ? RPW : ((N - r0 > 0) ? (int)(N - r0) : 0);
@@ -585,8 +570,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
   }
   // refill the words the next panel uses in the other slot buffer with the empty pattern
   if (next_P > 0) {
-    const int nrec = next_jb + 1, nrstr = BM_REC_SPREAD ? REC_STRIDE : nrec;
-    const int ncstr = BM_REC_SPREAD ? (next_P + 1) * REC_STRIDE : next_P * nrec + next_jb;
+    const int nrec = next_jb + 1, nrstr = nrec;
+    const int ncstr = next_P * nrec + next_jb;
     const int per_col = next_P * nrec + next_jb;
     unsigned long long *ns = (unsigned long long *)next_slots;
     for (int idx = g * SNT + tid; idx < next_jb * per_col; idx += P * SNT) {
@@ -596,8 +581,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       ns[2 * (size_t)el] = SENT;
       ns[2 * (size_t)el + 1] = SENT;
     }
-    if (BM_HDR_PACKED)
-      for (int idx = g * SNT + tid; idx < 2 * next_jb * next_P; idx += P * SNT) ns[2 * (size_t)SLOT_HDR + idx] = SENT;
+    for (int idx = g * SNT + tid; idx < 2 * next_jb * next_P; idx += P * SNT) ns[2 * (size_t)SLOT_HDR + idx] = SENT;
   }
 }
 
@@ -620,9 +604,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 // reads the block's first element) so that no branch separates the loads, and
 // only the stores are predicated.
 // ---------------------------------------------------------------------------
-#ifndef BM_LU_EVENT_FLAGS
 #define BM_LU_EVENT_FLAGS hipEventDisableSystemFence
-#endif
 #define SWAP_COLS 16
 #define ST_CW_NEXT 4  // columns per workgroup, next panel's columns
 #define ST_CW_REST 8  // columns per workgroup, the other columns
@@ -867,10 +849,9 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   }
   if (npanel > 0) {  // the first panel's words of slot buffer 0; each panel refills the next one's
     const int jb0 = (n < LU_NB) ? n : LU_NB;
-    const size_t cstr0 = BM_REC_SPREAD ? (size_t)(shape[1] + 1) * REC_STRIDE : (size_t)shape[1] * (jb0 + 1) + jb0;
+    const size_t cstr0 = (size_t)shape[1] * (jb0 + 1) + jb0;
     if (int rc0 = bm_fill_u64(s, w->slots, 2 * (size_t)jb0 * cstr0, ~0ull)) return rc0;
-    if (BM_HDR_PACKED)
-      if (int rc0 = bm_fill_u64(s, w->slots + SLOT_HDR, 2 * (size_t)jb0 * shape[1], ~0ull)) return rc0;
+    if (int rc0 = bm_fill_u64(s, w->slots + SLOT_HDR, 2 * (size_t)jb0 * shape[1], ~0ull)) return rc0;
   }
   const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
@@ -900,7 +881,9 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     // before it touches the columns of panel k + 1 (which were part of it).
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
-    if (pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+    // (a workspace without the second stream runs every update on s, in order)
+    const bool la = w->aux != nullptr;
+    if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
     auto update = [&](hipStream_t st, int lcols, int c0, int c1, bool next) -> int {
       const int cw = next ? ST_CW_NEXT : ST_CW_REST;
       const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 - c0 + cw - 1) / cw;
@@ -923,15 +906,18 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     };
     int rc = update(s, 0, jn, jn + jbn, true);
     if (rc) return rc;
-    BM_HIP_TRY(hipEventRecord(w->e_next, s));
-    BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
-    rc = update(w->aux, j, jn + jbn, n, false);
+    if (la) {
+      BM_HIP_TRY(hipEventRecord(w->e_next, s));
+      BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+    }
+    rc = update(la ? w->aux : s, j, jn + jbn, n, false);
     if (rc) return rc;
-    BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
+    if (la) BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
   }
-  if (npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+  if (w->aux && npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
   return BM_OK;
 }
+
 
 // ---------------------------------------------------------------------------
 // solve support: inverses of the 64 x 64 diagonal blocks of L (unit lower) and U,

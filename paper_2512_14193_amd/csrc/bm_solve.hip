@@ -63,12 +63,8 @@ int bm_launch_gather(hipStream_t s, int nf, int nrhs, const int32_t *perm, const
 // ---------------------------------------------------------------------------
 #define GV_ROWS 256
 #define GV_KC 32
-#ifndef GV_UN
 #define GV_UN 8
-#endif
-#ifndef GV_WG
 #define GV_WG 768  // enough workgroups (three per CU) to keep HBM busy: 256 reached a third of it
-#endif
 template <int NRM>
 __global__ __launch_bounds__(256) void gemv_partial_kernel(int m, int k, int nr, int kchunk, const cplx *A, long lda,
                                                            const cplx *B, long ldb, cplx *part) {

@@ -33,26 +33,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // complex k per stage: 16 for the deep three-multiplication products (the most
 // that keeps two workgroups per CU in LDS: 65 KB each), 8 for the k = 64 updates
 // of the LU
-#ifndef GM_BK3
 #define GM_BK3 16
-#endif
-#ifndef GM_BK4
 #define GM_BK4 8
-#endif
-#ifndef BM_SHALLOW_GEMM
-#define BM_SHALLOW_GEMM 1
-#endif
-#ifndef GM_3M_MIN_K
 #define GM_3M_MIN_K 256  // Gauss's 3-multiplication form from this depth k on
-#endif
 
 __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-#ifndef GM_OCC
 #define GM_OCC 2  // workgroups per CU the register allocation is bounded for
-#endif
 template <bool BETA0, bool M3>
 __global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
                                                     long lda, const cplx *__restrict__ B, long ldb, cplx beta,
@@ -271,7 +260,7 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
 int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
                     int64_t ldb, cplx beta, cplx *C, int64_t ldc) {
   if (m <= 0 || n <= 0) return BM_OK;
-  if (BM_SHALLOW_GEMM && k <= GS_K && n <= 64) {
+  if (k <= GS_K && n <= 64) {
     const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
     const long tiles = (long)tm * tn;
     if (tiles > 0x7fffffffL) return BM_E_ARG;

@@ -14,7 +14,7 @@
 // of G2_BK complex values, double buffered, with the global loads of the next
 // slice in flight during the MFMAs of the current one.
 //
-// Complex products (G2_3M): Gauss's three-multiplication form,
+// Complex products: Gauss's three-multiplication form,
 //   T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi),
 //   Re = T1 - T2,  Im = T3 - T1 - T2,
 // three real MFMAs per complex multiply-add instead of four (Re += Ar Br - Ai Bi,
@@ -33,17 +33,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 #define G2_BM 128
 #define G2_BN 128
-#ifndef G2_BK
 #define G2_BK 8                       // k-slice of complex values per LDS stage
-#endif
 #define G2_LPT (G2_BK * G2_BM / 256)  // complex values of each operand loaded per thread and stage
-#ifndef G2_3M
-#define G2_3M 1
-#endif
-#ifndef G2_OCC
 #define G2_OCC 2  // workgroups per CU
-#endif
-#define G2_NP (G2_3M ? 3 : 2)  // operand planes of the products: (re, im[, re + im])
+#define G2_NP 3   // operand planes of the products: (re, im, re + im)
 #define G2_LP 2                // planes held in LDS (re, im); the sums come from the fragments
 
 __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
@@ -92,8 +85,7 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
     }
   };
 
-  // 3M: acc[0] = sum Ar Br, acc[1] = sum Ai Bi, acc[2] = sum (Ar + Ai)(Br + Bi)
-  // 4M: acc[0] = Re, acc[1] = Im
+  // acc[0] = sum Ar Br, acc[1] = sum Ai Bi, acc[2] = sum (Ar + Ai)(Br + Bi)
   f32x16 acc[G2_NP][2][2];
 #pragma unroll
   for (int p = 0; p < G2_NP; ++p)
@@ -122,12 +114,11 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
 #pragma unroll
       for (int b = 0; b < 2; ++b) bv[slot][p][b] = Bs[buf][p][k2 + fh][wn * 64 + b * 32 + fi];
     }
-    if (G2_NP == 3) {  // the FP32 sums re + im of the three-multiplication form
+    // the FP32 sums re + im of the three-multiplication form
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[slot][G2_NP - 1][a] = av[slot][0][a] + av[slot][1][a];
+    for (int a = 0; a < 2; ++a) av[slot][2][a] = av[slot][0][a] + av[slot][1][a];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[slot][G2_NP - 1][b] = bv[slot][0][b] + bv[slot][1][b];
-    }
+    for (int b = 0; b < 2; ++b) bv[slot][2][b] = bv[slot][0][b] + bv[slot][1][b];
   };
   for (int it = 0; it < nk; ++it) {
     const int buf = it & 1;
@@ -137,24 +128,12 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
     for (int k2 = 0; k2 < G2_BK; k2 += 2) {
       const int cur = (k2 >> 1) & 1;
       if (k2 + 2 < G2_BK) fload(buf, k2 + 2, cur ^ 1);
-      if (G2_3M) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[p][a][b] = mfma32(bv[cur][p][b], av[cur][p][a], acc[p][a][b]);
-      } else {
+      for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            acc[0][a][b] = mfma32(bv[cur][0][b], av[cur][0][a], acc[0][a][b]);
-            acc[1][a][b] = mfma32(bv[cur][1][b], av[cur][0][a], acc[1][a][b]);
-            acc[0][a][b] = mfma32(bv[cur][1][b], -av[cur][1][a], acc[0][a][b]);
-            acc[1][a][b] = mfma32(bv[cur][0][b], av[cur][1][a], acc[1][a][b]);
-          }
-      }
+          for (int b = 0; b < 2; ++b) acc[p][a][b] = mfma32(bv[cur][p][b], av[cur][p][a], acc[p][a][b]);
     }
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -184,15 +163,8 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
         const int row = row0 + wm * 64 + a * 32 + fi;
         const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
         if (row < m && col < n) {
-          float re, im;
-          if (G2_3M) {
-            const float t1 = acc[0][a][b][r], t2 = acc[1][a][b][r];
-            re = t1 - t2;
-            im = acc[2][a][b][r] - t1 - t2;
-          } else {
-            re = acc[0][a][b][r];
-            im = acc[1][a][b][r];
-          }
+          const float t1 = acc[0][a][b][r], t2 = acc[1][a][b][r];
+          const float re = t1 - t2, im = acc[2][a][b][r] - t1 - t2;
           const cplx v = cmk((double)re, (double)im);
           cplx out = cmul(alpha, v);
           if constexpr (!BETA0) out = cadd(out, cmul(beta, cmk(cin[rr].x, cin[rr].y)));

@@ -52,6 +52,9 @@ CASES = [
     ("disk256", I.disk(256, 1.0), I.Physics.from_wavenumbers(2.0, 3.0)),
     ("star200-complexk", I.star(200), I.Physics.from_wavenumbers(6.0 + 0.4j, 9.0 + 0.6j)),
     ("ellipse130", I.ellipse(130, 2.0, 0.7), I.Physics.from_wavenumbers(3.0, 7.0, beta=0.3 + 0.5j)),
+    # |k1 r| up to about 48 with Im k != 0: the device Hankel's complex asymptotic
+    # branch (|z| >= 25); wavenumbers from the range of the served contour sweep
+    ("star512-complexk-asymptotic", I.star(512), I.Physics.from_wavenumbers(12.4 + 0.35j, 1.5 * (12.4 + 0.35j))),
 ]
 
 

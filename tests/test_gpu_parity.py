@@ -35,6 +35,9 @@ CASES = [
     ("star200-complexk", I.star(200), I.Physics.from_wavenumbers(6.0 + 0.4j, 9.0 + 0.6j)),
     ("ellipse130", I.ellipse(130, 2.0, 0.7), I.Physics.from_wavenumbers(3.0, 7.0, beta=0.3 + 0.5j)),
     ("star96-small-k", I.star(96), I.Physics.from_wavenumbers(0.4, 0.9)),
+    # |k1 r| up to about 48 with Im k != 0: the device Hankel's complex asymptotic
+    # branch (|z| >= 25); wavenumbers from the range of the served contour sweep
+    ("star512-complexk-asymptotic", I.star(512), I.Physics.from_wavenumbers(12.4 + 0.35j, 1.5 * (12.4 + 0.35j))),
 ]
 
 
@@ -100,14 +103,19 @@ def test_zgetrf_vs_numpy(n):
         assert np.all(one(L[k + 1:, k] * U[k, k]) <= one(U[k, k]) * (1 + 1e-13))
 
 
-def test_zgetrf_large():
-    """n = 6244: 98 panels of 128-row workgroups ending on a ragged one, long lookahead
-    updates on the second stream.  The factors solve a system with a known solution
-    (host triangular solves with the returned pivots) and satisfy the partial-pivoting
-    bound."""
+@pytest.mark.parametrize("n", [6244, 8192, 8320])
+def test_zgetrf_large(n):
+    """Large factorisations, each against a known solution (host triangular solves
+    with the returned pivots) and the partial-pivoting bound:
+      n = 6244: 49 panel workgroups of 128 rows, ending on a ragged panel;
+      n = 8192: exactly 64 workgroups for the first panel (the mixed U33 of the
+                N = 8192 workload);
+      n = 8320: 65 workgroups for the first panels, the layout with more than 64
+                panel headers per column (the ordinary comparator at N = 8192
+                starts at 128)."""
     import scipy.linalg as sla
-    n = 6244
-    rng = np.random.default_rng(6244)
+    print(f"[zgetrf_large] n={n}", flush=True)
+    rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
     x = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
     b = A @ x

@@ -112,6 +112,21 @@ def test_served_solutions_vs_oracle():
         assert rel_cols(X.cpu().numpy(), Xo) < 1e-10
 
 
+def test_served_request_in_sweep_range_vs_oracle():
+    """A request of the served sweep's own kind and size: star N = 1024, k0 on a
+    circle |k - 12| = 0.5 (|k1 r| reaches about 49 with Im k != 0: the complex
+    asymptotic branch of the device Hankel functions), 16 probing right-hand sides,
+    through a captured graph, against the oracle's dense solve."""
+    k0 = complex(I.contour_nodes(12.0, 0.5, 32)[3])
+    r = Req(1024, k0, 16, 77)
+    s = B.Server(graph_max_n=1024)
+    (res, X), = serve(s, [r])
+    s.close()
+    assert res["status"] == 0 and res["graph"] == 1
+    Xo = O.zgesv(O.build_mixed(r.bnd, r.ph), r.Bh)
+    assert rel_cols(X.cpu().numpy(), Xo) < 1e-10
+
+
 def test_graph_replays_with_eager_work_between():
     """One handle's captured graph replayed for new wavenumbers, with the
     program's own eager work and synchronisations between the replays: every
