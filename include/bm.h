@@ -241,6 +241,20 @@ int bm_zgemm(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *al
              const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
              void *C, int64_t ldc);
 int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info);
+/* Allocation-free variant of bm_zgetrf, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same factorisation, arguments and result as bm_zgetrf, with two
+ * differences: its scratch memory (panel exchange records, interchange lists,
+ * device flags; about 35 MB) is a device array of the library that every call on
+ * the same device shares, so calls that overlap in time on one device race and must
+ * be serialised by the caller; and the trailing updates run on hip_stream itself
+ * (no second stream).  It calls no allocation routine (no hipMalloc, no stream or
+ * event creation).  info (host) may be NULL: then the call is asynchronous and a
+ * device-side error is not reported; otherwise it synchronises hip_stream.
+ * Errors: BM_E_ARG (n < 0, n > BM_NOALLOC_MAX_N, lda < n, null pointers),
+ * BM_E_HIP, BM_E_DEVICE. */
+#define BM_NOALLOC_MAX_N 16384
+int bm_zgetrf_noalloc(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info);
 /* bm_zgemm_f32: as bm_zgemm, with A and B rounded to complex64 and the products
  * accumulated in FP32 on the matrix cores; C stays complex128. */
 int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha,

@@ -29,7 +29,8 @@ EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
             "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
-            "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature"]
+            "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
+            "bm_zgetrf_noalloc"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -115,6 +116,7 @@ def lib():
         L.bm_phase_times.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
         L.bm_zgemm.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_zgetrf.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
+        L.bm_zgetrf_noalloc.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
         L.bm_zgemm_f32.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_set_precision.argtypes = [vp, i32, ctypes.c_double, i32]
         L.bm_refine_stats.argtypes = [vp, ctypes.POINTER(i32), dp]
@@ -420,3 +422,20 @@ def zgetrf(A, stream=None):
     check(lib().bm_zgetrf(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(piv), ctypes.byref(info)), "bm_zgetrf")
     return piv, info.value
 
+
+BM_NOALLOC_MAX_N = 16384
+
+
+def zgetrf_noalloc(A, ipiv, stream=None, sync=True):
+    """bm_zgetrf_noalloc: in-place LU with the library's static scratch (no device
+    allocation); ipiv: int32 CUDA tensor of n entries supplied by the caller.
+    Returns info when sync, else None (asynchronous)."""
+    stream = stream or torch.cuda.current_stream()
+    n = A.shape[0]
+    if sync:
+        info = ctypes.c_int32(0)
+        check(lib().bm_zgetrf_noalloc(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(ipiv), ctypes.byref(info)),
+              "bm_zgetrf_noalloc")
+        return info.value
+    check(lib().bm_zgetrf_noalloc(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(ipiv), None), "bm_zgetrf_noalloc")
+    return None

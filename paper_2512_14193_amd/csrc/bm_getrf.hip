@@ -25,6 +25,8 @@
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
 // bounded: on expiry the kernel raises the device error flag and runs to completion.
+#include <mutex>
+
 #include "bm_internal.h"
 #include "bm_trinv.h"
 
@@ -918,6 +920,66 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   return BM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free LU (bm_zgetrf_noalloc): the factorisation's scratch memory (the
+// two exchange-slot buffers of the panels, the per-panel interchange lists and the
+// two device flags) lives in one file-scope device array instead of memory the
+// call allocates.  Host code never uses the array's name as a device address: its
+// address on each device comes from hipGetSymbolAddress, taken once per device on
+// the first call there.  All calls on one device share the array, so calls that
+// overlap in time on one device race; each call refills what must start empty.
+// Without the second stream (which would have to be created) every trailing update
+// runs on the caller's stream after the next panel's own update.
+// ---------------------------------------------------------------------------
+#define NA_SLOTS_BYTES (sizeof(cplx) * 2 * SLOT_ELEMS)
+#define NA_SWP_BYTES (sizeof(int32_t) * (size_t)(BM_NOALLOC_MAX_N / LU_NB) * SWP_STRIDE)
+#define NA_SCRATCH_BYTES (NA_SLOTS_BYTES + NA_SWP_BYTES + 256)
+static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+
+#define NA_MAX_DEV 64
+static void *na_ptr[NA_MAX_DEV];
+static std::mutex na_mutex;
+
+static int na_scratch(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= NA_MAX_DEV) return BM_E_HIP;
+  std::lock_guard<std::mutex> lk(na_mutex);
+  if (!na_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BM_E_HIP;
+    na_ptr[dev] = ptr;
+  }
+  *out = (unsigned char *)na_ptr[dev];
+  return BM_OK;
+}
+
+extern "C" int bm_zgetrf_noalloc(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info) {
+  if (n < 0 || n > BM_NOALLOC_MAX_N || lda < n || (n > 0 && (!A || !ipiv))) return BM_E_ARG;
+  if (n == 0) {
+    if (info) *info = 0;
+    return BM_OK;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  int dev = 0;
+  BM_HIP_TRY(hipGetDevice(&dev));
+  unsigned char *sp = nullptr;
+  if (int rc = na_scratch(dev, &sp)) return rc;
+  bm_getrf_ws w;  // host view of the scratch; no stream, no events
+  w.n = BM_NOALLOC_MAX_N;
+  w.npanel = BM_NOALLOC_MAX_N / LU_NB;
+  w.slots = (cplx *)sp;
+  w.swp = (int32_t *)(sp + NA_SLOTS_BYTES);
+  w.zbuf = nullptr;
+  w.aux = nullptr;
+  w.e_next = w.e_rest = nullptr;
+  int32_t *dev_err = (int32_t *)(sp + NA_SLOTS_BYTES + NA_SWP_BYTES);
+  int rc = bm_getrf_run(s, n, (cplx *)A, lda, ipiv, dev_err, &w, 0);
+  if (rc || !info) return rc;
+  int32_t h[2] = {0, 0};
+  BM_HIP_TRY(hipMemcpyAsync(h, dev_err, sizeof(h), hipMemcpyDeviceToHost, s));
+  BM_HIP_TRY(hipStreamSynchronize(s));
+  *info = h[1];
+  return h[0] ? BM_E_DEVICE : BM_OK;
+}
 
 // ---------------------------------------------------------------------------
 // solve support: inverses of the 64 x 64 diagonal blocks of L (unit lower) and U,
