@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_zgemm_star2048_traffic.json")
 ZGEMM_SRC = os.path.join(ROOT, "paper_2512_14193_amd", "csrc", "bm_zgemm.hip")
@@ -82,7 +83,9 @@ def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12):
     P.phase_times()  # reset the per-phase accumulators
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for s in range(steps):
+        if s == steps - 1:
+            P.set_profiling(2)  # the last timed step also times each panel kernel
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -97,45 +100,67 @@ def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12):
         raise RuntimeError(f"{form}: singular factor, info = {info}")
     phases = {name: (ms[i] / cnt[i] if cnt[i] else None)
               for i, name in enumerate(["assemble", "schur_gemm", "lu", "solve", "far_field"])}
+    # per panel launch, over the panels of the last timed step (the latest 64 when
+    # a step has more: the last 64 panels, the shortest, at N = 8192)
+    phases["panel_kernel_avg"] = ms[5] / cnt[5] if cnt[5] else None
     out = {"seconds": t1 - t0, "phase_ms": phases, "X": X.cpu().numpy(), "F": F.cpu().numpy(),
-           "refine_iterations": refine[0], "rel_residual": refine[1]}
+           "refine_iterations": refine[0], "rel_residual": refine[1], "panel_launches_timed": cnt[5]}
     P.close()
     return out
 
 
 def mixed_precision_section(name, steps, warmup, tol):
     """FP64 block LU against the mixed-precision one (FP32 matrix-core Schur
-    complement + FP64 refinement to `tol` relative residual)
-    on the same workload, both end to end; the plain FP64 LU of the ordinary
-    2N x 2N system on the same boundary as the second reference."""
+    complement + FP64 refinement) on the same workload, both end to end, at the
+    refinement target `tol` and at the tests' 1e-12; the plain FP64 LU of the
+    ordinary 2N x 2N system on the same boundary as the second reference."""
     import numpy as np
     from paper_2512_14193_amd import inputs as I
     w = I.workload(name)
     N = w.boundary.n_nodes
     res = {}
-    for prec in ("fp64", "mixed"):
-        r = run_formulation("mixed", w, steps, warmup, precision=prec, tol=tol)
+    for key, prec, t in (("fp64", "fp64", tol), ("mixed", "mixed", tol), ("mixed_tol_1e-12", "mixed", 1e-12)):
+        r = run_formulation("mixed", w, steps, warmup, precision=prec, tol=t)
         ph = r["phase_ms"]
-        res[prec] = {"solves_per_s": steps / r["seconds"], "ms_per_step": 1e3 * r["seconds"] / steps,
-                     "phase_ms": ph,
-                     "schur_tflops": 16.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
-                     "schur_executed_mfma_tflops": 12.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
-                     "refine_iterations": r["refine_iterations"], "rel_residual": r["rel_residual"], "X": r["X"]}
-    Xf, Xm = res["fp64"].pop("X"), res["mixed"].pop("X")
-    diff = float(np.max(np.linalg.norm(Xm - Xf, axis=0) / np.linalg.norm(Xf, axis=0)))
+        res[key] = {"solves_per_s": steps / r["seconds"], "ms_per_step": 1e3 * r["seconds"] / steps,
+                    "phase_ms": ph, "refine_tol": t if prec == "mixed" else None,
+                    "schur_tflops": 16.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
+                    "schur_executed_mfma_tflops": 12.0 * N ** 3 / (ph["schur_gemm"] * 1e-3) / 1e12,
+                    "refine_iterations": r["refine_iterations"], "rel_residual": r["rel_residual"], "X": r["X"]}
+    Xf = res["fp64"]["X"]
+    rel = lambda a, b: float(np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)))  # noqa: E731
+    diffs = {k: rel(res[k].pop("X"), Xf) for k in ("mixed", "mixed_tol_1e-12")}
+    res["fp64"].pop("X")
     o = run_formulation("ordinary", w, steps, warmup)
     ordinary = {"solves_per_s": steps / o["seconds"], "ms_per_step": 1e3 * o["seconds"] / steps,
                 "phase_ms": o["phase_ms"]}
     return {"workload": name, "unknowns": 3 * N, "steps": steps, "refine_tol": tol,
-            "fp64": res["fp64"], "mixed": res["mixed"], "ordinary_fp64": ordinary,
+            "fp64": res["fp64"], "mixed": res["mixed"], "mixed_tol_1e-12": res["mixed_tol_1e-12"],
+            "ordinary_fp64": ordinary,
             "speedup_mixed_over_fp64_block_lu": res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"],
+            "speedup_mixed_tol_1e-12_over_fp64_block_lu":
+                res["mixed_tol_1e-12"]["solves_per_s"] / res["fp64"]["solves_per_s"],
             "speedup_mixed_over_ordinary_fp64_lu": res["mixed"]["solves_per_s"] / ordinary["solves_per_s"],
-            "rel_diff_mixed_vs_fp64": diff}
+            "rel_diff_mixed_vs_fp64": diffs["mixed"], "rel_diff_mixed_tol_1e-12_vs_fp64": diffs["mixed_tol_1e-12"],
+            "rel_diff_uq_ordinary_vs_fp64_mixed_form": rel(o["X"], Xf[:2 * N])}
 
 
-def cpu_baseline(w):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, X_gpu=None, F_gpu=None):
     """The oracle as it stands on the host cores: explicit 3N x 3N matrix, dense
-    partial-pivot LU, 8-RHS solve and far field for the same workload."""
+    partial-pivot LU, 8-RHS solve and far field for the same workload; with the
+    GPU's solution and far field of the same workload, their error against it."""
+    import numpy as np
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     O.lib()  # build/load outside the timed region
@@ -144,11 +169,17 @@ def cpu_baseline(w):
     Bm = O.rhs_plane_wave(w.boundary, w.physics, w.theta_inc)
     X = O.zgesv(A, Bm)
     N = w.boundary.n_nodes
-    O.far_field(w.boundary, w.physics, X[:N], X[N:2 * N], w.theta_obs)
+    F = O.far_field(w.boundary, w.physics, X[:N], X[N:2 * N], w.theta_obs)
     t = time.perf_counter() - t0
-    return {"value": 1.0 / t, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full pass of {w.name} (assembly of the explicit {3 * N}x{3 * N} matrix, "
-                      f"dense LU, {len(w.theta_inc)}-RHS solve, far field) on the host; {t:.1f} s"}
+    out = {"value": 1.0 / t, "unit": "solves/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"one full pass of {w.name} (assembly of the explicit {3 * N}x{3 * N} matrix, "
+                     f"dense LU, {len(w.theta_inc)}-RHS solve, far field) on the host; {t:.1f} s"}
+    rel = lambda a, b: float(np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)))  # noqa: E731
+    if X_gpu is not None:
+        out["gpu_vs_oracle_rel_err_solution"] = rel(X_gpu, X)
+    if F_gpu is not None:
+        out["gpu_vs_oracle_rel_err_far_field"] = rel(F_gpu, F)
+    return out
 
 
 def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
@@ -348,6 +379,34 @@ def main():
     t_factor = (ph["schur_gemm"] + ph["lu"]) * 1e-3
     factor_tflops = (flops_schur + flops_lu) / t_factor / 1e12
     traffic = traffic_record()
+    # The panel factorisation kernel: mean algorithmic flops of the step's panels
+    # (LU of an R x 64 panel: sum_c 8 (R - c - 1)(63 - c) for the rank-1 updates and
+    # 6 (R - c - 1) for the scaling, R = N - 64 i) over its mean launch duration.
+    nb = 64
+    panel_rows = [N - nb * i for i in range((N + nb - 1) // nb)]
+    panel_flops = [sum(8.0 * max(R - c - 1, 0) * max(min(nb, R) - c - 1, 0) + 6.0 * max(R - c - 1, 0)
+                       for c in range(min(nb, R))) for R in panel_rows]
+    timed = panel_flops[-mixed["panel_launches_timed"]:]  # the panels the events covered
+    panel_flops_mean = sum(timed) / len(timed)
+    t_panel = ph["panel_kernel_avg"] * 1e-3
+    panel_step_ms = ph["panel_kernel_avg"] * len(panel_rows)
+    kern = {
+        "panel": {"kernel": "panel_kernel<1> (one 64-column panel of the LU of U33; 64 dependent pivot steps, "
+                            "one cross-workgroup exchange each)",
+                  "bound": "alu", "achieved": panel_flops_mean / t_panel / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                  "unit": "TFLOP/s", "frac": panel_flops_mean / t_panel / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                  "traffic": None, "avg_launch_ms": ph["panel_kernel_avg"], "launches_per_step": len(panel_rows),
+                  "ms_per_step": panel_step_ms, "flops_per_launch_mean": panel_flops_mean,
+                  "launches_timed": mixed["panel_launches_timed"]},
+        "schur_gemm": {"kernel": "zgemm_kernel<true,true> (Schur complement, m=n=N, k=2N; 16 N^3 algorithmic flops)",
+                       "bound": "mfma", "achieved": schur_tflops, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic,
+                       "avg_launch_ms": ph["schur_gemm"], "launches_per_step": 1, "ms_per_step": ph["schur_gemm"]},
+    }
+    dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    roofline = dict(kern[dominant])
+    roofline["dominant_by_time_per_step"] = True
+    roofline["other_kernels"] = {k: v for k, v in kern.items() if k != dominant}
     rec = {
         "metric": "block-LU solves/s (mixed Burton-Miller, assemble + factor + 8-RHS solve + far field)",
         "value": value,
@@ -364,14 +423,12 @@ def main():
         "config": {"workload": w.name, "boundary": w.boundary.name, "n_nodes": N, "unknowns": 3 * N,
                    "k0": w.physics.k0.real, "k1": w.physics.k1.real, "eps1": w.physics.eps1, "nrhs": R,
                    "far_field_angles": len(w.theta_obs), "quadrature": "Kress log-split"},
-        "roofline": {"bound": "mfma",
-                     "kernel": "zgemm_kernel<true,true> (Schur complement, m=n=N, k=2N; 16 N^3 algorithmic flops)",
-                     "achieved": schur_tflops, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic},
+        "roofline": roofline,
         "schur_executed_mfma_tflops": flops_schur_mfma / t_schur / 1e12,
         "phase_ms": ph,
         "factor_tflops": factor_tflops,
         "factor_mfma_frac": factor_tflops / PEAK_FP64_MFMA_TFLOPS,
+        "lu_phase_tflops": flops_lu / (ph["lu"] * 1e-3) / 1e12,
         "rhs_solves_per_s": value * R,
     }
     if not args.no_comparator:
@@ -392,7 +449,7 @@ def main():
     if not args.no_ssm:
         rec["ssm"] = ssm_section(args.ssm_n, args.ssm_per_side)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w)
+        rec["cpu_baseline"] = cpu_baseline(w, mixed["X"], mixed["F"])
     print(json.dumps(rec), flush=True)
 
 

@@ -223,9 +223,11 @@ int bm_sync(bm_problem *p);
 
 /* Per-phase timing with HIP events recorded on the problem's stream around each
  * call of a phase: [0] bm_assemble, [1] Schur-complement GEMM (mixed only),
- * [2] LU factorisation, [3] bm_solve, [4] bm_far_field.  enable != 0 turns the
+ * [2] LU factorisation, [3] bm_solve, [4] bm_far_field, [5] each panel-factorisation
+ * kernel of the LU (only with enable = 2: one pair per panel launch, which adds
+ * about 5 us per panel to the factorisation).  enable != 0 turns the
  * recording on (it does not synchronise).  bm_phase_times synchronises the stream
- * and writes, for each of the first n_phase (<= 5) phases, the summed duration in
+ * and writes, for each of the first n_phase (<= 6) phases, the summed duration in
  * milliseconds (ms, host) and the number of timed calls (count, host) since its
  * previous call, then resets them; at most the latest 64 calls per phase are kept. */
 int bm_set_profiling(bm_problem *p, int32_t enable);

@@ -611,3 +611,40 @@ int orc_far_field(int N, const double *x, const double *dx, const double *prm, i
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Kernels between arbitrary points (the proxy interactions of Sec. 4.2)      */
+/* ------------------------------------------------------------------------- */
+
+/* For each pair s: target x_s with unit normal nu_x, source y_s with unit
+ * normal nu_y and source weight w_s, the four kernels of Sec. 2.2 at
+ * wavenumber k (no quadrature correction: the points are distinct),
+ *   S  = (i/4) H0(kr),            D = (ik/4) H1(kr) nu_y.(x - y)/r,
+ *   D* = (ik/4) H1(kr) nu_x.(y - x)/r,
+ *   N  = (ik/4)[(H1(kr)/r) nu_x.nu_y + (nu_x.d)(nu_y.d)/r^2 (k H0(kr) - 2 H1(kr)/r)],
+ * d = x - y, each times w_s.  out: 4 ns complex values (S, D, D*, N per pair).
+ * Returns -1 if some pair has x = y. */
+int orc_point_kernels(double kr, double ki, int ns, const double *x, const double *nx,
+                      const double *y, const double *ny, const double *w, dcplx *out) {
+  const lcplx k = (long double)kr + I * (long double)ki;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|: bad)
+  for (int s = 0; s < ns; ++s) {
+    const long double d1 = (long double)x[2*s] - y[2*s], d2 = (long double)x[2*s+1] - y[2*s+1];
+    const long double r2 = d1*d1 + d2*d2;
+    if (r2 == 0.0L) { bad = 1; continue; }
+    const long double r = sqrtl(r2);
+    lcplx H0, H1, J0, J1;
+    hankel01_l(k * r, &H0, &H1, &J0, &J1);
+    const long double nxd = nx[2*s] * d1 + nx[2*s+1] * d2;   /* nu_x . d */
+    const long double nyd = ny[2*s] * d1 + ny[2*s+1] * d2;   /* nu_y . d */
+    const long double a = (long double)nx[2*s] * ny[2*s] + (long double)nx[2*s+1] * ny[2*s+1];
+    const long double ws = w[s];
+    const lcplx ik4 = I * k / 4.0L;
+    out[4*s]     = (dcplx)((I / 4.0L) * H0 * ws);
+    out[4*s + 1] = (dcplx)(ik4 * H1 * (nyd / r) * ws);
+    out[4*s + 2] = (dcplx)(ik4 * H1 * (-nxd / r) * ws);
+    out[4*s + 3] = (dcplx)(ik4 * ((H1 / r) * a + (nxd * nyd / r2) * (k * H0 - 2.0L * H1 / r)) * ws);
+  }
+  return bad ? -1 : 0;
+}

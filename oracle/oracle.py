@@ -56,6 +56,8 @@ def lib():
             L.orc_zgetrf.argtypes = [ctypes.c_int, ctypes.c_void_p, _iptr]
             L.orc_zgetrs.argtypes = [ctypes.c_int, ctypes.c_void_p, _iptr, ctypes.c_int, ctypes.c_void_p]
             L.orc_zgesv.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+            L.orc_point_kernels.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _dptr, _dptr, _dptr,
+                                             _dptr, _dptr, ctypes.c_void_p]
             L.orc_far_field.argtypes = [ctypes.c_int, _dptr, _dptr, _dptr, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_int, _dptr, ctypes.c_void_p]
             _lib = L
@@ -212,3 +214,20 @@ def far_field(boundary, physics, U, Q, theta_obs):
                         _d(np.ascontiguousarray(boundary.dx)), _d(prm), U.shape[1], _c(U), _c(Q),
                         theta_obs.shape[0], _d(theta_obs), _c(F))
     return F
+
+
+def point_kernels(k, x, nx, y, ny, w):
+    """S, D, D*, N kernels (Sec. 2.2) for pairs of distinct points: x, nx, y, ny
+    arrays (..., 2) of targets, their unit normals, sources and theirs; w (...)
+    source weights.  Returns four complex arrays of the broadcast shape."""
+    x, nx, y, ny = (np.asarray(a, dtype=np.float64) for a in (x, nx, y, ny))
+    w = np.asarray(w, dtype=np.float64)
+    shape = np.broadcast_shapes(x.shape[:-1], nx.shape[:-1], y.shape[:-1], ny.shape[:-1], w.shape)
+    arrs = [np.ascontiguousarray(np.broadcast_to(a, shape + (2,))) for a in (x, nx, y, ny)]
+    wb = np.ascontiguousarray(np.broadcast_to(w, shape))
+    ns = int(np.prod(shape)) if shape else 1
+    out = np.empty((ns, 4), dtype=np.complex128)
+    k = complex(k)
+    if lib().orc_point_kernels(k.real, k.imag, ns, *[_d(a) for a in arrs], _d(wb), _c(out)):
+        raise ValueError("coincident points")
+    return tuple(out[:, q].reshape(shape) for q in range(4))

@@ -285,15 +285,18 @@ class Problem:
         check(lib().bm_refine_stats(self._h, ctypes.byref(it), ctypes.byref(rr)), "bm_refine_stats")
         return it.value, rr.value
 
-    def set_profiling(self, on: bool = True):
-        check(lib().bm_set_profiling(self._h, 1 if on else 0), "bm_set_profiling")
+    def set_profiling(self, on=True):
+        """bm_set_profiling: True/1 times the phases, 2 also every panel kernel of the LU."""
+        level = 2 if on == 2 else (1 if on else 0)
+        check(lib().bm_set_profiling(self._h, level), "bm_set_profiling")
 
     def phase_times(self):
-        """Summed ms and call counts per phase [assemble, schur, lu, solve, far_field]
-        since the previous call (then reset)."""
-        ms = (ctypes.c_double * 5)()
-        cnt = (ctypes.c_int32 * 5)()
-        check(lib().bm_phase_times(self._h, ms, cnt, 5), "bm_phase_times")
+        """Summed ms and call counts per phase [assemble, schur, lu, solve, far_field,
+        panel kernels] since the previous call (then reset; at most the latest 64
+        calls of a phase are kept)."""
+        ms = (ctypes.c_double * 6)()
+        cnt = (ctypes.c_int32 * 6)()
+        check(lib().bm_phase_times(self._h, ms, cnt, 6), "bm_phase_times")
         return list(ms), list(cnt)
 
 

@@ -145,9 +145,11 @@ void bm_destroy(bm_problem *p) {
   free_problem(p);
 }
 
+}  // extern "C"
+
 // Phase timing: each call of a phase records an event pair in a ring of
 // BM_EV_RING slots; bm_phase_times sums the pairs recorded since its last call.
-static void phase_begin(bm_problem *p, int ph) {
+void bm_phase_begin(bm_problem *p, int ph) {
   if (!p->profiling) return;
   if (!p->ev_created[ph]) {
     for (int e = 0; e < BM_EV_RING; ++e) {
@@ -159,11 +161,16 @@ static void phase_begin(bm_problem *p, int ph) {
   (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][0], p->stream);
 }
 
-static void phase_end(bm_problem *p, int ph) {
+void bm_phase_end(bm_problem *p, int ph) {
   if (!p->profiling || !p->ev_created[ph]) return;
   (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][1], p->stream);
   ++p->ev_count[ph];
 }
+
+static void phase_begin(bm_problem *p, int ph) { bm_phase_begin(p, ph); }
+static void phase_end(bm_problem *p, int ph) { bm_phase_end(p, ph); }
+
+extern "C" {
 
 }  // extern "C"
 
@@ -248,7 +255,9 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   phase_begin(p, BM_PH_LU);
   // (mixed precision: the trailing updates beside the next panel run on the FP32
   // matrix cores; the panels, the next panel's own update and the storage stay FP64)
+  p->gws->prof = (p->profiling >= 2) ? p : nullptr;  // per-panel timing (BM_PH_PANEL)
   rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec == BM_PREC_MIXED);
+  p->gws->prof = nullptr;
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);
@@ -448,7 +457,7 @@ int bm_sync(bm_problem *p) {
 
 int bm_set_profiling(bm_problem *p, int32_t enable) {
   if (!p) return BM_E_ARG;
-  p->profiling = enable ? 1 : 0;
+  p->profiling = (enable >= 2) ? 2 : (enable ? 1 : 0);
   return BM_OK;
 }
 

@@ -199,6 +199,92 @@ __device__ inline void store_entry(const asm_args &A, int blk, int row, int col,
   }
 }
 
+// Geometry of an off-diagonal node pair (i != j) and its quadrature weights.
+struct pair_geo {
+  double si, sj;      // |x'_i|, |x'_j|
+  double r, rinv;
+  double ndi, ndj;    // n_i . d, n_j . d with n = (x2', -x1') (|n| = |x'|), d = x_i - x_j
+  double a, b;        // nu_i . nu_j, (nu_i . d)(nu_j . d) / r^2
+  double R, L;        // log-split weights of m = |i - j|
+  double kap;         // N_0 numerator: T_m + h K0 (N_0,ij = kap / s_i)
+};
+
+__device__ __forceinline__ pair_geo pair_geometry(const asm_args &A, int i, int j) {
+  const int N = A.N;
+  const double2 xi = A.x[i], ai = A.dx[i], xj = A.x[j], aj = A.dx[j];
+  pair_geo g;
+  g.si = sqrt(ai.x * ai.x + ai.y * ai.y);
+  g.sj = sqrt(aj.x * aj.x + aj.y * aj.y);
+  const int m = (i > j) ? i - j : j - i;
+  g.R = A.wts[m];
+  const double T = A.wts[N + m], C = A.wts[3 * N + m];
+  g.L = A.wts[2 * N + m];
+  const double d1 = xi.x - xj.x, d2 = xi.y - xj.y;
+  const double r2 = d1 * d1 + d2 * d2;
+  g.r = sqrt(r2);
+  g.rinv = 1.0 / g.r;
+  g.ndj = aj.y * d1 - aj.x * d2;
+  g.ndi = ai.y * d1 - ai.x * d2;
+  g.a = (ai.y * aj.y + ai.x * aj.x) / (g.si * g.sj);
+  g.b = (g.ndi / g.si) * (g.ndj / g.sj) * g.rinv * g.rinv;
+  // Laplace part: K0 = (1/4pi)[-2 x'_i.x'_j / r^2 + 4 (d.x'_i)(d.x'_j)/r^4 - 1/(2 sin^2)]
+  const double dai = d1 * ai.x + d2 * ai.y, daj = d1 * aj.x + d2 * aj.y;
+  const double aa = ai.x * aj.x + ai.y * aj.y;
+  const double K0 = (-2.0 * aa / r2 + 4.0 * dai * daj / (r2 * r2) - C) / (4.0 * BM_PI);
+  g.kap = T + A.h * K0;
+  return g;
+}
+
+// Diagonal entries (i, i) of the four blocks from the limits of the split kernels:
+// mixed {M13, M23, M31, M32}, ordinary {M31, M32, D_k1 + I/2, -eps1 S_k1}.
+template <int FORM>
+__device__ __forceinline__ void diag_entries(const asm_args &A, int i, cplx (&e)[4]) {
+  const int N = A.N;
+  const double h = A.h;
+  const bm_phys ph = A.ph;
+  const double2 ai = A.dx[i], bi = A.ddx[i], ci = A.d3x[i];
+  const double si = sqrt(ai.x * ai.x + ai.y * ai.y);
+  const double s2 = si * si;
+  const double R0 = A.wts[0], T0 = A.wts[N];
+  const double kap = (ai.y * bi.x - ai.x * bi.y) / (4.0 * BM_PI * s2);  // D_ii / h
+  const double Dd = h * kap;
+  const double pq = ai.x * bi.x + ai.y * bi.y, B = bi.x * bi.x + bi.y * bi.y, q = ai.x * ci.x + ai.y * ci.y;
+  const double K0d = (-(pq * pq) / (s2 * s2) + (0.5 * B + q / 3.0) / s2 - 1.0 / 6.0) / (4.0 * BM_PI);
+  const double N0d = (T0 + h * K0d) / si;
+  cplx S[2], Nd0;
+  for (int w = 0; w < 2; ++w) {
+    const cplx k = w ? ph.k1 : ph.k0;
+    const cplx lk = clog_d(cscale(k, 0.5 * si));
+    // S_ii = R0 (-s/4pi) + h (i/4 - gamma/2pi - ln(k s/2)/2pi) s
+    cplx K2 = cscale(lk, -1.0 / (2.0 * BM_PI));
+    K2.x -= BM_EULER / (2.0 * BM_PI);
+    K2.y += 0.25;
+    S[w] = cscale(cadd(cmk(-R0 / (4.0 * BM_PI), 0.0), cscale(K2, h)), si);
+    if (w == 0) {
+      // (N_k - N_0)_ii = (R0 (-k^2/8pi) + h (i k^2/8 + (1-2gamma) k^2/8pi - (k^2/4pi) ln(k s/2))) s
+      const cplx k2 = cmul(k, k);
+      cplx t = cscale(k2, (1.0 - 2.0 * BM_EULER) / (8.0 * BM_PI));
+      t = cadd(t, cmk(-0.125 * k2.y, 0.125 * k2.x));
+      t = csub(t, cscale(cmul(k2, lk), 1.0 / (4.0 * BM_PI)));
+      Nd0 = cscale(cadd(cscale(k2, -R0 / (8.0 * BM_PI)), cscale(t, h)), si);
+    }
+  }
+  const cplx Nk0 = cadd(cmk(N0d, 0.0), Nd0);
+  const cplx M31 = cadd(cmk(Dd - 0.5, 0.0), cmul(ph.beta, Nk0));
+  const cplx M32 = cscale(cadd(S[0], cmul(ph.beta, cmk(Dd + 0.5, 0.0))), -ph.eps0);
+  if (FORM == BM_MIXED) {
+    e[0] = cneg(S[1]);
+    e[1] = cmk(-(Dd + 0.5) / ph.eps1, 0.0);
+    e[2] = M31;
+    e[3] = M32;
+  } else {
+    e[0] = M31;
+    e[1] = M32;
+    e[2] = cmk(Dd + 0.5, 0.0);
+    e[3] = cscale(S[1], -ph.eps1);
+  }
+}
+
 template <int FORM, bool WIDE>
 __global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
   // unordered tile pair (I, J), I <= J, from the triangular index
@@ -218,30 +304,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
   cplx f[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};  // (j, i) entries
   const bool valid = (i < N) && (j < N);
   if (valid) {
-    const double2 xi = A.x[i], ai = A.dx[i];
-    const double si = sqrt(ai.x * ai.x + ai.y * ai.y);
-    const double h = A.h;
     if (i != j) {
-      const double2 xj = A.x[j], aj = A.dx[j];
-      const double sj = sqrt(aj.x * aj.x + aj.y * aj.y);
-      const int m = (i > j) ? i - j : j - i;
-      const double R = A.wts[m], T = A.wts[N + m], L = A.wts[2 * N + m], C = A.wts[3 * N + m];
-      const double d1 = xi.x - xj.x, d2 = xi.y - xj.y;
-      const double r2 = d1 * d1 + d2 * d2, r = sqrt(r2), rinv = 1.0 / r;
-      // unnormalised normals n = (x2', -x1'), |n| = |x'|
-      const double ndj = aj.y * d1 - aj.x * d2;  // n_j . d
-      const double ndi = ai.y * d1 - ai.x * d2;  // n_i . d
-      const double a = (ai.y * aj.y + ai.x * aj.x) / (si * sj);
-      const double b = (ndi / si) * (ndj / sj) * rinv * rinv;
-      // Laplace part: K0 = (1/4pi)[-2 x'_i.x'_j / r^2 + 4 (d.x'_i)(d.x'_j)/r^4 - 1/(2 sin^2)]
-      const double dai = d1 * ai.x + d2 * ai.y, daj = d1 * aj.x + d2 * aj.y;
-      const double aa = ai.x * aj.x + ai.y * aj.y;
-      const double K0 = (-2.0 * aa / r2 + 4.0 * dai * daj / (r2 * r2) - C) / (4.0 * BM_PI);
-      const double kap = T + h * K0;  // N_0,ij = kap / s_i, N_0,ji = kap / s_j
-
+      const pair_geo g = pair_geometry(A, i, j);
+      const double si = g.si, sj = g.sj, ndi = g.ndi, ndj = g.ndj, kap = g.kap;
       bool bad = false;
-      const pair_k p0 = pair_scalars<WIDE>(ph.k0, r, rinv, R, L, h, a, b, true, &bad);
-      const pair_k p1 = pair_scalars<WIDE>(ph.k1, r, rinv, R, L, h, a, b, false, &bad);
+      const pair_k p0 = pair_scalars<WIDE>(ph.k0, g.r, g.rinv, g.R, g.L, A.h, g.a, g.b, true, &bad);
+      const pair_k p1 = pair_scalars<WIDE>(ph.k1, g.r, g.rinv, g.R, g.L, A.h, g.a, g.b, false, &bad);
       if (WIDE && bad) atomicOr(A.dom_err, 1);
       // k0 operators at (i,j) and (j,i)
       const cplx S0ij = cscale(p0.sig, sj), S0ji = cscale(p0.sig, si);
@@ -270,47 +338,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(asm_args A) {
         f[3] = cscale(p1.sig, -ph.eps1 * si);
       }
     } else {
-      // diagonal limits
-      const double2 bi = A.ddx[i], ci = A.d3x[i];
-      const double s2 = si * si;
-      const double R0 = A.wts[0], T0 = A.wts[N];
-      const double kap = (ai.y * bi.x - ai.x * bi.y) / (4.0 * BM_PI * s2);  // D_ii / h
-      const double Dd = h * kap;
-      const double pq = ai.x * bi.x + ai.y * bi.y, B = bi.x * bi.x + bi.y * bi.y, q = ai.x * ci.x + ai.y * ci.y;
-      const double K0d = (-(pq * pq) / (s2 * s2) + (0.5 * B + q / 3.0) / s2 - 1.0 / 6.0) / (4.0 * BM_PI);
-      const double N0d = (T0 + h * K0d) / si;
-      cplx S[2], Nd0;
-      for (int w = 0; w < 2; ++w) {
-        const cplx k = w ? ph.k1 : ph.k0;
-        const cplx lk = clog_d(cscale(k, 0.5 * si));
-        // S_ii = R0 (-s/4pi) + h (i/4 - gamma/2pi - ln(k s/2)/2pi) s
-        cplx K2 = cscale(lk, -1.0 / (2.0 * BM_PI));
-        K2.x -= BM_EULER / (2.0 * BM_PI);
-        K2.y += 0.25;
-        S[w] = cscale(cadd(cmk(-R0 / (4.0 * BM_PI), 0.0), cscale(K2, h)), si);
-        if (w == 0) {
-          // (N_k - N_0)_ii = (R0 (-k^2/8pi) + h (i k^2/8 + (1-2gamma) k^2/8pi - (k^2/4pi) ln(k s/2))) s
-          const cplx k2 = cmul(k, k);
-          cplx t = cscale(k2, (1.0 - 2.0 * BM_EULER) / (8.0 * BM_PI));
-          t = cadd(t, cmk(-0.125 * k2.y, 0.125 * k2.x));
-          t = csub(t, cscale(cmul(k2, lk), 1.0 / (4.0 * BM_PI)));
-          Nd0 = cscale(cadd(cscale(k2, -R0 / (8.0 * BM_PI)), cscale(t, h)), si);
-        }
-      }
-      const cplx Nk0 = cadd(cmk(N0d, 0.0), Nd0);
-      const cplx M31 = cadd(cmk(Dd - 0.5, 0.0), cmul(ph.beta, Nk0));
-      const cplx M32 = cscale(cadd(S[0], cmul(ph.beta, cmk(Dd + 0.5, 0.0))), -ph.eps0);
-      if (FORM == BM_MIXED) {
-        e[0] = cneg(S[1]);
-        e[1] = cmk(-(Dd + 0.5) / ph.eps1, 0.0);
-        e[2] = M31;
-        e[3] = M32;
-      } else {
-        e[0] = M31;
-        e[1] = M32;
-        e[2] = cmk(Dd + 0.5, 0.0);
-        e[3] = cscale(S[1], -ph.eps1);
-      }
+      diag_entries<FORM>(A, i, e);
     }
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk) store_entry<FORM>(A, blk, i, j, e[blk]);
@@ -477,5 +505,173 @@ int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int
                        (long)ldx, theta, F + (long)r0 * ldf, (long)ldf);
     BM_HIP_TRY(hipGetLastError());
   }
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Entries for index lists and proxy interactions (the fast direct solver of
+// Sec. 4.2).  An index code is (type << 20) | node, type 0 = u, 1 = q, 2 = phi.
+//
+// mixed_entry: one entry of the explicit 3N x 3N matrix of eq. (dis_mixedBM),
+// identity and zero blocks included, from the same pair formulas and diagonal
+// limits as the assembly (sector wavenumbers).
+// ---------------------------------------------------------------------------
+__device__ cplx mixed_entry(const asm_args &A, int tr, int i, int tc, int j) {
+  const bm_phys ph = A.ph;
+  int blk = -1;  // M13, M23, M31, M32
+  if (tr == 0 && tc == 2) blk = 0;
+  else if (tr == 1 && tc == 2) blk = 1;
+  else if (tr == 2 && tc == 0) blk = 2;
+  else if (tr == 2 && tc == 1) blk = 3;
+  if (blk < 0) return cmk((tr == tc && tr < 2 && i == j) ? 1.0 : 0.0, 0.0);
+  if (i == j) {
+    cplx e[4];
+    diag_entries<BM_MIXED>(A, i, e);
+    return e[blk];
+  }
+  const pair_geo g = pair_geometry(A, i, j);
+  bool bad = false;
+  if (blk < 2) {
+    const pair_k p1 = pair_scalars<false>(ph.k1, g.r, g.rinv, g.R, g.L, A.h, g.a, g.b, false, &bad);
+    return blk == 0 ? cscale(p1.sig, -g.sj) : cscale(p1.del, g.ndi * g.sj / (g.si * ph.eps1));
+  }
+  const pair_k p0 = pair_scalars<false>(ph.k0, g.r, g.rinv, g.R, g.L, A.h, g.a, g.b, blk == 2, &bad);
+  if (blk == 2) {
+    const cplx N0 = cadd(cmk(g.kap / g.si, 0.0), cscale(p0.nu, g.sj));
+    return cadd(cscale(p0.del, g.ndj), cmul(ph.beta, N0));
+  }
+  const cplx Ds0 = cscale(p0.del, -g.ndi * g.sj / g.si);
+  return cscale(cadd(cscale(p0.sig, g.sj), cmul(ph.beta, Ds0)), -ph.eps0);
+}
+
+// The four kernels between two distinct points (no quadrature correction):
+//   S = (i/4) H0(kr), D = (ik/4) H1(kr) ny.(x - y)/r, D* = (ik/4) H1(kr) nx.(y - x)/r,
+//   N = (ik/4)[(H1(kr)/r) nx.ny + (nx.d)(ny.d)/r^2 (k H0(kr) - 2 H1(kr)/r)], d = x - y.
+struct pt_k {
+  cplx S, D, Ds, N;
+};
+__device__ inline pt_k point_kernels(cplx k, double2 x, double2 nx, double2 y, double2 ny) {
+  const double d1 = x.x - y.x, d2 = x.y - y.y;
+  const double r2 = d1 * d1 + d2 * d2, r = sqrt(r2), rinv = 1.0 / r;
+  const bm_hk4 hk = bm_hankel01(cscale(k, r));
+  const double nxd = nx.x * d1 + nx.y * d2, nyd = ny.x * d1 + ny.y * d2, a = nx.x * ny.x + nx.y * ny.y;
+  const cplx ik4 = cmk(-0.25 * k.y, 0.25 * k.x);
+  pt_k o;
+  o.S = cmk(-0.25 * hk.h0.y, 0.25 * hk.h0.x);
+  o.D = cscale(cmul(ik4, hk.h1), nyd * rinv);
+  o.Ds = cscale(cmul(ik4, hk.h1), -nxd * rinv);
+  const cplx hh = cadd(cscale(hk.h1, rinv * a),
+                       cscale(csub(cmul(k, hk.h0), cscale(hk.h1, 2.0 * rinv)), nxd * nyd * rinv * rinv));
+  o.N = cmul(ik4, hh);
+  return o;
+}
+
+__device__ inline double2 node_normal(const asm_args &A, int i, double *s) {
+  const double2 a = A.dx[i];
+  *s = sqrt(a.x * a.x + a.y * a.y);
+  return make_double2(a.y / *s, -a.x / *s);
+}
+
+// One batch item: an M x C column-major output at out + off (leading dimension ld).
+//   mode 0: A[rows, cols] for the code lists rl (M) and cl (C);
+//   mode 1: target of a column skeleton of type ctype (Table tb:low-rank, R rows):
+//           rows 0..np-1 the proxy points as targets with the kernel combination of
+//           that type, rows np.. the near rows rl[r - np] (matrix entries); columns
+//           the candidate codes cl; every source carries its trapezoid weight;
+//   mode 2: conjugate transpose of the target of a row skeleton of type ctype
+//           (Table tb:low-rank, L rows): rows are the sources, first the proxy points
+//           (np of them, 2 np for type 2: first D0 + beta N0, then S0 + beta D*0) with
+//           weight pw, then the near columns rl[r - nps]; columns the candidate rows cl.
+struct fds_tgt {
+  int M, C, ld, mode, ctype, np;
+  long off;
+  double cx, cy, rho, pw;
+  const int *rl, *cl;
+};
+
+#define FDS_CODE_NODE(c) ((c) & 0xFFFFF)
+#define FDS_CODE_TYPE(c) ((c) >> 20)
+
+__global__ __launch_bounds__(256) void fds_target_kernel(asm_args A, const fds_tgt *items, cplx *out) {
+  const fds_tgt it = items[blockIdx.y];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)it.M * it.C) return;
+  const int r = (int)(e % it.M), c = (int)(e / it.M);
+  const bm_phys ph = A.ph;
+  const int cc = it.cl[c], ct = FDS_CODE_TYPE(cc), cn = FDS_CODE_NODE(cc);
+  cplx v;
+  if (it.mode == 0) {
+    const int rc = it.rl[r];
+    v = mixed_entry(A, FDS_CODE_TYPE(rc), FDS_CODE_NODE(rc), ct, cn);
+  } else if (it.mode == 1) {
+    if (r < it.np) {
+      double sn, sp;
+      sincospi(2.0 * r / it.np, &sp, &sn);  // (sin, cos) of the proxy angle
+      const double2 nx = make_double2(sn, sp);
+      const double2 x = make_double2(it.cx + it.rho * sn, it.cy + it.rho * sp);
+      double sj;
+      const double2 ny = node_normal(A, cn, &sj);
+      const double w = A.h * sj;
+      if (ct == 0) {
+        const pt_k k = point_kernels(ph.k0, x, nx, A.x[cn], ny);
+        v = cscale(cadd(k.D, cmul(ph.beta, k.N)), w);
+      } else if (ct == 1) {
+        const pt_k k = point_kernels(ph.k0, x, nx, A.x[cn], ny);
+        v = cscale(cadd(k.S, cmul(ph.beta, k.Ds)), w);
+      } else {
+        v = cscale(point_kernels(ph.k1, x, nx, A.x[cn], ny).S, w);
+      }
+    } else {
+      const int rc = it.rl[r - it.np];
+      v = mixed_entry(A, FDS_CODE_TYPE(rc), FDS_CODE_NODE(rc), ct, cn);
+    }
+  } else {
+    const int nps = (ct == 2) ? 2 * it.np : it.np;
+    if (r < nps) {
+      const int q = r % it.np;
+      double sn, sp;
+      sincospi(2.0 * q / it.np, &sp, &sn);
+      const double2 ny = make_double2(sn, sp);
+      const double2 y = make_double2(it.cx + it.rho * sn, it.cy + it.rho * sp);
+      double si;
+      const double2 nx = node_normal(A, cn, &si);
+      const double2 x = A.x[cn];
+      if (ct == 0) {
+        v = point_kernels(ph.k1, x, nx, y, ny).S;
+      } else if (ct == 1) {
+        v = point_kernels(ph.k1, x, nx, y, ny).Ds;
+      } else {
+        const pt_k k = point_kernels(ph.k0, x, nx, y, ny);
+        v = (r < it.np) ? cadd(k.D, cmul(ph.beta, k.N)) : cadd(k.S, cmul(ph.beta, k.Ds));
+      }
+      v = cscale(v, it.pw);
+    } else {
+      const int rc = it.rl[r - nps];
+      v = mixed_entry(A, ct, cn, FDS_CODE_TYPE(rc), FDS_CODE_NODE(rc));
+    }
+    v = cconj(v);
+  }
+  out[it.off + r + (long)c * it.ld] = v;
+}
+
+int bm_launch_fds_targets(hipStream_t s, const bm_problem *p, int nitems, const void *items_dev, long max_elems,
+                          cplx *out) {
+  if (nitems <= 0 || max_elems <= 0) return BM_OK;
+  asm_args A;
+  A.N = p->n;
+  A.h = BM_PI / (p->n / 2);
+  A.ph = p->phys;
+  A.x = (const double2 *)p->geo;
+  A.dx = (const double2 *)(p->geo + 2 * p->n);
+  A.ddx = (const double2 *)(p->geo + 4 * p->n);
+  A.d3x = (const double2 *)(p->geo + 6 * p->n);
+  A.wts = p->wts;
+  A.top = A.bot = A.ord = nullptr;
+  A.dom_err = nullptr;
+  const long nb = (max_elems + 255) / 256;
+  if (nb > 0x7fffffffL || nitems > 65535) return BM_E_ARG;
+  hipLaunchKernelGGL(fds_target_kernel, dim3((unsigned)nb, nitems), dim3(256), 0, s, A, (const fds_tgt *)items_dev,
+                     out);
+  BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

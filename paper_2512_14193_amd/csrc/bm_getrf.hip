@@ -876,7 +876,9 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     // kernel is bounded, so a launch whose workgroups cannot all become resident
     // ends with BM_E_DEVICE, not a hang.
     const int rpl = shape[3 * pi];
+    if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
     BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
+    if (w->prof) bm_phase_end(w->prof, BM_PH_PANEL);
     // Lookahead: the stream s applies the panel's interchanges and its update to the
     // next panel's columns only; the auxiliary stream applies them to every other
     // column while s factors the next panel.  s waits for that rest of panel k - 1

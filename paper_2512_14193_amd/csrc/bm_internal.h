@@ -75,6 +75,7 @@ struct bm_getrf_ws {
   cplx *zbuf;          // triangular solves: [ticket counters][lower solve's blocks][upper solve's blocks]
   hipStream_t aux;     // second stream: the trailing update of panel k runs beside panel k + 1
   hipEvent_t e_next, e_rest;
+  struct bm_problem *prof;  // non-null: time each panel launch in that problem's BM_PH_PANEL phase
 };
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {
@@ -160,7 +161,7 @@ struct bm_phys {
 
 enum { BM_ST_CREATED = 0, BM_ST_ASSEMBLED = 1, BM_ST_FACTORED = 2 };
 #define BM_EV_RING 64
-enum { BM_PH_ASSEMBLE = 0, BM_PH_SCHUR = 1, BM_PH_LU = 2, BM_PH_SOLVE = 3, BM_PH_FAR = 4, BM_NPHASE = 5 };
+enum { BM_PH_ASSEMBLE = 0, BM_PH_SCHUR = 1, BM_PH_LU = 2, BM_PH_SOLVE = 3, BM_PH_FAR = 4, BM_PH_PANEL = 5, BM_NPHASE = 6 };
 
 
 struct bm_problem {
@@ -222,6 +223,9 @@ bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);
 size_t bm_getrf_ws_bytes(int n);  // device bytes bm_getrf_ws_create(n) allocates
 int bm_getrf_prepare();           // kernel attributes on the current device (outside any capture)
+// phase timing (bm_set_profiling): an event pair around the work enqueued between the calls
+void bm_phase_begin(struct bm_problem *p, int ph);
+void bm_phase_end(struct bm_problem *p, int ph);
 // parameter checks of bm_assemble (BM_OK or BM_E_ARG)
 int bm_check_params(const bm_params *prm);
 // Fill n 8-byte words at p with v on stream s (a kernel, so that the sequence stays
