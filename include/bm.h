@@ -395,6 +395,63 @@ void bm_server_destroy(bm_server *s);
 int bm_block_moments(void *hip_stream, int32_t rows, int32_t L, const void *U, int64_t ldu,
                      const void *X, int64_t ldx, int32_t nmom, const double *coef, void *S);
 
+/* ---------------------------------------------------------------------------
+ * Proxy-compressed fast direct solver (Sec. 4.2) for boundaries too large for the
+ * dense factorisation (N = 65536: the four blocks alone would need 275 GB).
+ *
+ * Binary tree of leaf cells of `leaf` consecutive nodes (N / leaf a power of two);
+ * weak admissibility: every off-diagonal block A_ij of eq. (block_Aij) is factored
+ * as L_i S_ij R_j (eq. aij=usv) with block-diagonal L_i, R_j (one block per unknown
+ * type u, q, phi) and S_ij the original entries between the skeletons.  Skeletons
+ * and interpolation matrices come from column-pivoted QR of the proxy targets of
+ * Table (tb:low-rank): a circle around the cell of 1.5 times its diameter (centred
+ * on the cell's bounding box, radius 0.75 times its diagonal) with
+ * max(n_proxy, 2 |k|max rho + 64) equispaced points (rounded up to a multiple of 8),
+ * plus the points of other cells inside the circle with their real entries; rank =
+ * pivots with |R_jj| > tol |R_00|, the same count for rows and columns per type
+ * (the larger).  The compressed system eq. (compressed), with diagonal blocks
+ * (R_i A_ii^{-1} L_i)^{-1}, is compressed again level by level (recursive
+ * skeletonisation) up to a dense root.  Leaf blocks use Theorem (thm:LU)
+ * (U33 = -[M31 M32][M13; M23]), A_ii^{-1} L_i Corollary (lem:block_LU) and
+ * A_ii^{-1} f_i Corollary (lem:for_ssm_RHS).  Quadrature: the one-point
+ * zeta-corrected trapezoid rule (BM_QUAD_ZETA1), whose entries between distinct
+ * nodes are point interactions.  Wavenumbers in the sector |Im k| <= Re k / 2.
+ * Accuracy: the solution differs from the dense solution of the same system by
+ * about tol times the conditioning of the compressed blocks. */
+typedef struct bm_fds bm_fds;
+
+typedef struct {
+  int32_t leaf;      /* leaf cell size, 16..320 (default 256)                      */
+  int32_t n_proxy;   /* proxy points per circle at least, >= 8 (default 128)       */
+  double tol;        /* rank tolerance of the column-pivoted QR, (0, 1) (1e-10)    */
+} bm_fds_config;
+
+/* Create a solver for N nodes (N <= 65536, N / leaf a power of two >= 2), cfg NULL
+ * for the defaults, every call ordered on hip_stream.  Errors: BM_E_ARG, BM_E_NOMEM,
+ * BM_E_HIP. */
+int bm_fds_create(int32_t n, const bm_fds_config *cfg, void *hip_stream, bm_fds **out);
+/* Compress and factor the mixed system for this geometry and these parameters (as
+ * bm_assemble).  Synchronous (the tree's index lists live on the host).  Errors:
+ * BM_E_ARG (as bm_assemble, a wavenumber below the sector, a proxy target of more
+ * than 8192 rows), BM_E_NOMEM, BM_E_HIP, BM_E_DEVICE (an exactly singular block). */
+int bm_fds_factor(bm_fds *f, const bm_geometry *geometry, const bm_params *params);
+/* X = A^{-1} B for nrhs right-hand sides (3N x nrhs, column-major, ld >= 3N, X not
+ * aliasing B), through the compressed factorisation.  Synchronous.
+ * Errors: BM_E_STATE before bm_fds_factor, BM_E_ARG. */
+int bm_fds_solve(bm_fds *f, int32_t nrhs, const void *B, int64_t ldb, void *X, int64_t ldx);
+/* Plane-wave right-hand sides and far field, as bm_rhs_plane_wave and bm_far_field. */
+int bm_fds_rhs_plane_wave(bm_fds *f, int32_t nrhs, const double *theta_inc, void *B, int64_t ldb);
+int bm_fds_far_field(bm_fds *f, int32_t nrhs, const void *X, int64_t ldx, int32_t nang, const double *theta,
+                     void *F, int64_t ldf);
+/* Host outputs: the number of levels L; for every level l = 0..L (l = L the leaves)
+ * the sum and the largest number of skeletons of its cells (skel_sum, skel_max: host
+ * arrays of at least L + 1 entries; level 0 holds 0); the order of the dense root
+ * system; the device bytes held.  Errors: BM_E_STATE before bm_fds_factor. */
+int bm_fds_info(bm_fds *f, int32_t *levels, int32_t *skel_sum, int32_t *skel_max, int32_t *root_n,
+                int64_t *bytes);
+/* Release the solver and its device memory (after synchronising its stream). */
+void bm_fds_destroy(bm_fds *f);
+
 /* Text for a status code. */
 const char *bm_strerror(int code);
 

@@ -30,7 +30,8 @@ EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
             "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
             "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
-            "bm_zgetrf_noalloc"]
+            "bm_zgetrf_noalloc", "bm_fds_create", "bm_fds_factor", "bm_fds_solve", "bm_fds_rhs_plane_wave",
+            "bm_fds_far_field", "bm_fds_info", "bm_fds_destroy"]
 
 
 class BMGeometry(ctypes.Structure):
@@ -60,6 +61,10 @@ class BMRequestResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reused_factors", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
+class BMFdsConfig(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class BMServerCounters(ctypes.Structure):
@@ -117,6 +122,15 @@ def lib():
         L.bm_zgemm.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_zgetrf.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
         L.bm_zgetrf_noalloc.argtypes = [vp, i32, vp, i64, vp, ctypes.POINTER(i32)]
+        L.bm_fds_create.argtypes = [i32, ctypes.POINTER(BMFdsConfig), vp, ctypes.POINTER(vp)]
+        L.bm_fds_factor.argtypes = [vp, ctypes.POINTER(BMGeometry), ctypes.POINTER(BMParams)]
+        L.bm_fds_solve.argtypes = [vp, i32, vp, i64, vp, i64]
+        L.bm_fds_rhs_plane_wave.argtypes = [vp, i32, vp, vp, i64]
+        L.bm_fds_far_field.argtypes = [vp, i32, vp, i64, i32, vp, vp, i64]
+        L.bm_fds_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.bm_fds_destroy.argtypes = [vp]
+        L.bm_fds_destroy.restype = None
         L.bm_zgemm_f32.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
         L.bm_set_precision.argtypes = [vp, i32, ctypes.c_double, i32]
         L.bm_refine_stats.argtypes = [vp, ctypes.POINTER(i32), dp]
@@ -442,3 +456,74 @@ def zgetrf_noalloc(A, ipiv, stream=None, sync=True):
         return info.value
     check(lib().bm_zgetrf_noalloc(_stream_handle(stream), n, _ptr(A), _ld(A), _ptr(ipiv), None), "bm_zgetrf_noalloc")
     return None
+
+
+class FDS:
+    """Proxy-compressed fast direct solver of the mixed system (bm_fds_*)."""
+
+    def __init__(self, n_nodes: int, leaf: int = 256, n_proxy: int = 128, tol: float = 1e-10,
+                 stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs on the GPU only")
+        self.n = int(n_nodes)
+        self.rows = 3 * self.n
+        self.stream = stream or torch.cuda.current_stream()
+        cfg = BMFdsConfig(int(leaf), int(n_proxy), float(tol))
+        h = ctypes.c_void_p()
+        check(lib().bm_fds_create(self.n, ctypes.byref(cfg), _stream_handle(self.stream), ctypes.byref(h)),
+              "bm_fds_create")
+        self._h = h
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bm_fds_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self, geometry, physics):
+        """bm_fds_factor; geometry: four contiguous (N, 2) float64 CUDA tensors."""
+        for t in geometry:
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == (self.n, 2)):
+                raise ValueError("geometry must be contiguous (N, 2) float64 CUDA tensors")
+        g = BMGeometry(*[t.data_ptr() for t in geometry])
+        check(lib().bm_fds_factor(self._h, ctypes.byref(g), ctypes.byref(_params(physics))), "bm_fds_factor")
+
+    def solve(self, B: torch.Tensor, X: torch.Tensor | None = None) -> torch.Tensor:
+        if X is None:
+            X = fortran_empty(B.shape[0], B.shape[1])
+        check(lib().bm_fds_solve(self._h, B.shape[1], _ptr(B), _ld(B), _ptr(X), _ld(X)), "bm_fds_solve")
+        return X
+
+    def rhs_plane_wave(self, theta: torch.Tensor, B: torch.Tensor | None = None) -> torch.Tensor:
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        if B is None:
+            B = fortran_empty(self.rows, theta.shape[0])
+        check(lib().bm_fds_rhs_plane_wave(self._h, theta.shape[0], _ptr(theta), _ptr(B), _ld(B)),
+              "bm_fds_rhs_plane_wave")
+        return B
+
+    def far_field(self, X: torch.Tensor, theta: torch.Tensor, F: torch.Tensor | None = None) -> torch.Tensor:
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        if F is None:
+            F = fortran_empty(theta.shape[0], X.shape[1])
+        check(lib().bm_fds_far_field(self._h, X.shape[1], _ptr(X), _ld(X), theta.shape[0], _ptr(theta), _ptr(F),
+                                     _ld(F)), "bm_fds_far_field")
+        return F
+
+    def info(self) -> dict:
+        lev = ctypes.c_int32(0)
+        ssum = (ctypes.c_int32 * 32)()
+        smax = (ctypes.c_int32 * 32)()
+        rn = ctypes.c_int32(0)
+        by = ctypes.c_int64(0)
+        check(lib().bm_fds_info(self._h, ctypes.byref(lev), ssum, smax, ctypes.byref(rn), ctypes.byref(by)),
+              "bm_fds_info")
+        L = lev.value
+        return {"levels": L, "skeletons_sum": list(ssum[:L + 1]), "skeletons_max": list(smax[:L + 1]),
+                "root_n": rn.value, "device_bytes": by.value}

@@ -572,26 +572,6 @@ __device__ inline double2 node_normal(const asm_args &A, int i, double *s) {
   return make_double2(a.y / *s, -a.x / *s);
 }
 
-// One batch item: an M x C column-major output at out + off (leading dimension ld).
-//   mode 0: A[rows, cols] for the code lists rl (M) and cl (C);
-//   mode 1: target of a column skeleton of type ctype (Table tb:low-rank, R rows):
-//           rows 0..np-1 the proxy points as targets with the kernel combination of
-//           that type, rows np.. the near rows rl[r - np] (matrix entries); columns
-//           the candidate codes cl; every source carries its trapezoid weight;
-//   mode 2: conjugate transpose of the target of a row skeleton of type ctype
-//           (Table tb:low-rank, L rows): rows are the sources, first the proxy points
-//           (np of them, 2 np for type 2: first D0 + beta N0, then S0 + beta D*0) with
-//           weight pw, then the near columns rl[r - nps]; columns the candidate rows cl.
-struct fds_tgt {
-  int M, C, ld, mode, ctype, np;
-  long off;
-  double cx, cy, rho, pw;
-  const int *rl, *cl;
-};
-
-#define FDS_CODE_NODE(c) ((c) & 0xFFFFF)
-#define FDS_CODE_TYPE(c) ((c) >> 20)
-
 __global__ __launch_bounds__(256) void fds_target_kernel(asm_args A, const fds_tgt *items, cplx *out) {
   const fds_tgt it = items[blockIdx.y];
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

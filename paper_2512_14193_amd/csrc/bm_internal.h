@@ -218,6 +218,46 @@ int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *
 int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
                       const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
 
+// Batched complex GEMM C = alpha A B + beta C, one descriptor per product
+struct bm_gemm_desc {
+  int m, n, k;
+  cplx alpha, beta;
+  const cplx *A;
+  long lda;
+  const cplx *B;
+  long ldb;
+  cplx *C;
+  long ldc;
+};
+// max_tiles: the largest ceil(m / 64) * ceil(n / 64) over the descriptors
+int bm_launch_zgemm_batched(hipStream_t s, int count, const bm_gemm_desc *d_dev, int max_tiles);
+
+// One batch item: an M x C column-major output at out + off (leading dimension ld).
+//   mode 0: A[rows, cols] for the code lists rl (M) and cl (C);
+//   mode 1: target of a column skeleton of type ctype (Table tb:low-rank, R rows):
+//           rows 0..np-1 the proxy points as targets with the kernel combination of
+//           that type, rows np.. the near rows rl[r - np] (matrix entries); columns
+//           the candidate codes cl; every source carries its trapezoid weight;
+//   mode 2: conjugate transpose of the target of a row skeleton of type ctype
+//           (Table tb:low-rank, L rows): rows are the sources, first the proxy points
+//           (np of them, 2 np for type 2: first D0 + beta N0, then S0 + beta D*0) with
+//           weight pw, then the near columns rl[r - nps]; columns the candidate rows cl.
+struct fds_tgt {
+  int M, C, ld, mode, ctype, np;
+  long off;
+  double cx, cy, rho, pw;
+  const int *rl, *cl;
+};
+
+
+// index code of the fast direct solver: (type << 20) | node, type 0 = u, 1 = q, 2 = phi
+#define FDS_CODE(t, v) (((t) << 20) | (v))
+#define FDS_CODE_NODE(c) ((c) & 0xFFFFF)
+#define FDS_CODE_TYPE(c) ((c) >> 20)
+// the items (device array) into out; max_elems: the largest M * C
+int bm_launch_fds_targets(hipStream_t s, const bm_problem *p, int nitems, const void *items_dev, long max_elems,
+                          cplx *out);
+
 // LU
 bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);

@@ -29,9 +29,13 @@ __global__ __launch_bounds__(1024) void perm_kernel(int nf, int npanel, const in
 }
 
 int bm_launch_perm(hipStream_t s, bm_getrf_ws *w, int nf, int32_t *perm) {
+  // the panels of this factorisation of order nf (a workspace sized for a larger
+  // order holds no interchange lists for the panels beyond them)
+  const int npanel = (nf + LU_NB - 1) / LU_NB;
+  if (nf > w->n || npanel > w->npanel) return BM_E_ARG;
   const int use_lds = (nf <= 32768) ? 1 : 0;
   const size_t lds = use_lds ? sizeof(int32_t) * (size_t)nf : 0;
-  hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(1024), lds, s, nf, w->npanel, (const int32_t *)w->swp, perm, use_lds);
+  hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(1024), lds, s, nf, npanel, (const int32_t *)w->swp, perm, use_lds);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

@@ -42,10 +42,12 @@ __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
 }
 
 #define GM_OCC 2  // workgroups per CU the register allocation is bounded for
+// One 64 x 64 output tile (index `tile`, tiles_m tiles down the rows) of
+// C = alpha A B + beta C; the body of the plain and the batched kernels.
 template <bool BETA0, bool M3>
-__global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
-                                                    long lda, const cplx *__restrict__ B, long ldb, cplx beta,
-                                                    cplx *__restrict__ C, long ldc, int tiles_m) {
+__device__ __forceinline__ void zgemm_tile(int tile, int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
+                                           long lda, const cplx *__restrict__ B, long ldb, cplx beta,
+                                           cplx *__restrict__ C, long ldc, int tiles_m) {
   constexpr int GM_BK = M3 ? GM_BK3 : GM_BK4;
   constexpr int GM_LPT = GM_BK * GM_BM / 256;  // complex values of each operand loaded per thread and stage
   __shared__ cplx As[2][GM_BK][GM_BM];
@@ -54,7 +56,6 @@ __global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k,
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int tile = blockIdx.x;
   const int row0 = (tile % tiles_m) * GM_BM, col0 = (tile / tiles_m) * GM_BN;
 
   // global -> LDS assignment (GM_LPT complex values per thread and operand)
@@ -193,6 +194,36 @@ if constexpr (M3) {
       }
 }
 
+template <bool BETA0, bool M3>
+__global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
+                                                    long lda, const cplx *__restrict__ B, long ldb, cplx beta,
+                                                    cplx *__restrict__ C, long ldc, int tiles_m) {
+  zgemm_tile<BETA0, M3>(blockIdx.x, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
+}
+
+// Batched products: descriptor blockIdx.y, its tiles on blockIdx.x (a launch covers
+// the largest product; workgroups beyond a smaller product's tiles return).
+__global__ __launch_bounds__(256, GM_OCC) void zgemm_batched_kernel(const bm_gemm_desc *d) {
+  const bm_gemm_desc g = d[blockIdx.y];
+  if (g.m <= 0 || g.n <= 0) return;
+  const int tm = (g.m + GM_BM - 1) / GM_BM, tn = (g.n + GM_BN - 1) / GM_BN;
+  if ((int)blockIdx.x >= tm * tn) return;
+  // beta = 0: C is not read (it may hold anything, NaN included)
+  if (g.beta.x == 0.0 && g.beta.y == 0.0)
+    zgemm_tile<true, false>(blockIdx.x, g.m, g.n, g.k, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc, tm);
+  else
+    zgemm_tile<false, false>(blockIdx.x, g.m, g.n, g.k, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc, tm);
+}
+
+int bm_launch_zgemm_batched(hipStream_t s, int count, const bm_gemm_desc *d_dev, int max_tiles) {
+  if (count <= 0 || max_tiles <= 0) return BM_OK;
+  if (count > 65535) return BM_E_ARG;
+  hipLaunchKernelGGL(zgemm_batched_kernel, dim3(max_tiles, count), dim3(256), 0, s, d_dev);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+
 // Shallow, narrow products (k <= 64, n <= 64: the update of the next panel's
 // columns in the LU, on its critical path): 32 x 32 output tiles (four times the
 // workgroups of the 64 x 64 kernel) and the whole depth staged in one step, so a
@@ -251,7 +282,8 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
     const int row = row0 + wm * 16 + fi, col = col0 + wn * 16 + 4 * r + fq;
     if (row < m && col < n) {
       cplx out = cmul(alpha, cmk(accr[r], acci[r]));
-      out = cadd(out, cmul(beta, cmk(cv[r].x, cv[r].y)));
+      // beta = 0: C's old value is not used (it may hold anything, NaN included)
+      if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, cmk(cv[r].x, cv[r].y)));
       C[row + (long)col * ldc] = out;
     }
   }

@@ -55,7 +55,8 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"bm_geometry": binding.BMGeometry, "bm_params": binding.BMParams,
                "bm_server_config": binding.BMServerConfig, "bm_request": binding.BMRequest,
-               "bm_request_result": binding.BMRequestResult, "bm_server_counters": binding.BMServerCounters}
+               "bm_request_result": binding.BMRequestResult, "bm_server_counters": binding.BMServerCounters,
+               "bm_fds_config": binding.BMFdsConfig}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
