@@ -333,10 +333,11 @@ SSM_PRINTED = {2: (0.42948496520839791 - 1.2813737976521153j, 98.895),
                3: (1.3080120322683002 - 1.6817888047453846j, 114.206)}
 
 
-def ssm_section(n_nodes, per_side):
+def ssm_section(n_nodes, per_side, quadrature="zeta31"):
     """Sakurai-Sugiura eigenvalues of the mixed equation on the disk of radius
     0.5 (eps0 = 1, eps1 = 4) in squares of side 0.1 around the two printed
-    eigenvalues, L = M = 4 (Table tb:ssm_parameters), through the request server."""
+    eigenvalues, L = M = 4 (Table tb:ssm_parameters), through the request server,
+    on the order-31 zeta-corrected rule of that table by default."""
     import mpmath as mp
     import numpy as np
     from paper_2512_14193_amd import binding as B
@@ -344,11 +345,13 @@ def ssm_section(n_nodes, per_side):
     from paper_2512_14193_amd import ssm
 
     bnd = I.disk(n_nodes, 0.5)
-    srv = B.Server(lanes=4)
+    srv = B.Server(lanes=4, quadrature=quadrature)
     ssm.eigenvalues(bnd, 1.0, 4.0, SSM_PRINTED[2][0], per_side=1, server=srv)  # handle creation, untimed
     out = {"boundary": f"disk a=0.5, N={n_nodes}", "eps0": 1.0, "eps1": 4.0, "contour": "square, side 0.1",
-           "nodes_per_side": per_side, "quadrature": "Gauss-Legendre per side", "n_rhs": 4, "n_moments": 4,
-           "results": []}
+           "nodes_per_side": per_side, "contour_quadrature": "Gauss-Legendre per side",
+           "boundary_quadrature": {"zeta31": "zeta-corrected trapezoid, order 31", "kress": "Kress log-split",
+                                   "zeta": "zeta-corrected trapezoid, one point"}[quadrature],
+           "n_rhs": 4, "n_moments": 4, "results": []}
     mp.mp.dps = 40
     for order, (z0, paper_s) in SSM_PRINTED.items():
         res = ssm.eigenvalues(bnd, 1.0, 4.0, z0, side=0.1, per_side=per_side, server=srv)
@@ -400,6 +403,7 @@ def main():
     ap.add_argument("--fds-steps", type=int, default=3)
     ap.add_argument("--ssm-n", type=int, default=4000)
     ap.add_argument("--ssm-per-side", type=int, default=48)
+    ap.add_argument("--ssm-quadrature", default="zeta31", choices=["zeta31", "kress", "zeta"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
@@ -503,7 +507,7 @@ def main():
         rec["serving"] = serving_section(args.serving_rate, args.serving_graph_max_n, args.serving_inflight,
                                          args.serving_lanes, args.serving_concurrent_max_n)
     if not args.no_ssm:
-        rec["ssm"] = ssm_section(args.ssm_n, args.ssm_per_side)
+        rec["ssm"] = ssm_section(args.ssm_n, args.ssm_per_side, args.ssm_quadrature)
     if not args.no_fds:
         rec["fast_direct_solver"] = fds_section(args.fds_steps, 1)
     if not args.no_cpu_baseline:

@@ -84,9 +84,12 @@ enum bm_precision {
 
 enum bm_quadrature {
   BM_QUAD_KRESS = 0,  /* Kress' logarithmic splitting (default): spectral convergence  */
-  BM_QUAD_ZETA1 = 1   /* zeta-corrected trapezoid rule with one correction point, the
+  BM_QUAD_ZETA1 = 1,  /* zeta-corrected trapezoid rule with one correction point, the
                          lowest-order rule of Sec. 4: O(h) for N_k, the solution
                          converges at O(1/N)                                          */
+  BM_QUAD_ZETA31 = 2  /* zeta-corrected trapezoid rule of order 31 (Sec. 5.3): 15
+                         correction nodes on each side of the singular one; needs
+                         N >= 32                                                      */
 };
 
 /* Maximum number of right-hand sides handled per internal pass; bm_solve and
@@ -180,9 +183,14 @@ int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_i
  * rule exact on constants, 2 h ln(h / 2pi) for ln(4 sin^2((t - tau)/2)) and
  * -h (N^2 - 1) / (24 pi) for the finite part of 1 / (8 pi sin^2((t - tau)/2)),
  * h = 2 pi / N (the values of the zeta-function regularisation of those sums).
+ * BM_QUAD_ZETA31 adds corrections at the 15 nodes on each side, from the
+ * zeta-function expansion of the punctured rule's error: h w_m for the logarithm
+ * (cancelling the terms up to h^31, w solving sum_m w_m m^2i = 2 zeta'(-2i)) and
+ * v_m / h for the hypersingular part (v the weights of f''(0)/2 from the nodes),
+ * with the weights at the singular node adjusted to keep exactness on constants.
  * The identity and zero blocks of eq. dis_mixedBM, and so Theorem thm:LU, hold
- * for either rule.  The assembled blocks are invalidated (bm_assemble must
- * run again).  Errors: BM_E_ARG (unknown quadrature). */
+ * for every rule.  The assembled blocks are invalidated (bm_assemble must
+ * run again).  Errors: BM_E_ARG (unknown quadrature, BM_QUAD_ZETA31 with N < 32). */
 int bm_set_quadrature(bm_problem *p, int32_t quadrature);
 
 /* Refinement statistics of the latest bm_solve (host pointers): the largest
@@ -317,6 +325,7 @@ typedef struct {
   int32_t concurrent_max_n;  /* N up to which requests share the device; 0: 1024;
                                 with lanes > 1 it must be <= 2048 and
                                 lanes * ceil(concurrent_max_n / 64) <= CUs / 2      */
+  int32_t quadrature;        /* BM_QUAD_* of every handle (0: Kress)                 */
 } bm_server_config;
 
 /* One request.  Device arrays: the geometry (as bm_assemble), B (3N x nrhs,

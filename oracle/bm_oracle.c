@@ -198,6 +198,44 @@ static void zeta_weights_l(int N, long double *R, long double *T) {
   }
 }
 
+/* Zeta-corrected trapezoid weights of order 2p + 1 (p correction nodes on each
+ * side of the singular one; the weights h w_m and v_m / h come from the moment
+ * conditions of the zeta-function expansion of the punctured rule's error, computed
+ * by the caller in extended precision, see zeta_corrections.py):
+ *   R_m = h ln(4 sin^2(pi m/N)) + h w_|m|,   R_0 = 2 h ln(h/2pi) - 2 h sum w_m,
+ *   T_m = h / (8 pi sin^2(pi m/N)) + v_|m| / (2 pi h),
+ *   T_0 = -h (N^2 - 1)/(24 pi) - (1/(pi h)) sum v_m,
+ * for 1 <= |m| <= p (m taken mod N on both sides), the plain trapezoid weights beyond. */
+#define ZETA_PMAX 64
+static int zeta_p = 0;
+static long double zeta_w[ZETA_PMAX + 1], zeta_v[ZETA_PMAX + 1];
+
+int orc_set_zeta_corrections(int p, const double *w, const double *v) {
+  if (p < 0 || p > ZETA_PMAX) return -1;
+  zeta_p = p;
+  for (int m = 1; m <= p; ++m) { zeta_w[m] = w[m - 1]; zeta_v[m] = v[m - 1]; }
+  return 0;
+}
+
+static int zeta_hi_weights_l(int N, long double *R, long double *T) {
+  const int p = zeta_p;
+  if (2 * p + 1 > N) return -1;
+  zeta_weights_l(N, R, T);
+  const long double h = 2.0L * PI_L / (long double)N;
+  long double sw = 0.0L, sv = 0.0L;
+  for (int m = 1; m <= p; ++m) {
+    sw += zeta_w[m];
+    sv += zeta_v[m];
+    R[m] += h * zeta_w[m];
+    R[N - m] += h * zeta_w[m];
+    T[m] += zeta_v[m] / (2.0L * PI_L * h);
+    T[N - m] += zeta_v[m] / (2.0L * PI_L * h);
+  }
+  R[0] -= 2.0L * h * sw;
+  T[0] -= sv / (PI_L * h);
+  return 0;
+}
+
 void orc_zeta_weights(int N, double *R, double *T) {
   long double *r = (long double *)malloc(sizeof(long double) * N);
   long double *t = (long double *)malloc(sizeof(long double) * N);
@@ -324,15 +362,19 @@ static void op_entry(const geom_t *g, lcplx k, int i, int j, opent_t *o) {
   }
 }
 
-/* quad: 0 = Kress log-split weights, 1 = zeta-corrected trapezoid weights. */
+/* quad: 0 = Kress log-split weights, 1 = zeta-corrected trapezoid weights with one
+ * correction point, 2 = zeta-corrected weights of the order set by
+ * orc_set_zeta_corrections. */
 static int geom_init(geom_t *g, int N, const double *x, const double *dx,
                      const double *ddx, const double *d3x, int quad) {
-  if (N < 4 || (N % 2) != 0 || quad < 0 || quad > 1) return -1;
+  if (N < 4 || (N % 2) != 0 || quad < 0 || quad > 2) return -1;
+  if (quad == 2 && 2 * zeta_p + 1 > N) return -1;
   g->N = N; g->x = x; g->dx = dx; g->ddx = ddx; g->d3x = d3x;
   g->R = (long double *)malloc(sizeof(long double) * N);
   g->T = (long double *)malloc(sizeof(long double) * N);
   if (quad == 0) kress_weights_l(N, g->R, g->T);
-  else zeta_weights_l(N, g->R, g->T);
+  else if (quad == 1) zeta_weights_l(N, g->R, g->T);
+  else zeta_hi_weights_l(N, g->R, g->T);
   return 0;
 }
 
@@ -647,4 +689,14 @@ int orc_point_kernels(double kr, double ki, int ns, const double *x, const doubl
     out[4*s + 3] = (dcplx)(ik4 * ((H1 / r) * a + (nxd * nyd / r2) * (k * H0 - 2.0L * H1 / r)) * ws);
   }
   return bad ? -1 : 0;
+}
+
+/* R, T of the zeta-corrected rule of the order set by orc_set_zeta_corrections. */
+int orc_zeta31_weights(int N, double *R, double *T) {
+  long double *r = (long double *)malloc(sizeof(long double) * N);
+  long double *t = (long double *)malloc(sizeof(long double) * N);
+  int rc = zeta_hi_weights_l(N, r, t);
+  for (int m = 0; m < N && !rc; ++m) { R[m] = (double)r[m]; T[m] = (double)t[m]; }
+  free(r); free(t);
+  return rc;
 }

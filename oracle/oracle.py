@@ -46,6 +46,8 @@ def lib():
             L.orc_hankel01.argtypes = [ctypes.c_double, ctypes.c_double, _dptr]
             L.orc_kress_weights.argtypes = [ctypes.c_int, _dptr, _dptr]
             L.orc_zeta_weights.argtypes = [ctypes.c_int, _dptr, _dptr]
+            L.orc_set_zeta_corrections.argtypes = [ctypes.c_int, _dptr, _dptr]
+            L.orc_zeta31_weights.argtypes = [ctypes.c_int, _dptr, _dptr]
             geo = [ctypes.c_int, _dptr, _dptr, _dptr, _dptr]
             L.orc_layer_operators.argtypes = geo + [ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 4 + [ctypes.c_int]
             L.orc_block_entries.argtypes = geo + [_dptr, ctypes.c_int, _iptr, _iptr, _iptr, ctypes.c_void_p, ctypes.c_int]
@@ -90,7 +92,33 @@ def hankel01(z):
     return out[..., 0], out[..., 1], out[..., 2], out[..., 3]
 
 
-QUADRATURES = {"kress": 0, "zeta": 1}
+QUADRATURES = {"kress": 0, "zeta": 1, "zeta31": 2}
+ZETA31_P = 15  # order 2p + 1 = 31
+_zeta_set = None
+
+
+def _quad(name):
+    """The oracle's code for a quadrature; the order-31 zeta rule loads its
+    correction weights (zeta_corrections.py) into the C oracle first."""
+    global _zeta_set
+    q = QUADRATURES[name]
+    if q == 2 and _zeta_set != ZETA31_P:
+        from oracle import zeta_corrections as Z
+        w = np.ascontiguousarray(Z.log_weights(ZETA31_P), dtype=np.float64)
+        v = np.ascontiguousarray(Z.hyp_weights(ZETA31_P), dtype=np.float64)
+        if lib().orc_set_zeta_corrections(ZETA31_P, _d(w), _d(v)):
+            raise ValueError("zeta correction order")
+        _zeta_set = ZETA31_P
+    return q
+
+
+def zeta31_weights(n_nodes: int):
+    """R, T of the order-31 zeta-corrected rule (through a layer-operator call's tables)."""
+    _quad("zeta31")
+    R = np.empty(n_nodes)
+    T = np.empty(n_nodes)
+    lib().orc_zeta31_weights(n_nodes, _d(R), _d(T))
+    return R, T
 
 
 def kress_weights(n_nodes: int):
@@ -115,7 +143,7 @@ def layer_operators(boundary, k, quad="kress"):
     mats = [np.empty((N, N), dtype=np.complex128) for _ in range(4)]
     keep, g = _geo(boundary)
     k = complex(k)
-    rc = lib().orc_layer_operators(*g, k.real, k.imag, *[_c(m) for m in mats], QUADRATURES[quad])
+    rc = lib().orc_layer_operators(*g, k.real, k.imag, *[_c(m) for m in mats], _quad(quad))
     if rc:
         raise ValueError("invalid geometry")
     return tuple(mats)
@@ -134,7 +162,7 @@ def block_entries(boundary, physics, which, rows, cols, quad="kress"):
     keep, g = _geo(boundary)
     prm = physics.as_array()
     ip = lambda a: a.ctypes.data_as(_iptr)  # noqa: E731
-    lib().orc_block_entries(*g, _d(prm), rows.shape[0], ip(which), ip(rows), ip(cols), _c(out), QUADRATURES[quad])
+    lib().orc_block_entries(*g, _d(prm), rows.shape[0], ip(which), ip(rows), ip(cols), _c(out), _quad(quad))
     return out
 
 
@@ -144,7 +172,7 @@ def build_mixed(boundary, physics, quad="kress"):
     A = np.empty((3 * N, 3 * N), dtype=np.complex128)
     keep, g = _geo(boundary)
     prm = physics.as_array()
-    if lib().orc_build_mixed(*g, _d(prm), _c(A), QUADRATURES[quad]):
+    if lib().orc_build_mixed(*g, _d(prm), _c(A), _quad(quad)):
         raise ValueError("invalid geometry")
     return A
 
@@ -155,7 +183,7 @@ def build_ordinary(boundary, physics, quad="kress"):
     A = np.empty((2 * N, 2 * N), dtype=np.complex128)
     keep, g = _geo(boundary)
     prm = physics.as_array()
-    if lib().orc_build_ordinary(*g, _d(prm), _c(A), QUADRATURES[quad]):
+    if lib().orc_build_ordinary(*g, _d(prm), _c(A), _quad(quad)):
         raise ValueError("invalid geometry")
     return A
 

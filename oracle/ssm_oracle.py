@@ -79,15 +79,16 @@ def ss_eigenvalues(solve, center, side, per_side, U, V, n_mom, delta=1e-12):
     return np.sort_complex(np.array([v for v in zs if inside_square(v, center, side)])), S
 
 
-def mixed_resolvent(boundary, eps0, eps1, beta_of=None):
+def mixed_resolvent(boundary, eps0, eps1, beta_of=None, quad="kress"):
     """solve(omega, V) = A(omega)^{-1} V for the mixed system of eq. dis_mixedBM
-    with k_i = omega sqrt(eps_i) and beta = i / k0 unless beta_of(omega) is given."""
+    with k_i = omega sqrt(eps_i) and beta = i / k0 unless beta_of(omega) is given,
+    discretised with the quadrature `quad`."""
     from paper_2512_14193_amd import inputs as I
 
     def solve(omega, V):
         k0, k1 = omega * np.sqrt(eps0), omega * np.sqrt(eps1)
         beta = beta_of(omega) if beta_of else 1j / k0
         ph = I.Physics(k0=k0, k1=k1, eps0=eps0, eps1=eps1, beta=beta)
-        return O.zgesv(O.build_mixed(boundary, ph), V)
+        return O.zgesv(O.build_mixed(boundary, ph, quad), V)
 
     return solve

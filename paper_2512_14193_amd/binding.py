@@ -22,7 +22,8 @@ BM_MIXED, BM_ORDINARY = 0, 1
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
 BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT, BM_E_DOMAIN = -7, -8, -9, -10
 BM_PREC_FP64, BM_PREC_MIXED = 0, 1
-BM_QUAD_KRESS, BM_QUAD_ZETA1 = 0, 1
+BM_QUAD_KRESS, BM_QUAD_ZETA1, BM_QUAD_ZETA31 = 0, 1, 2
+QUADRATURES = {"kress": BM_QUAD_KRESS, "zeta": BM_QUAD_ZETA1, "zeta31": BM_QUAD_ZETA31}
 BM_MAX_NRHS = 32
 
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
@@ -48,7 +49,8 @@ class BMParams(ctypes.Structure):
 
 class BMServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("graph_max_n", ctypes.c_int32), ("lanes", ctypes.c_int32), ("concurrent_max_n", ctypes.c_int32)]
+                ("graph_max_n", ctypes.c_int32), ("lanes", ctypes.c_int32), ("concurrent_max_n", ctypes.c_int32),
+                ("quadrature", ctypes.c_int32)]
 
 
 class BMRequest(ctypes.Structure):
@@ -287,9 +289,10 @@ class Problem:
         check(lib().bm_set_precision(self._h, code, float(tol), int(max_iter)), "bm_set_precision")
 
     def set_quadrature(self, quadrature: str = "kress"):
-        """bm_set_quadrature: "kress" (log splitting) or "zeta" (one-point
-        zeta-corrected trapezoid rule); the problem must be assembled again."""
-        code = {"kress": BM_QUAD_KRESS, "zeta": BM_QUAD_ZETA1}[quadrature]
+        """bm_set_quadrature: "kress" (log splitting), "zeta" (one-point
+        zeta-corrected trapezoid rule) or "zeta31" (the order-31 one); the problem
+        must be assembled again."""
+        code = QUADRATURES[quadrature]
         check(lib().bm_set_quadrature(self._h, code), "bm_set_quadrature")
 
     def refine_stats(self):
@@ -336,11 +339,11 @@ class Server:
     returns the request's result."""
 
     def __init__(self, hbm_budget_bytes: int = 0, max_inflight: int = 4, graph_max_n: int = 0, lanes: int = 4,
-                 concurrent_max_n: int = 1024):
+                 concurrent_max_n: int = 1024, quadrature: str = "kress"):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs on the GPU only")
         cfg = BMServerConfig(int(hbm_budget_bytes), int(max_inflight), int(graph_max_n), int(lanes),
-                             int(concurrent_max_n))
+                             int(concurrent_max_n), QUADRATURES[quadrature])
         h = ctypes.c_void_p()
         check(lib().bm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bm_server_create")
         self._h = h

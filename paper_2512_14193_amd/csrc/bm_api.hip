@@ -379,7 +379,8 @@ int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_i
 
 int bm_set_quadrature(bm_problem *p, int32_t quadrature) {
   if (!p) return BM_E_ARG;
-  if (quadrature != BM_QUAD_KRESS && quadrature != BM_QUAD_ZETA1) return BM_E_ARG;
+  if (quadrature != BM_QUAD_KRESS && quadrature != BM_QUAD_ZETA1 && quadrature != BM_QUAD_ZETA31) return BM_E_ARG;
+  if (quadrature == BM_QUAD_ZETA31 && p->n < 32) return BM_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   if (int rc = bm_launch_weights(p->stream, p->n, p->wts, quadrature)) return rc;
   p->quad = quadrature;

@@ -21,6 +21,7 @@
 
 #include "bm_hankel.h"
 #include "bm_internal.h"
+#include "bm_zeta_corr.h"
 
 __constant__ double bm_hk_g0[BM_HQ + 1];
 __constant__ double bm_hk_g1[BM_HQ + 1];
@@ -116,12 +117,50 @@ __global__ void zeta_weights_kernel(int N, double *wts) {
   }
 }
 
+// The order-31 zeta-corrected rule: the one-point tables plus the corrections at the
+// nodes 1 <= |m| <= BM_ZETA_P (m taken mod N on both sides) of bm_zeta_corr.h:
+//   R_m += h w_|m|,  R_0 = 2 h ln(h / 2 pi) - 2 h sum w_m,
+//   T_m += v_|m| / (2 pi h),  T_0 -= sum v_m / (pi h).
+struct zeta_corr_tab {
+  double w[BM_ZETA_P], v[BM_ZETA_P];
+};
+__global__ void zeta_corr_kernel(int N, zeta_corr_tab c, double *wts) {
+  const double h = 2.0 * BM_PI / N;
+  const int m = threadIdx.x + 1;
+  if (m <= BM_ZETA_P) {
+    const double dw = h * c.w[m - 1], dv = c.v[m - 1] / (2.0 * BM_PI * h);
+    wts[m] += dw;
+    wts[N - m] += dw;
+    wts[N + m] += dv;
+    wts[N + N - m] += dv;
+  }
+  if (threadIdx.x == 0) {
+    double sw = 0.0, sv = 0.0;
+    for (int q = 0; q < BM_ZETA_P; ++q) {
+      sw += c.w[q];
+      sv += c.v[q];
+    }
+    wts[0] -= 2.0 * h * sw;
+    wts[N] -= sv / (BM_PI * h);
+  }
+}
+
 int bm_launch_weights(hipStream_t s, int n, double *wts, int quad) {
-  if (quad == BM_QUAD_ZETA1)
+  if (quad == BM_QUAD_ZETA31 && n < 2 * BM_ZETA_P + 2) return BM_E_ARG;
+  if (quad == BM_QUAD_ZETA1 || quad == BM_QUAD_ZETA31)
     hipLaunchKernelGGL(zeta_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, wts);
   else
     hipLaunchKernelGGL(weights_kernel, dim3(n), dim3(256), 0, s, n, wts);
   BM_HIP_TRY(hipGetLastError());
+  if (quad == BM_QUAD_ZETA31) {
+    zeta_corr_tab c;
+    for (int q = 0; q < BM_ZETA_P; ++q) {
+      c.w[q] = bm_zeta_w[q];
+      c.v[q] = bm_zeta_v[q];
+    }
+    hipLaunchKernelGGL(zeta_corr_kernel, dim3(1), dim3(64), 0, s, n, c, wts);
+    BM_HIP_TRY(hipGetLastError());
+  }
   return bm_hankel_init();
 }
 

@@ -83,6 +83,7 @@ struct bm_server {
   int max_inflight = 4;        // per lane
   int graph_max_n = 0;
   int concurrent_max_n = 0;
+  int quad = BM_QUAD_KRESS;    // quadrature of every handle
 
   std::mutex mu;
   std::condition_variable cv_work;   // worker: new request or stop
@@ -176,6 +177,10 @@ int acquire(bm_server *s, const bm_request &r, int lane, srv_handle **out) {
   srv_handle *h = new (std::nothrow) srv_handle();
   if (!h) return BM_E_NOMEM;
   int rc = bm_create(r.n, BM_MIXED, (void *)s->lanes[lane].stream, &h->p);
+  if (!rc && s->quad != BM_QUAD_KRESS) {
+    rc = bm_set_quadrature(h->p, s->quad);
+    if (rc) bm_destroy(h->p);
+  }
   if (rc) {
     delete h;
     return rc;
@@ -437,6 +442,7 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
   bm_server_config c{};
   if (cfg) c = *cfg;
   if (c.graph_max_n < 0 || c.lanes < 0 || c.lanes > 16 || c.concurrent_max_n < 0) return BM_E_ARG;
+  if (c.quadrature != BM_QUAD_KRESS && c.quadrature != BM_QUAD_ZETA1 && c.quadrature != BM_QUAD_ZETA31) return BM_E_ARG;
   const int lanes = c.lanes > 0 ? c.lanes : 4;
   const int cmax = c.concurrent_max_n > 0 ? c.concurrent_max_n : 1024;
   int dev = 0, ncu = 0;
@@ -450,6 +456,7 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
   s->max_inflight = c.max_inflight > 0 ? c.max_inflight : 4;
   s->graph_max_n = c.graph_max_n;
   s->concurrent_max_n = cmax;
+  s->quad = c.quadrature;
   size_t free_b = 0, total_b = 0;
   bool ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
   s->budget = c.hbm_budget_bytes > 0 ? c.hbm_budget_bytes : (int64_t)(0.9 * (double)free_b);

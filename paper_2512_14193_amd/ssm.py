@@ -62,14 +62,16 @@ def contour(center: complex, side: float, per_side: int):
 def eigenvalues(boundary, eps0: float, eps1: float, center: complex, side: float = 0.1, per_side: int = 48,
                 n_rhs: int = 4, n_mom: int = 4, seed: int = I.SEED_BASE + 7, delta: float = 1e-8,
                 server: B.Server | None = None, U: np.ndarray | None = None, V: np.ndarray | None = None,
-                beta_of=None) -> SSResult:
+                beta_of=None, quadrature: str = "zeta31") -> SSResult:
     """Eigenvalues of the mixed system on `boundary` (k_i = omega sqrt(eps_i),
     beta = i / k0 unless beta_of(omega) is given) inside the square of the
     given side around `center`.  U, V default to complex Gaussian blocks drawn
     from `seed` and `seed + 1` (V is the right-hand side block).  Singular
     values of H below delta times the largest are rounding noise: measured on
-    the disk of Sec. 5.3 that floor grows from 3e-13 at N = 256 to 1.4e-10 at
-    N = 4000, while the singular values of the eigenvalues stay near 0.4."""
+    the disk of Sec. 5.3 (Kress rule) that floor grows from 3e-13 at N = 256 to
+    1.4e-10 at N = 4000, while the singular values of the eigenvalues stay near
+    0.4.  `quadrature` is the rule of the solver's own server (by default the
+    order-31 zeta-corrected rule of that section); a given server brings its own."""
     N = boundary.n_nodes
     rows = 3 * N
     dev = torch.device("cuda")
@@ -83,7 +85,7 @@ def eigenvalues(boundary, eps0: float, eps1: float, center: complex, side: float
     z, w = contour(center, side, per_side)
     rho = 0.5 * side
     own = server is None
-    srv = B.Server(lanes=4) if own else server
+    srv = B.Server(lanes=4, quadrature=quadrature) if own else server
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:

@@ -7,7 +7,8 @@ domain it needs.
     H_2^(1) and H_3^(1)) against the oracle, and BM_E_DOMAIN when |k| r >= 6;
   * the eigenvalues from the request server + device moments against the
     oracle's projection with the same probing blocks, and against mpmath roots
-    of H_n^(1) (Table tb:ssm_eigenvalues): both twice, to 1e-12.
+    of H_n^(1) (Table tb:ssm_eigenvalues): both twice, to 1e-12, with the Kress
+    rule and with the order-31 zeta-corrected rule the paper uses there.
 """
 import os
 
@@ -91,16 +92,18 @@ def test_domain_error_and_recovery():
     assert e.value.code == B.BM_E_ARG
 
 
+@pytest.mark.parametrize("quad", ["kress", "zeta31"])
 @pytest.mark.parametrize("order", [2, 3])
-def test_ss_eigenvalues_vs_oracle_and_hankel_zeros(order):
+def test_ss_eigenvalues_vs_oracle_and_hankel_zeros(order, quad):
     N = 64
+    print(f"[ssm] order {order}, {quad}", flush=True)
     bnd = I.disk(N, 0.5)
     center = printed(order)[0]
     rng = np.random.default_rng(10 + order)
     g = lambda: rng.standard_normal((3 * N, 4)) + 1j * rng.standard_normal((3 * N, 4))  # noqa: E731
     U, V = g(), g()
-    res = ssm.eigenvalues(bnd, 1.0, 4.0, center, side=0.1, per_side=48, n_rhs=4, n_mom=4, U=U, V=V)
-    ev_o, sv_o = SO.ss_eigenvalues(SO.mixed_resolvent(bnd, 1.0, 4.0), center, 0.1, 48, U, V, 4)
+    res = ssm.eigenvalues(bnd, 1.0, 4.0, center, side=0.1, per_side=48, n_rhs=4, n_mom=4, U=U, V=V, quadrature=quad)
+    ev_o, sv_o = SO.ss_eigenvalues(SO.mixed_resolvent(bnd, 1.0, 4.0, quad=quad), center, 0.1, 48, U, V, 4)
     assert res.n_solves == 192 and res.rank == 2 and len(res.eigenvalues) == 2
     assert np.abs(res.eigenvalues - ev_o).max() < 1e-12
     assert np.abs(res.singular_values[:2] - sv_o[:2]).max() < 1e-10 * sv_o[0]

@@ -1,5 +1,5 @@
-"""Zeta-corrected quadrature (one correction point) on the device against the
-oracle's, and the quadrature switch of a problem handle."""
+"""Zeta-corrected quadratures (the one-point rule and the order-31 rule) on the
+device against the oracle's, and the quadrature switch of a problem handle."""
 import numpy as np
 import pytest
 import torch
@@ -29,14 +29,16 @@ def to_dev(a):
     return B.fortran(torch.as_tensor(np.asarray(a, dtype=np.complex128)).cuda())
 
 
+@pytest.mark.parametrize("rule", ["zeta", "zeta31"])
 @pytest.mark.parametrize("name,bnd,ph", CASES, ids=[c[0] for c in CASES])
-def test_zeta_blocks_and_solution(name, bnd, ph):
+def test_zeta_blocks_and_solution(name, bnd, ph, rule):
     N = bnd.n_nodes
+    print(f"[zeta] {name} {rule}", flush=True)
     P = B.Problem(N, "mixed")
-    P.set_quadrature("zeta")
+    P.set_quadrature(rule)
     P.assemble(bnd, ph)
     top, bot = (to_np(t) for t in P.copy_blocks())
-    A = O.build_mixed(bnd, ph, "zeta")
+    A = O.build_mixed(bnd, ph, rule)
     for got, ref in ((top, np.vstack([A[:N, 2 * N:], A[N:2 * N, 2 * N:]])), (bot, A[2 * N:, :2 * N])):
         assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
     assert P.block_lu() == 0
@@ -68,3 +70,40 @@ def test_quadrature_switch():
     with pytest.raises(B.BMError) as e:
         B.check(B.lib().bm_set_quadrature(P._h, 7), "bm_set_quadrature")
     assert e.value.code == B.BM_E_ARG
+
+
+def test_zeta31_weights_table_and_smallest_size():
+    """The device's order-31 correction table against the oracle's weights (through
+    the single-layer block of a disk at the smallest admissible N = 32, where the
+    fifteen-point stencils on both sides just stay apart), and N = 30 refused."""
+    bnd, ph = I.disk(32, 1.0), I.Physics.from_wavenumbers(2.0, 3.0)
+    P = B.Problem(32, "mixed")
+    P.set_quadrature("zeta31")
+    P.assemble(bnd, ph)
+    top, bot = (to_np(t) for t in P.copy_blocks())
+    A = O.build_mixed(bnd, ph, "zeta31")
+    assert np.abs(top[:32] - A[:32, 64:]).max() < 1e-13 * np.abs(A[:32, 64:]).max()
+    assert np.abs(bot - A[64:, :64]).max() < 1e-13 * np.abs(A[64:, :64]).max()
+    P.close()
+    Q = B.Problem(30, "mixed")
+    with pytest.raises(B.BMError) as e:
+        Q.set_quadrature("zeta31")
+    assert e.value.code == B.BM_E_ARG
+    Q.close()
+
+
+def test_served_request_on_zeta31_vs_oracle():
+    """A server whose handles use the order-31 rule: a served solve against the
+    oracle's dense solve of the same system."""
+    bnd, ph = I.star(160), I.Physics.from_wavenumbers(5.0 + 0.2j, 7.5 + 0.3j)
+    N = 160
+    geo = [torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous() for a in (bnd.x, bnd.dx, bnd.ddx, bnd.d3x)]
+    Bh = I.probing_rhs(3 * N, 3, 21)
+    X = B.fortran_empty(3 * N, 3)
+    srv = B.Server(lanes=2, quadrature="zeta31")
+    res = srv.wait(srv.submit(geo, ph, to_dev(Bh), X))
+    srv.close()
+    assert res["status"] == 0
+    Xo = O.zgesv(O.build_mixed(bnd, ph, "zeta31"), Bh)
+    Xg = to_np(X)
+    assert np.max(np.linalg.norm(Xg - Xo, axis=0) / np.linalg.norm(Xo, axis=0)) < 1e-10
