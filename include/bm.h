@@ -193,6 +193,24 @@ int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_i
  * run again).  Errors: BM_E_ARG (unknown quadrature, BM_QUAD_ZETA31 with N < 32). */
 int bm_set_quadrature(bm_problem *p, int32_t quadrature);
 
+/* Whether bm_block_lu forms U33 = -M31 M13 - M32 M23 (Theorem thm:LU) in column
+ * segments beside the factorisation of the columns already formed (on = 1) or
+ * in full before it (on = 0).  Both give the factorisation of the same U33 with
+ * the same pivoting rule; the segmented product sums k in slices for its first
+ * columns, so the two agree to rounding, not bitwise.  Available for the mixed
+ * form with N <= 4096 in FP64 precision (the default there; the mixed-precision
+ * factorisation always forms U33 first).  Errors: BM_E_ARG (on = 1 where it is
+ * not available). */
+int bm_set_lu_overlap(bm_problem *p, int32_t on);
+
+/* Host pointers: *enabled the setting of bm_set_lu_overlap; *segments the
+ * column segments in which the latest bm_block_lu formed U33 beside its
+ * factorisation (0: formed in full first, also where the overlap is enabled but
+ * the product would not keep ahead of the panels on this device).  With
+ * profiling on, phase 1 of bm_phase_times is then the product's span (its first
+ * segment's start to its last one's end) and phase 2 the whole factorisation. */
+int bm_lu_overlap_info(bm_problem *p, int32_t *enabled, int32_t *segments);
+
 /* Refinement statistics of the latest bm_solve (host pointers): the largest
  * number of refinement steps over its column chunks and the final
  * max_j ||b_j - A x_j||_2 / ||b_j||_2 (0 after an FP64 solve). */

@@ -31,6 +31,7 @@ EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
             "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
             "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
+            "bm_set_lu_overlap", "bm_lu_overlap_info",
             "bm_zgetrf_noalloc", "bm_fds_create", "bm_fds_factor", "bm_fds_solve", "bm_fds_rhs_plane_wave",
             "bm_fds_far_field", "bm_fds_info", "bm_fds_destroy"]
 
@@ -146,6 +147,8 @@ def lib():
         L.bm_server_destroy.restype = None
         L.bm_block_moments.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, dp, vp]
         L.bm_set_quadrature.argtypes = [vp, i32]
+        L.bm_set_lu_overlap.argtypes = [vp, i32]
+        L.bm_lu_overlap_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bm_strerror.argtypes = [ctypes.c_int]
         L.bm_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -287,6 +290,16 @@ class Problem:
         """bm_set_precision: "fp64" or "mixed" (FP32 matrix cores + FP64 refinement)."""
         code = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED}[precision]
         check(lib().bm_set_precision(self._h, code, float(tol), int(max_iter)), "bm_set_precision")
+
+    def set_lu_overlap(self, on: bool = True):
+        """bm_set_lu_overlap: form U33 beside its factorisation (True) or before it."""
+        check(lib().bm_set_lu_overlap(self._h, 1 if on else 0), "bm_set_lu_overlap")
+
+    def lu_overlap_info(self):
+        """bm_lu_overlap_info: (enabled, segments of the latest factorisation)."""
+        e, sg = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib().bm_lu_overlap_info(self._h, ctypes.byref(e), ctypes.byref(sg)), "bm_lu_overlap_info")
+        return bool(e.value), sg.value
 
     def set_quadrature(self, quadrature: str = "kress"):
         """bm_set_quadrature: "kress" (log splitting), "zeta" (one-point

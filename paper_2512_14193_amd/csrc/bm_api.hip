@@ -41,6 +41,7 @@ static void free_problem(bm_problem *p) {
   (void)hipFree(p->ir_r);
   (void)hipFree(p->ir_d);
   (void)hipFree(p->ir_norm);
+  (void)hipFree(p->pipe_w);
   bm_getrf_ws_destroy(p->gws);
   for (int i = 0; i < BM_NPHASE; ++i)
     if (p->ev_created[i])
@@ -56,7 +57,7 @@ static void free_problem(bm_problem *p) {
 // Device bytes of every allocation of a problem handle: bm_create allocates
 // exactly these and bm_problem_bytes adds them up (zero: not allocated).
 struct bm_alloc_sizes {
-  size_t geo, wts, top, bot, lu, ipiv, dinv, perm, work_g, work_p, dev_err, ir_r, ir_d, ir_norm;
+  size_t geo, wts, top, bot, lu, ipiv, dinv, perm, work_g, work_p, dev_err, ir_r, ir_d, ir_norm, pipe_w;
 };
 
 static bm_alloc_sizes problem_sizes(int n, int formulation) {
@@ -83,6 +84,8 @@ static bm_alloc_sizes problem_sizes(int n, int formulation) {
   z.ir_r = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
   z.ir_d = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
   z.ir_norm = mixed ? sizeof(double) * 2 * BM_MAX_NRHS : 0;
+  // split-K partials of the Schur complement computed beside the LU
+  z.pipe_w = (mixed && n <= BM_PIPE_MAX_N) ? c * bm_getrf_pipe_w_elems(n) : 0;
   return z;
 }
 
@@ -115,11 +118,17 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
             dev_alloc(&p->bot, z.bot) && dev_alloc(&p->lu, z.lu) && dev_alloc(&p->ipiv, z.ipiv) &&
             dev_alloc(&p->dinv, z.dinv) && dev_alloc(&p->perm, z.perm) && dev_alloc(&p->work_g, z.work_g) &&
             dev_alloc(&p->work_p, z.work_p) && dev_alloc(&p->dev_err, z.dev_err) && dev_alloc(&p->ir_r, z.ir_r) &&
-            dev_alloc(&p->ir_d, z.ir_d) && dev_alloc(&p->ir_norm, z.ir_norm);
+            dev_alloc(&p->ir_d, z.ir_d) && dev_alloc(&p->ir_norm, z.ir_norm) && dev_alloc(&p->pipe_w, z.pipe_w);
+  p->pipe_w_elems = z.pipe_w / sizeof(cplx);
   p->prec = BM_PREC_FP64;
   p->ir_tol = 1e-12;
   p->ir_maxit = 10;
   if (ok) p->gws = bm_getrf_ws_create(p->nf);
+  // the Schur complement beside the LU (mixed form, FP64, N <= BM_PIPE_MAX_N)
+  if (ok && p->gws && p->pipe_w) {
+    ok = bm_getrf_pipe_create(p->gws) == BM_OK;
+    p->pipeline = ok ? 1 : 0;
+  }
   if (!ok || !p->gws) {
     free_problem(p);
     return BM_E_NOMEM;
@@ -149,7 +158,7 @@ void bm_destroy(bm_problem *p) {
 
 // Phase timing: each call of a phase records an event pair in a ring of
 // BM_EV_RING slots; bm_phase_times sums the pairs recorded since its last call.
-void bm_phase_begin(bm_problem *p, int ph) {
+void bm_phase_begin_on(bm_problem *p, int ph, hipStream_t st) {
   if (!p->profiling) return;
   if (!p->ev_created[ph]) {
     for (int e = 0; e < BM_EV_RING; ++e) {
@@ -158,14 +167,18 @@ void bm_phase_begin(bm_problem *p, int ph) {
     }
     p->ev_created[ph] = 1;
   }
-  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][0], p->stream);
+  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][0], st);
 }
 
-void bm_phase_end(bm_problem *p, int ph) {
+// (the end may be recorded on another stream of the device than the begin)
+void bm_phase_end_on(bm_problem *p, int ph, hipStream_t st) {
   if (!p->profiling || !p->ev_created[ph]) return;
-  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][1], p->stream);
+  (void)hipEventRecord(p->ev[ph][p->ev_count[ph] % BM_EV_RING][1], st);
   ++p->ev_count[ph];
 }
+
+void bm_phase_begin(bm_problem *p, int ph) { bm_phase_begin_on(p, ph, p->stream); }
+void bm_phase_end(bm_problem *p, int ph) { bm_phase_end_on(p, ph, p->stream); }
 
 static void phase_begin(bm_problem *p, int ph) { bm_phase_begin(p, ph); }
 static void phase_end(bm_problem *p, int ph) { bm_phase_end(p, ph); }
@@ -196,7 +209,7 @@ int bm_problem_bytes(int32_t n, int32_t formulation, int64_t *bytes) {
   if (formulation != BM_MIXED && formulation != BM_ORDINARY) return BM_E_ARG;
   const bm_alloc_sizes z = problem_sizes(n, formulation);
   size_t b = z.geo + z.wts + z.top + z.bot + z.lu + z.ipiv + z.dinv + z.perm + z.work_g + z.work_p + z.dev_err +
-             z.ir_r + z.ir_d + z.ir_norm;
+             z.ir_r + z.ir_d + z.ir_norm + z.pipe_w;
   b += bm_getrf_ws_bytes(formulation == BM_MIXED ? n : 2 * n);
   *bytes = (int64_t)b;
   return BM_OK;
@@ -243,6 +256,26 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   const int n = p->n, nf = p->nf;
   int rc = BM_OK;
+  if (p->form == BM_MIXED && p->prec == BM_PREC_FP64 && p->pipeline) {
+    // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23], formed in
+    // column segments beside the factorisation of the columns already formed
+    phase_begin(p, BM_PH_LU);
+    p->gws->prof = (p->profiling >= 2) ? p : nullptr;
+    p->gws->prof_schur = p->profiling ? p : nullptr;  // the product's span in BM_PH_SCHUR
+    rc = bm_getrf_schur_run(p->stream, n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, 2 * n, p->lu, nf, p->ipiv,
+                            p->dev_err, p->gws, p->pipe_w, p->pipe_w_elems, &p->lu_segments);
+    p->gws->prof = nullptr;
+    p->gws->prof_schur = nullptr;
+    if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
+    if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
+    phase_end(p, BM_PH_LU);
+    if (rc) return rc;
+    p->state = BM_ST_FACTORED;
+    p->factored_prec = p->prec;
+    if (info) return read_dev_err(p, info);
+    return BM_OK;
+  }
+  p->lu_segments = 0;
   if (p->form == BM_MIXED) {
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
     phase_begin(p, BM_PH_SCHUR);
@@ -385,6 +418,20 @@ int bm_set_quadrature(bm_problem *p, int32_t quadrature) {
   if (int rc = bm_launch_weights(p->stream, p->n, p->wts, quadrature)) return rc;
   p->quad = quadrature;
   if (p->state > BM_ST_CREATED) p->state = BM_ST_CREATED;  // blocks of the old rule are stale
+  return BM_OK;
+}
+
+int bm_set_lu_overlap(bm_problem *p, int32_t on) {
+  if (!p || (on != 0 && on != 1)) return BM_E_ARG;
+  if (on && (!p->pipe_w || !p->gws || !p->gws->pipe)) return BM_E_ARG;
+  p->pipeline = on;
+  return BM_OK;
+}
+
+int bm_lu_overlap_info(bm_problem *p, int32_t *enabled, int32_t *segments) {
+  if (!p || !enabled || !segments) return BM_E_ARG;
+  *enabled = p->pipeline;
+  *segments = p->lu_segments;
   return BM_OK;
 }
 

@@ -25,6 +25,7 @@
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
 // bounded: on expiry the kernel raises the device error flag and runs to completion.
+#include <cstring>
 #include <mutex>
 
 #include "bm_internal.h"
@@ -734,6 +735,9 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
 // driver
 // ---------------------------------------------------------------------------
 
+struct bm_lu_pipe;
+static void pipe_destroy(bm_lu_pipe *q);
+
 bm_getrf_ws *bm_getrf_ws_create(int n) {
   bm_getrf_ws *w = new bm_getrf_ws();
   w->n = n;
@@ -765,6 +769,7 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   }
   if (w->e_next) (void)hipEventDestroy(w->e_next);
   if (w->e_rest) (void)hipEventDestroy(w->e_rest);
+  pipe_destroy(w->pipe);
   delete w;
 }
 
@@ -833,17 +838,45 @@ int bm_getrf_prepare() {
   return BM_OK;
 }
 
-int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
-                 int gemm32) {
-  if (!w || w->n < n) return BM_E_ARG;
+// The interchanges of the panel at column j (jb columns, list swp) on the columns
+// [0, lcols), and on the columns [c0, c1) right of it also U12 = L11^{-1} A12 and
+// the trailing update A22 -= L21 U12 (FP32 matrix cores with gemm32).  `next`:
+// the narrow column split for the next panel's columns (critical path).
+static int lu_update(hipStream_t st, cplx *A, long lda, int n, int j, int jb, const int32_t *swp, int lcols, int c0,
+                     int c1, bool next, int gemm32) {
+  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  const int cw = next ? ST_CW_NEXT : ST_CW_REST;
+  const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 > c0) ? (c1 - c0 + cw - 1) / cw : 0;
+  if (nleft + nright > 0) {
+    if (next)
+      hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_NEXT>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A, lda,
+                         j, jb, lcols, c0, c1, swp, nleft);
+    else
+      hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_REST>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A, lda,
+                         j, jb, lcols, c0, c1, swp, nleft);
+    BM_HIP_TRY(hipGetLastError());
+  }
+  const int nr = n - j - jb, jn = j + jb;
+  if (nr > 0 && c1 > c0)
+    // gemm32: the FP32 matrix cores for the columns beyond the next panel (the
+    // next panel's 64 columns, on the critical path, keep the FP64 shallow kernel)
+    return ((gemm32 && !next) ? bm_launch_zgemm32 : bm_launch_zgemm)(st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda,
+                                                                     lda, A + j + (long)c0 * lda, lda, one,
+                                                                     A + jn + (long)c0 * lda, lda);
+  return BM_OK;
+}
+
+// Common start of a factorisation: panel shapes (rows per lane, workgroups) and
+// the device flags and the first panel's exchange words reset.
+static int lu_begin(hipStream_t s, int n, int32_t *dev_err, bm_getrf_ws *w, int *shape, int *ncu_out) {
   if (int rc0 = bm_getrf_prepare()) return rc0;
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   int ncu = 0;
   BM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  *ncu_out = ncu;
   if (int rc0 = bm_fill_u64(s, dev_err, 1, 0ull)) return rc0;  // [0] error, [1] info
   const int npanel = (n + LU_NB - 1) / LU_NB;
-  int shape[3 * 1024];  // rows per lane, P per panel
   if (npanel > 1024) return BM_E_ARG;
   for (int pi = 0; pi < npanel; ++pi) {
     const int R = n - pi * LU_NB;
@@ -855,70 +888,342 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     if (int rc0 = bm_fill_u64(s, w->slots, 2 * (size_t)jb0 * cstr0, ~0ull)) return rc0;
     if (int rc0 = bm_fill_u64(s, w->slots + SLOT_HDR, 2 * (size_t)jb0 * shape[1], ~0ull)) return rc0;
   }
-  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  return BM_OK;
+}
+
+// Launch of panel pi (all P workgroups must run at the same time: P <= the CU
+// count, checked in panel_shape, and one workgroup fits a CU, so on a device that
+// is not saturated by other work every workgroup is resident at once; a plain
+// launch avoids the start and drain cost of a cooperative launch.  Every wait in
+// the kernel is bounded, so a launch whose workgroups cannot all become resident
+// ends with BM_E_DEVICE, not a hang.)
+static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                    const int *shape, int pi) {
+  const int npanel = (n + LU_NB - 1) / LU_NB;
+  const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
+  int P = shape[3 * pi + 1];
+  int next_P = 0, next_jb = 0;
+  if (pi + 1 < npanel) {
+    next_jb = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
+    next_P = shape[3 * (pi + 1) + 1];
+  }
+  cplx *cur = w->slots + (size_t)(pi & 1) * SLOT_ELEMS, *nxt = w->slots + (size_t)((pi + 1) & 1) * SLOT_ELEMS;
+  int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
+  long ldal = (long)lda;
+  int nn = n, jj = j, jbb = jb;
+  void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp};
+  const int rpl = shape[3 * pi];
+  if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
+  BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
+  if (w->prof) bm_phase_end(w->prof, BM_PH_PANEL);
+  return BM_OK;
+}
+
+int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                 int gemm32) {
+  if (!w || w->n < n) return BM_E_ARG;
+  int shape[3 * 1024];  // rows per lane, P per panel
+  int ncu = 0;
+  if (int rc0 = lu_begin(s, n, dev_err, w, shape, &ncu)) return rc0;
+  const int npanel = (n + LU_NB - 1) / LU_NB;
+  // (a workspace without the second stream runs every update on s, in order)
+  const bool la = w->aux != nullptr;
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
     const int jb = (n - j < LU_NB) ? n - j : LU_NB;
-    int P = shape[3 * pi + 1];
-    int next_P = 0, next_jb = 0;
-    if (pi + 1 < npanel) {
-      next_jb = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
-      next_P = shape[3 * (pi + 1) + 1];
-    }
-    cplx *cur = w->slots + (size_t)(pi & 1) * SLOT_ELEMS, *nxt = w->slots + (size_t)((pi + 1) & 1) * SLOT_ELEMS;
-    int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
-    long ldal = (long)lda;
-    int nn = n, jj = j, jbb = jb;
-    void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp};
-    // All P workgroups must run at the same time.  P <= the CU count (checked in
-    // panel_shape) and one workgroup fits a CU, so on a device that is not
-    // saturated by other work every workgroup is resident at once; a plain launch
-    // avoids the start and drain cost of a cooperative launch.  Every wait in the
-    // kernel is bounded, so a launch whose workgroups cannot all become resident
-    // ends with BM_E_DEVICE, not a hang.
-    const int rpl = shape[3 * pi];
-    if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
-    BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
-    if (w->prof) bm_phase_end(w->prof, BM_PH_PANEL);
+    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi)) return rc;
+    const int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
     // Lookahead: the stream s applies the panel's interchanges and its update to the
     // next panel's columns only; the auxiliary stream applies them to every other
     // column while s factors the next panel.  s waits for that rest of panel k - 1
     // before it touches the columns of panel k + 1 (which were part of it).
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
-    // (a workspace without the second stream runs every update on s, in order)
-    const bool la = w->aux != nullptr;
     if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
-    auto update = [&](hipStream_t st, int lcols, int c0, int c1, bool next) -> int {
-      const int cw = next ? ST_CW_NEXT : ST_CW_REST;
-      const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 - c0 + cw - 1) / cw;
-      if (nleft + nright > 0) {
-        if (next)
-          hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_NEXT>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A,
-                             ldal, j, jb, lcols, c0, c1, (const int32_t *)swp, nleft);
-        else
-          hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_REST>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A,
-                             ldal, j, jb, lcols, c0, c1, (const int32_t *)swp, nleft);
-        BM_HIP_TRY(hipGetLastError());
-      }
-      if (nr > 0 && c1 > c0)
-        // gemm32: the FP32 matrix cores for the columns beyond the next panel (the
-        // next panel's 64 columns, on the critical path, keep the FP64 shallow kernel)
-        return ((gemm32 && !next) ? bm_launch_zgemm32 : bm_launch_zgemm)(
-            st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda, lda, A + j + (long)c0 * lda, lda, one,
-            A + jn + (long)c0 * lda, lda);
-      return BM_OK;
-    };
-    int rc = update(s, 0, jn, jn + jbn, true);
+    int rc = lu_update(s, A, (long)lda, n, j, jb, swp, 0, jn, jn + jbn, true, gemm32);
     if (rc) return rc;
     if (la) {
       BM_HIP_TRY(hipEventRecord(w->e_next, s));
       BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
     }
-    rc = update(la ? w->aux : s, j, jn + jbn, n, false);
+    rc = lu_update(la ? w->aux : s, A, (long)lda, n, j, jb, swp, j, jn + jbn, n, false, gemm32);
     if (rc) return rc;
     if (la) BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
   }
   if (w->aux && npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// LU of A = alpha Bot Top with the product computed beside the panels
+// (the Schur complement of Theorem thm:LU; FP64)
+//
+// The product is formed in column segments of whole 64-column blocks.  Block 0
+// goes first on the whole device (k split into slices summed afterwards, so that
+// its few tiles fill the CUs); the other segments follow on a third stream g as a
+// bounded persistent grid of one workgroup per CU, which leaves as many CUs free
+// as the largest panel has workgroups, while the panels factor the columns that
+// are already there.  A segment whose first panel is f is brought up to date by a
+// fourth stream c: the interchanges, U12 rows and trailing updates of panels
+// 0 .. f - 2 on its columns, in panel order, each as soon as its panel is done;
+// from panel f - 1 on the segment belongs to the ordinary lookahead (s for the
+// next panel's columns, aux for the others).  The catch-up reads every panel's L
+// columns as the panel left them, so the interchanges of later panels on the
+// columns left of them are deferred to c, after the last catch-up.
+//
+// The segment widths come from a timing model of the device (one 64 x 64 tile of
+// depth k on a CU that holds one workgroup: 0.12 us per unit of k; a panel of the
+// chain: 0.15 ms; a catch-up step: 12 us plus its GEMM at 25 TFLOP/s): each
+// segment is the widest whose product and catch-up end before the panels reach
+// it, so that the chain never waits; a wrong model costs time, never correctness.
+// ---------------------------------------------------------------------------
+#define SP_MAXB (BM_PIPE_MAX_N / LU_NB)
+#define SP_MAXSEG 24
+
+struct bm_lu_pipe {
+  hipStream_t g, c;
+  hipEvent_t e_in, e_cdone, ep[SP_MAXB], es[SP_MAXSEG], ec[SP_MAXSEG];
+};
+
+static void pipe_destroy(bm_lu_pipe *q) {
+  if (!q) return;
+  if (q->g) {
+    (void)hipStreamSynchronize(q->g);
+    (void)hipStreamDestroy(q->g);
+  }
+  if (q->c) {
+    (void)hipStreamSynchronize(q->c);
+    (void)hipStreamDestroy(q->c);
+  }
+  hipEvent_t *evs[] = {&q->e_in, &q->e_cdone};
+  for (hipEvent_t *e : evs)
+    if (*e) (void)hipEventDestroy(*e);
+  for (int i = 0; i < SP_MAXB; ++i)
+    if (q->ep[i]) (void)hipEventDestroy(q->ep[i]);
+  for (int i = 0; i < SP_MAXSEG; ++i) {
+    if (q->es[i]) (void)hipEventDestroy(q->es[i]);
+    if (q->ec[i]) (void)hipEventDestroy(q->ec[i]);
+  }
+  delete q;
+}
+
+int bm_getrf_pipe_create(bm_getrf_ws *w) {
+  if (!w) return BM_E_ARG;
+  if (w->pipe) return BM_OK;
+  bm_lu_pipe *q = new (std::nothrow) bm_lu_pipe();
+  if (!q) return BM_E_NOMEM;
+  memset((void *)q, 0, sizeof(*q));
+  const unsigned fl = hipEventDisableTiming | BM_LU_EVENT_FLAGS;
+  bool ok = hipStreamCreateWithFlags(&q->g, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&q->c, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&q->e_in, fl) == hipSuccess &&
+            hipEventCreateWithFlags(&q->e_cdone, fl) == hipSuccess;
+  for (int i = 0; ok && i < SP_MAXB; ++i) ok = hipEventCreateWithFlags(&q->ep[i], fl) == hipSuccess;
+  for (int i = 0; ok && i < SP_MAXSEG; ++i)
+    ok = hipEventCreateWithFlags(&q->es[i], fl) == hipSuccess && hipEventCreateWithFlags(&q->ec[i], fl) == hipSuccess;
+  if (!ok) {
+    pipe_destroy(q);
+    return BM_E_HIP;
+  }
+  w->pipe = q;
+  return BM_OK;
+}
+
+size_t bm_getrf_pipe_w_elems(int n) {
+  // split-K partials: block 0 over the whole device (at most 16 slices of n x 64)
+  // or one round of the bounded grid (at most 256 tiles of 64 x 64)
+  const size_t a = (size_t)16 * n * LU_NB, b = (size_t)256 * 64 * 64;
+  return a > b ? a : b;
+}
+
+struct sp_seg {
+  int b0, b1, ks;  // blocks [b0, b1), k split into ks slices
+};
+
+// k-slices of a product of `tiles` tiles on `slots` workgroups: enough to fill
+// them in one round, at most 16, each at least 256 deep (the three-multiplication
+// form), and the partials within the workspace
+static int sp_ksplit(int tiles, int slots, int k, size_t w_cap) {
+  int ks = (tiles <= slots) ? slots / tiles : 1;
+  const int kmax = (k / 256 > 1) ? k / 256 : 1;
+  if (ks > kmax) ks = kmax;
+  if (ks > 16) ks = 16;
+  while (ks > 1 && (size_t)ks * tiles * 64 * 64 > w_cap) --ks;
+  return ks < 1 ? 1 : ks;
+}
+
+static double sp_time(int tiles, int ks, int slots, int k, double per_k) {
+  int kc = (k + ks - 1) / ks;
+  kc = (kc + 15) / 16 * 16;
+  const int rounds = (tiles * ks + slots - 1) / slots;
+  return rounds * per_k * kc + (ks > 1 ? 0.006 : 0.0);
+}
+
+// Returns 1 when the planned product ends before the chain of panels (the overlap
+// pays), else 0 (then the product is better formed in full first).
+static int sp_plan(int n, int k, int ncu, int gs, size_t w_cap, sp_seg *seg, int *nseg_out) {
+  const int B = (n + LU_NB - 1) / LU_NB, tb = B;  // blocks; row tiles of a block
+  const double per_k1 = 0.49 / 4096.0;            // ms per unit of k: one workgroup per CU
+  const double per_k2 = 0.84 / 4096.0;            // two per CU (block 0, whole device)
+  const double beta = 0.15 + 0.05 * ((n > 2048) ? (n - 2048) / 2048.0 : 0.0), margin = 0.03;
+  int nseg = 0;
+  const int ks0 = sp_ksplit(tb, 2 * ncu, k, w_cap);
+  const double t0 = sp_time(tb, ks0, 2 * ncu, k, per_k2);
+  seg[nseg++] = {0, 1, ks0};
+  double E = t0;
+  int f = 1;
+  while (f < B) {
+    int best = 1, bks = sp_ksplit(tb, gs, k, w_cap);
+    double bt = sp_time(tb, bks, gs, k, per_k1);
+    for (int b = 2; b <= B - f; ++b) {
+      const int ks = sp_ksplit(tb * b, gs, k, w_cap);
+      const double t = sp_time(tb * b, ks, gs, k, per_k1), fin = E + t;
+      int a = (int)((fin - t0) / beta);
+      if (a > f - 1) a = f - 1;
+      if (a < 0) a = 0;
+      const double step = 0.012 + 8.0 * n * (64.0 * b) * 64.0 / 25e9;
+      if (fin + a * step <= t0 + beta * f - margin) {
+        best = b;
+        bks = ks;
+        bt = t;
+      }
+    }
+    if (nseg == SP_MAXSEG - 1) {  // the last segment takes the rest
+      best = B - f;
+      bks = sp_ksplit(tb * best, gs, k, w_cap);
+      bt = sp_time(tb * best, bks, gs, k, per_k1);
+    }
+    seg[nseg++] = {f, f + best, bks};
+    E += bt;
+    f += best;
+  }
+  *nseg_out = nseg;
+  return (E <= t0 + beta * B - margin) ? 1 : 0;
+}
+
+int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_t ldbot, const cplx *top,
+                       int64_t ldtop, int k, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                       cplx *W, size_t w_elems, int *nseg_out) {
+  if (!w || w->n < n || n < 1 || n > BM_PIPE_MAX_N || !w->aux || !w->pipe || k < 1 || !W || !nseg_out ||
+      w_elems < bm_getrf_pipe_w_elems(n))
+    return BM_E_ARG;
+  *nseg_out = 0;
+  bm_lu_pipe *q = w->pipe;
+  int shape[3 * SP_MAXB];
+  int ncu = 0;
+  if (int rc0 = lu_begin(s, n, dev_err, w, shape, &ncu)) return rc0;
+  const int B = (n + LU_NB - 1) / LU_NB;
+  int pmax = 0;
+  for (int pi = 0; pi < B; ++pi) pmax = (shape[3 * pi + 1] > pmax) ? shape[3 * pi + 1] : pmax;
+  const int gs = ncu - pmax;  // the product's workgroups: one per CU, the panel's CUs left free
+  if (gs < 1) return BM_E_ARG;
+  sp_seg seg[SP_MAXSEG];
+  int nseg = 0;
+  bm_problem *ps = w->prof_schur;
+  if (!sp_plan(n, k, ncu, gs, w_elems, seg, &nseg)) {
+    // the product would not keep ahead of the panels: form it in full first
+    if (ps) bm_phase_begin_on(ps, BM_PH_SCHUR, s);
+    if (int rc0 = bm_launch_zgemm(s, n, n, k, alpha, bot, ldbot, top, ldtop, cmk(0.0, 0.0), A, lda)) return rc0;
+    if (ps) bm_phase_end_on(ps, BM_PH_SCHUR, s);
+    return bm_getrf_run(s, n, A, lda, ipiv, dev_err, w, 0);
+  }
+  *nseg_out = nseg;
+  const long ldal = (long)lda;
+  auto cols = [&](int i, int *c0, int *c1) {
+    *c0 = seg[i].b0 * LU_NB;
+    *c1 = (seg[i].b1 * LU_NB < n) ? seg[i].b1 * LU_NB : n;
+  };
+  // block 0 over the whole device, then the other segments on g (the product's
+  // span, from block 0's start on s to the last segment's end on g, is timed)
+  if (ps) bm_phase_begin_on(ps, BM_PH_SCHUR, s);
+  {
+    int c0, c1;
+    cols(0, &c0, &c1);
+    if (int rc0 = bm_launch_zgemm_persist(s, n, c1 - c0, k, alpha, bot, ldbot, top, ldtop, A, lda, 2 * ncu,
+                                          seg[0].ks, W, w_elems, 0))
+      return rc0;
+  }
+  BM_HIP_TRY(hipEventRecord(q->e_in, s));
+  BM_HIP_TRY(hipStreamWaitEvent(q->g, q->e_in, 0));
+  for (int i = 1; i < nseg; ++i) {
+    int c0, c1;
+    cols(i, &c0, &c1);
+    if (int rc0 = bm_launch_zgemm_persist(q->g, n, c1 - c0, k, alpha, bot, ldbot, top + (long)c0 * ldtop, ldtop,
+                                          A + (long)c0 * lda, lda, gs, seg[i].ks, W, w_elems, 1))
+      return rc0;
+    BM_HIP_TRY(hipEventRecord(q->es[i], q->g));
+  }
+  if (ps) bm_phase_end_on(ps, BM_PH_SCHUR, nseg > 1 ? q->g : s);
+  // the catch-up stream's work, in order: per segment its product, the updates of
+  // panels 0 .. f - 2, its completion event; then the deferred left interchanges
+  // of panels 1 .. B - 1.  Items are issued once their panel has been issued.
+  struct item {
+    int type, i, p;  // 0: wait for segment i's product, 1: catch-up step, 2: record, 3: left interchanges
+  };
+  item items[SP_MAXSEG * (SP_MAXB + 2) + SP_MAXB];
+  int nit = 0;
+  for (int i = 1; i < nseg; ++i) {
+    items[nit++] = {0, i, -1};
+    for (int p = 0; p <= seg[i].b0 - 2; ++p) items[nit++] = {1, i, p};
+    items[nit++] = {2, i, -1};
+  }
+  for (int p = 1; p < B; ++p) items[nit++] = {3, 0, p};
+  int next_item = 0;
+  auto issue = [&](int h) -> int {
+    while (next_item < nit && items[next_item].p <= h) {
+      const item it = items[next_item++];
+      if (it.type == 0) {
+        BM_HIP_TRY(hipStreamWaitEvent(q->c, q->es[it.i], 0));
+      } else if (it.type == 2) {
+        BM_HIP_TRY(hipEventRecord(q->ec[it.i], q->c));
+      } else {
+        const int j = it.p * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
+        const int32_t *swp = w->swp + (size_t)it.p * SWP_STRIDE;
+        BM_HIP_TRY(hipStreamWaitEvent(q->c, q->ep[it.p], 0));
+        if (it.type == 1) {
+          int c0, c1;
+          cols(it.i, &c0, &c1);
+          if (int rc0 = lu_update(q->c, A, ldal, n, j, jb, swp, 0, c0, c1, false, 0)) return rc0;
+        } else {
+          // the L columns of panels < p are read by the updates of their own
+          // panels, the last of which (p - 1, on aux) is behind e_rest
+          BM_HIP_TRY(hipStreamWaitEvent(q->c, w->e_rest, 0));
+          if (int rc0 = lu_update(q->c, A, ldal, n, j, jb, swp, j, 0, 0, false, 0)) return rc0;
+        }
+      }
+    }
+    return BM_OK;
+  };
+  if (int rc0 = issue(-1)) return rc0;
+  for (int pi = 0; pi < B; ++pi) {
+    const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
+    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi)) return rc;
+    BM_HIP_TRY(hipEventRecord(q->ep[pi], s));
+    if (int rc = issue(pi)) return rc;
+    const int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
+    const int nr = n - j - jb;
+    const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;
+    if (pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+    int hi = 0;  // end of the columns that follow the lookahead after this panel
+    for (int i = 0; i < nseg; ++i)
+      if (seg[i].b0 <= pi + 1) {
+        int c0, c1;
+        cols(i, &c0, &c1);
+        hi = c1;
+        if (i > 0 && seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(s, q->ec[i], 0));  // joins now
+      }
+    if (int rc = lu_update(s, A, ldal, n, j, jb, swp, 0, jn, jn + jbn, true, 0)) return rc;
+    BM_HIP_TRY(hipEventRecord(w->e_next, s));
+    BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+    for (int i = 1; i < nseg; ++i)
+      if (seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(w->aux, q->ec[i], 0));
+    if (int rc = lu_update(w->aux, A, ldal, n, j, jb, swp, 0, jn + jbn, hi, false, 0)) return rc;
+    BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
+  }
+  if (int rc = issue(B)) return rc;
+  if (next_item != nit) return BM_E_ARG;  // (every item's panel exists)
+  BM_HIP_TRY(hipEventRecord(q->e_cdone, q->c));
+  BM_HIP_TRY(hipStreamWaitEvent(s, q->e_cdone, 0));
+  BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
   return BM_OK;
 }
 

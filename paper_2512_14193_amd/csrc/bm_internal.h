@@ -76,6 +76,8 @@ struct bm_getrf_ws {
   hipStream_t aux;     // second stream: the trailing update of panel k runs beside panel k + 1
   hipEvent_t e_next, e_rest;
   struct bm_problem *prof;  // non-null: time each panel launch in that problem's BM_PH_PANEL phase
+  struct bm_problem *prof_schur;  // non-null: the segmented product's span in its BM_PH_SCHUR phase
+  struct bm_lu_pipe *pipe;  // streams and events of the LU with the Schur complement beside it (or null)
 };
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {
@@ -197,6 +199,10 @@ struct bm_problem {
   double ir_relres;     // its final max_j ||b_j - A x_j|| / ||b_j||
   cplx *ir_r, *ir_d;    // mixed: 3N x BM_MAX_NRHS residual and correction
   double *ir_norm;      // device: per column ||r_j||^2, ||b_j||^2
+  cplx *pipe_w;         // device: split-K partials of the Schur complement beside the LU (or null)
+  size_t pipe_w_elems;
+  int pipeline;         // 1: U33 formed beside its factorisation (mixed form, FP64)
+  int lu_segments;      // column segments of the latest factorisation's product (0: formed in full)
 
   int profiling;
   hipEvent_t ev[BM_NPHASE][BM_EV_RING][2];
@@ -214,6 +220,12 @@ int bm_launch_far_field(bm_problem *p, int nrhs, const cplx *X, int64_t ldx, int
                         cplx *F, int64_t ldf);
 int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
                     const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
+// Deep product C = alpha A B (beta = 0) on a bounded grid of `grid` persistent
+// workgroups (one per CU with one_per_cu), k split into ksplit slices summed
+// through W (at least ksplit m n complex values when ksplit > 1)
+int bm_launch_zgemm_persist(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
+                            const cplx *B, int64_t ldb, cplx *C, int64_t ldc, int grid, int ksplit, cplx *W,
+                            size_t w_elems, int one_per_cu);
 // the same product on the FP32 matrix cores (operands rounded to complex64, FP32 accumulation)
 int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
                       const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
@@ -262,10 +274,22 @@ int bm_launch_fds_targets(hipStream_t s, const bm_problem *p, int nitems, const 
 bm_getrf_ws *bm_getrf_ws_create(int n);
 void bm_getrf_ws_destroy(bm_getrf_ws *w);
 size_t bm_getrf_ws_bytes(int n);  // device bytes bm_getrf_ws_create(n) allocates
+// LU of A = alpha Bot Top (n x n; Bot n x k, Top k x n) with the product computed
+// in column segments beside the panel factorisation (FP64, n <= BM_PIPE_MAX_N);
+// W: split-K workspace of bm_getrf_pipe_w_elems(n) complex values
+#define BM_PIPE_MAX_N 4096
+size_t bm_getrf_pipe_w_elems(int n);
+int bm_getrf_pipe_create(bm_getrf_ws *w);  // the extra streams and events (once)
+// (*nseg: the segments used, 0 when the model chose to form the product first)
+int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_t ldbot, const cplx *top,
+                       int64_t ldtop, int k, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                       cplx *W, size_t w_elems, int *nseg);
 int bm_getrf_prepare();           // kernel attributes on the current device (outside any capture)
 // phase timing (bm_set_profiling): an event pair around the work enqueued between the calls
 void bm_phase_begin(struct bm_problem *p, int ph);
 void bm_phase_end(struct bm_problem *p, int ph);
+void bm_phase_begin_on(struct bm_problem *p, int ph, hipStream_t st);
+void bm_phase_end_on(struct bm_problem *p, int ph, hipStream_t st);
 // parameter checks of bm_assemble (BM_OK or BM_E_ARG)
 int bm_check_params(const bm_params *prm);
 // Fill n 8-byte words at p with v on stream s (a kernel, so that the sequence stays

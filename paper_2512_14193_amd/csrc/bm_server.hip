@@ -181,6 +181,9 @@ int acquire(bm_server *s, const bm_request &r, int lane, srv_handle **out) {
     rc = bm_set_quadrature(h->p, s->quad);
     if (rc) bm_destroy(h->p);
   }
+  // served factorisations form U33 first: the segmented product holds most CUs
+  // for its whole length, which requests overlapping on other lanes would share
+  if (!rc) (void)bm_set_lu_overlap(h->p, 0);
   if (rc) {
     delete h;
     return rc;

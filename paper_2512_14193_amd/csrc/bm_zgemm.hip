@@ -201,6 +201,102 @@ __global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k,
   zgemm_tile<BETA0, M3>(blockIdx.x, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
 }
 
+// Persistent form of the deep product (beta = 0), for the Schur complement
+// computed beside the panel factorisation: a bounded grid walks the work items
+// (tile, k-slice), so the CUs it does not hold stay free for the panels; the
+// dynamic LDS of the launch (unused) limits how many of its workgroups share a CU.
+// With ksplit > 1, item (tile, s) writes the partial product of k-slice s
+// (kc deep) to W + s m n (ld m), summed into C by zgemm_splitk_reduce.
+template <bool M3>
+__global__ __launch_bounds__(256, GM_OCC) void zgemm_persist_kernel(int m, int n, int k, cplx alpha,
+                                                                    const cplx *__restrict__ A, long lda,
+                                                                    const cplx *__restrict__ B, long ldb,
+                                                                    cplx *__restrict__ C, long ldc, int tiles_m,
+                                                                    int ntiles, int ksplit, int kc,
+                                                                    cplx *__restrict__ W) {
+  const cplx zero = cmk(0.0, 0.0), one = cmk(1.0, 0.0);
+  const int items = ntiles * ksplit;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int tile = item % ntiles, sl = item / ntiles;
+    if (ksplit == 1) {
+      zgemm_tile<true, M3>(tile, m, n, k, alpha, A, lda, B, ldb, zero, C, ldc, tiles_m);
+    } else {
+      const int k0 = sl * kc, kk = (k - k0 < kc) ? k - k0 : kc;
+      zgemm_tile<true, M3>(tile, m, n, kk, one, A + (long)k0 * lda, lda, B + k0, ldb, zero, W + (long)sl * m * n, m,
+                           tiles_m);
+    }
+  }
+}
+
+#define GM_PERSIST_PAD (16 << 10)  // 66 KB static + 16 KB: a second workgroup does not fit in 160 KB
+
+// C = alpha sum_s W_s, the k-slices summed in order (deterministic)
+__global__ __launch_bounds__(256) void zgemm_splitk_reduce(int m, int n, int ksplit, cplx alpha,
+                                                           const cplx *__restrict__ W, cplx *__restrict__ C,
+                                                           long ldc) {
+  const long mn = (long)m * n;
+  for (long idx = blockIdx.x * 256L + threadIdx.x; idx < mn; idx += (long)gridDim.x * 256) {
+    st_v2 acc = st_ld(W, idx);
+    for (int sl = 1; sl < ksplit; ++sl) {
+      const st_v2 v = st_ld(W, sl * mn + idx);
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    const long i = idx % m, j = idx / m;
+    C[i + j * ldc] = cmul(alpha, cmk(acc.x, acc.y));
+  }
+}
+
+int bm_launch_zgemm_persist(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
+                            const cplx *B, int64_t ldb, cplx *C, int64_t ldc, int grid, int ksplit, cplx *W,
+                            size_t w_elems, int one_per_cu) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  if (k <= 0 || grid <= 0 || ksplit < 1 || ksplit > 64) return BM_E_ARG;
+  const int tm = (m + GM_BM - 1) / GM_BM, tn = (n + GM_BN - 1) / GM_BN;
+  const long tiles = (long)tm * tn;
+  if (tiles * ksplit > 0x7fffffffL) return BM_E_ARG;
+  // k-slices: multiples of the stage depth, every slice non-empty
+  int kc = (k + ksplit - 1) / ksplit;
+  kc = (kc + GM_BK3 - 1) / GM_BK3 * GM_BK3;
+  const int ks = (k + kc - 1) / kc;
+  if (ks > 1 && (!W || w_elems < (size_t)ks * m * n)) return BM_E_ARG;
+  const bool m3 = (ks > 1 ? kc : k) >= GM_3M_MIN_K;
+  const int items = (int)(tiles * ks);
+  const unsigned g = (unsigned)((grid < items) ? grid : items);
+  // one workgroup per CU: dynamic LDS that, with the 66 KB of the kernel, leaves
+  // no room for a second one
+  const size_t dyn = one_per_cu ? (size_t)GM_PERSIST_PAD : 0;
+  if (one_per_cu) {
+    static int attr_done[64];
+    int dev = 0;
+    BM_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return BM_E_ARG;
+    if (!attr_done[dev]) {
+      BM_HIP_TRY(hipFuncSetAttribute((const void *)zgemm_persist_kernel<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, GM_PERSIST_PAD));
+      BM_HIP_TRY(hipFuncSetAttribute((const void *)zgemm_persist_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, GM_PERSIST_PAD));
+      attr_done[dev] = 1;
+    }
+  }
+  if (m3)
+    hipLaunchKernelGGL((zgemm_persist_kernel<true>), dim3(g), dim3(256), dyn, s, m, n, k, alpha, A, (long)lda, B,
+                       (long)ldb, C, (long)ldc, tm, (int)tiles, ks, kc, W);
+  else
+    hipLaunchKernelGGL((zgemm_persist_kernel<false>), dim3(g), dim3(256), dyn, s, m, n, k, alpha, A, (long)lda, B,
+                       (long)ldb, C, (long)ldc, tm, (int)tiles, ks, kc, W);
+  BM_HIP_TRY(hipGetLastError());
+  if (ks > 1) {
+    const long mn = (long)m * n;
+    long rb = (mn + 255) / 256;
+    if (rb > g) rb = g;  // no more workgroups than the product's own grid
+    hipLaunchKernelGGL(zgemm_splitk_reduce, dim3((unsigned)rb), dim3(256), 0, s, m, n, ks, alpha, (const cplx *)W, C,
+                       (long)ldc);
+    BM_HIP_TRY(hipGetLastError());
+  }
+  return BM_OK;
+}
+
 // Batched products: descriptor blockIdx.y, its tiles on blockIdx.x (a launch covers
 // the largest product; workgroups beyond a smaller product's tiles return).
 __global__ __launch_bounds__(256, GM_OCC) void zgemm_batched_kernel(const bm_gemm_desc *d) {

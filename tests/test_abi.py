@@ -37,9 +37,12 @@ def test_problem_bytes_without_device():
     # host arithmetic only: the sum of bm_create's allocations
     b = {n: binding.problem_bytes(n) for n in (512, 1024, 2048, 4096)}
     for n, v in b.items():
-        # blocks and U33 (80 N^2 bytes), O(N) vectors, the exchange buffers (34 MB)
-        # and the split-K partials of the solve (at most 1024 x 256 rows x 32 columns)
-        assert 80 * n * n < v < 80 * n * n + 4096 * n + 200 * 2 ** 20, (n, v)
+        # blocks and U33 (80 N^2 bytes), O(N) vectors, the exchange buffers (34 MB),
+        # the split-K partials of the solve (at most 1024 x 256 rows x 32 columns)
+        # and those of the Schur complement beside the LU (16 slices of N x 64)
+        assert 80 * n * n < v < 80 * n * n + (4096 + 16 * 64 * 16) * n + 200 * 2 ** 20, (n, v)
+    # the Schur partials only where the segmented product is available (N <= 4096)
+    assert binding.problem_bytes(4098) - binding.problem_bytes(4096) < 80 * (4098 ** 2 - 4096 ** 2) + 2 ** 20
     assert binding.problem_bytes(512, "ordinary") < b[512]
     lib = binding.lib()
     out = ctypes.c_int64(0)
