@@ -20,7 +20,10 @@
 //  3. trailing update A22 -= L21 U12 with the MFMA GEMM.
 //  Steps 2 and 3 run first for the next panel's columns only; for all other
 //  columns they run on a second stream while the next panel is factored
-//  (lookahead of depth one).
+//  (lookahead of depth one).  A panel of 64 rows per workgroup and at least 10
+//  workgroups does steps 2 and 3 for its own columns itself, before its chain
+//  starts (the fused form of panel_kernel), saving two launches per panel on the
+//  critical path.
 //
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
@@ -61,7 +64,10 @@
 // side (16 bytes each: one poll instruction of the chain reads P / 8 cache lines).
 #define SLOT_REC_ELEMS ((size_t)LU_NB * (PANEL_PMAX * (LU_NB + 1) + LU_NB))
 #define SLOT_HDR ((int)SLOT_REC_ELEMS)  // header of column c, workgroup g: SLOT_HDR + c P + g
-#define SLOT_ELEMS (SLOT_REC_ELEMS + (size_t)LU_NB * PANEL_PMAX)  // complex values per slot buffer
+// after the headers, the U12 block (LU_NB x LU_NB, column-major) of a panel that
+// applies the previous panel's update to its own columns (the fused form below)
+#define SLOT_U12 ((int)(SLOT_REC_ELEMS + (size_t)LU_NB * PANEL_PMAX))
+#define SLOT_ELEMS ((size_t)SLOT_U12 + (size_t)LU_NB * LU_NB)  // complex values per slot buffer
 
 // 16-byte agent-coherent loads and stores of the exchange records: buffer
 // instructions with the sc1 cache-policy bit (agent scope on gfx94x / gfx950).
@@ -187,10 +193,28 @@ __device__ inline cplx pivot_recip(cplx u) {
 //   slots[c * cstride + g * rs]  record of workgroup g: (value, row), then the row
 //   slots[c * cstride + P * rs]  the diagonal row j + c, by its owner
 //   slots[SLOT_HDR + c * P + g]  the header (value, row) of workgroup g when packed
-template <int RPL>
+typedef double pdbl4 __attribute__((ext_vector_type(4)));
+__device__ inline pdbl4 pmfma16(double a, double b, pdbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// FUSE: the panel first applies the previous panel's update to its own columns
+// (what the separate interchange/TRSM and k = 64 update launches do otherwise):
+// the previous panel (columns j0 .. j0 + 63, interchange list swp0) gives
+//   U12 = L11^{-1} (its interchanged rows j0 .. j0 + 63 of these columns),
+//   each row r >= j:  a_r = (row sigma(r) of these columns) - L(r, j0..) U12,
+// sigma the interchanges' row sources.  Every workgroup solves the columns
+// c = g (mod P) of U12 (lane = row, one column per wavefront) and publishes them
+// in the slot buffer's U12 block with the exchange protocol (agent-scope stores
+// over the empty pattern, polled by the readers); every workgroup then reads all
+// of U12 and forms its rows' update on the FP64 matrix cores.  Rows j0 .. j0 + 63
+// of these columns (U12 itself) are written back by workgroup 0 at the end, when
+// every workgroup has long finished reading the old values (it has published its
+// candidate of column 0, which workgroup 0 waited for).  RPL = 1 and P >= 10 only.
+template <int RPL, bool FUSE>
 __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
                                                     int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
-                                                    int next_jb, int32_t *swp) {
+                                                    int next_jb, int32_t *swp, int j0, const int32_t *swp0) {
   constexpr int RPW = 64 * RPL;  // rows per workgroup
   constexpr int LDP = RPW + 1;   // column stride of the LDS panel (odd: conflict-free row reads)
   extern __shared__ cplx pan[];  // jb x LDP
@@ -210,7 +234,151 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
   const int nv = (N - r0 >= RPW) ? RPW : ((N - r0 > 0) ? (int)(N - r0) : 0);
   bool ok = true;
 
-  {
+  if constexpr (FUSE) {
+    static_assert(RPL == 1, "the fused update holds U12 beside a 64-row panel");
+    constexpr int UOFF = LU_NB * (64 + 1);  // U12 in LDS after the panel block
+    cplx *Ls = pan;                         // L11, then this workgroup's rows of L21 (ld 64)
+    cplx *Us = pan + UOFF;                  // all of U12 (ld 64)
+    __shared__ int s_src[64], s_srcx[64];   // row sources of rows r0 + i and j0 + i
+    if (tid < 64) {
+      s_src[tid] = (int)r0 + tid;
+      s_srcx[tid] = j0 + tid;
+    }
+    __syncthreads();
+    {
+      const int np = swp0[0];
+      for (int e = tid; e < np; e += SNT) {
+        const int dst = swp0[1 + 2 * e], src = swp0[2 + 2 * e];
+        if (dst >= r0 && dst < r0 + 64) s_src[dst - r0] = src;
+        if (dst >= j0 && dst < j0 + 64) s_srcx[dst - j0] = src;
+      }
+    }
+    // L11 of the previous panel into LDS; each wavefront's column of U12 (its
+    // interchanged rows j0 .. j0 + 63) into registers
+    for (int idx = tid; idx < LU_NB * LU_NB; idx += SNT) {
+      const int r = idx & 63, c = idx >> 6;
+      st_st(Ls, idx, st_ld(A, (long)(j0 + r) + (long)(j0 + c) * lda));
+    }
+    __syncthreads();
+    const int cown = g + P * wave;  // this wavefront's column of U12
+    if (wave < SNT / 64 && cown < jb) {
+      cplx x = A[(long)s_srcx[lane] + (long)(j + cown) * lda];
+      for (int c0 = 0; c0 < LU_NB - 1; c0 += 8) {
+        cplx lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + u;
+          lv[u] = (c < LU_NB - 1 && lane > c) ? Ls[c * 64 + lane] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + u;
+          if (c < LU_NB - 1) x = cfms(x, lv[u], readlane_c(x, c));
+        }
+      }
+      rec_store(rs, SLOT_U12 + cown * 64 + lane, x);
+    }
+    // (columns c = g + P w, w < 7 wavefronts: all of jb <= 64 are covered when P >= 10)
+    __syncthreads();  // every wavefront done with L11
+    // all of U12 (every load in flight, then polled until written), and this
+    // workgroup's rows of L21, into LDS
+    {
+      constexpr int UPT = (LU_NB * LU_NB + SNT - 1) / SNT;
+      bm_v4i uv[UPT];
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) {
+        const int idx = tid + SNT * q;
+        if (idx < LU_NB * jb) uv[q] = rec_load(rs, SLOT_U12 + idx);
+      }
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) {
+        const int idx = tid + SNT * q;
+        if (idx < LU_NB * LU_NB) {
+          const int r = idx & 63, kc = idx >> 6;  // L21: row r, column kc of the previous panel
+          st_st(Ls, kc * 64 + r, (r < nv) ? st_ld(A, (r0 + r) + (long)(j0 + kc) * lda) : st_v2{0.0, 0.0});
+        }
+      }
+      const unsigned long long t0 = wall_clock64();
+      for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < UPT; ++q) {
+          const int idx = tid + SNT * q;
+          if (idx < LU_NB * jb && rec_empty(uv[q])) {
+            all = false;
+            uv[q] = rec_load(rs, SLOT_U12 + idx);
+          }
+        }
+        if (all) break;
+        if (!ok || wait_expired(t0)) {
+          if (ok) atomicOr(dev_err, 1);
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) {
+        const int idx = tid + SNT * q;
+        if (idx < LU_NB * LU_NB) Us[idx] = (idx < LU_NB * jb) ? rec_value(uv[q]) : cmk(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    // this workgroup's rows: (row sigma(r) of these columns) - L21 U12; wavefronts
+    // 0 .. 3 each own a 32 x 32 quarter (2 x 2 blocks of 16 x 16 MFMA results:
+    // lane l, register q -> row l % 16, column 4 q + l / 16 of a block)
+    pdbl4 accr[2][2], acci[2][2];
+    const int wm = wave & 1, wn = (wave >> 1) & 1, fq = lane >> 4, fi = lane & 15;
+    if (wave < 4) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accr[a][b] = (pdbl4){0, 0, 0, 0};
+          acci[a][b] = (pdbl4){0, 0, 0, 0};
+        }
+      for (int k4 = 0; k4 < LU_NB; k4 += 4) {
+        cplx av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = Ls[(k4 + fq) * 64 + wm * 32 + a * 16 + fi];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Us[(wn * 32 + b * 16 + fi) * 64 + k4 + fq];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            accr[a][b] = pmfma16(bv[b].x, av[a].x, accr[a][b]);
+            acci[a][b] = pmfma16(bv[b].y, av[a].x, acci[a][b]);
+            accr[a][b] = pmfma16(bv[b].y, -av[a].y, accr[a][b]);
+            acci[a][b] = pmfma16(bv[b].x, av[a].y, acci[a][b]);
+          }
+      }
+    }
+    __syncthreads();  // L21 read by every wavefront before the panel block overwrites it
+    if (wave < 4) {
+      st_v2 old[2][2][4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = wm * 32 + a * 16 + fi, c = wn * 32 + b * 16 + 4 * q + fq;
+            old[a][b][q] = st_ld(A, (r < nv && c < jb) ? (long)s_src[r] + (long)(j + c) * lda : (long)j + (long)j * lda);
+          }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = wm * 32 + a * 16 + fi, c = wn * 32 + b * 16 + 4 * q + fq;
+            if (c < jb)
+              st_st(pan, c * LDP + r,
+                    (r < nv) ? st_v2{old[a][b][q].x - accr[a][b][q], old[a][b][q].y - acci[a][b][q]} : st_v2{0.0, 0.0});
+          }
+    }
+  } else {
     // the workgroup's block of the panel into LDS: each thread's loads in one
     // batch (unconditional, an item outside the block reads the panel's first
     // element), then the LDS stores
@@ -585,6 +753,17 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       ns[2 * (size_t)el + 1] = SENT;
     }
     for (int idx = g * SNT + tid; idx < 2 * next_jb * next_P; idx += P * SNT) ns[2 * (size_t)SLOT_HDR + idx] = SENT;
+    for (int idx = g * SNT + tid; idx < 2 * LU_NB * LU_NB; idx += P * SNT) ns[2 * (size_t)SLOT_U12 + idx] = SENT;
+  }
+  if constexpr (FUSE) {
+    // U12: rows j0 .. j0 + 63 of this panel's columns
+    if (g == 0) {
+      const cplx *Us = pan + LU_NB * (64 + 1);
+      for (int idx = tid; idx < LU_NB * jb; idx += SNT) {
+        const int k = idx & 63, cc = idx >> 6;
+        A[(long)(j0 + k) + (long)(j + cc) * lda] = Us[cc * 64 + k];
+      }
+    }
   }
 }
 
@@ -778,8 +957,9 @@ __global__ void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv);
 #define TI_LDS ((size_t)(2 * TI_N * (TI_N + 1) + 1024) * sizeof(cplx))  // M, X, T of tri_inv64
 
 typedef void (*panel_fn)(int, cplx *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int,
-                         int32_t *);
-static const panel_fn panel_fns[2] = {panel_kernel<1>, panel_kernel<2>};
+                         int32_t *, int, const int32_t *);
+// 64 and 128 rows per workgroup; 64 rows with the previous panel's update fused
+static const panel_fn panel_fns[3] = {panel_kernel<1, false>, panel_kernel<2, false>, panel_kernel<1, true>};
 
 static int panel_attr_done[64];
 
@@ -824,7 +1004,7 @@ int bm_getrf_prepare() {
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 3; ++k)
       BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)PANEL_LDS_ALLOC));
     BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel<ST_CW_NEXT>,
@@ -897,6 +1077,13 @@ static int lu_begin(hipStream_t s, int n, int32_t *dev_err, bm_getrf_ws *w, int 
 // launch avoids the start and drain cost of a cooperative launch.  Every wait in
 // the kernel is bounded, so a launch whose workgroups cannot all become resident
 // ends with BM_E_DEVICE, not a hang.)
+// whether panel pi applies the previous panel's update to its own columns itself
+// (64 rows per workgroup, enough workgroups to solve U12 one column per wavefront)
+static bool lu_fused(int n, const int *shape, int pi) {
+  (void)n;
+  return pi >= 1 && shape[3 * pi] == 1 && shape[3 * pi + 1] >= 10;
+}
+
 static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
                     const int *shape, int pi) {
   const int npanel = (n + LU_NB - 1) / LU_NB;
@@ -911,10 +1098,14 @@ static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, i
   int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
   long ldal = (long)lda;
   int nn = n, jj = j, jbb = jb;
-  void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp};
+  const bool fuse = lu_fused(n, shape, pi);
+  int j0 = fuse ? j - LU_NB : 0;
+  const int32_t *swp0 = fuse ? w->swp + (size_t)(pi - 1) * SWP_STRIDE : swp;
+  void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp, &j0, &swp0};
   const int rpl = shape[3 * pi];
   if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
-  BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
+  BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[fuse ? 2 : rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC,
+                             s));
   if (w->prof) bm_phase_end(w->prof, BM_PH_PANEL);
   return BM_OK;
 }
@@ -939,7 +1130,10 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
     if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
-    int rc = lu_update(s, A, (long)lda, n, j, jb, swp, 0, jn, jn + jbn, true, gemm32);
+    // (a fused next panel applies this update to its own columns)
+    int rc = (pi + 1 < npanel && lu_fused(n, shape, pi + 1))
+                 ? BM_OK
+                 : lu_update(s, A, (long)lda, n, j, jb, swp, 0, jn, jn + jbn, true, gemm32);
     if (rc) return rc;
     if (la) {
       BM_HIP_TRY(hipEventRecord(w->e_next, s));
@@ -1211,7 +1405,8 @@ int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_
         hi = c1;
         if (i > 0 && seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(s, q->ec[i], 0));  // joins now
       }
-    if (int rc = lu_update(s, A, ldal, n, j, jb, swp, 0, jn, jn + jbn, true, 0)) return rc;
+    if (!(pi + 1 < B && lu_fused(n, shape, pi + 1)))
+      if (int rc = lu_update(s, A, ldal, n, j, jb, swp, 0, jn, jn + jbn, true, 0)) return rc;
     BM_HIP_TRY(hipEventRecord(w->e_next, s));
     BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
     for (int i = 1; i < nseg; ++i)
