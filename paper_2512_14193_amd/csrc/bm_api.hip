@@ -124,11 +124,9 @@ int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out
   p->ir_tol = 1e-12;
   p->ir_maxit = 10;
   if (ok) p->gws = bm_getrf_ws_create(p->nf);
-  // the Schur complement beside the LU (mixed form, FP64, N <= BM_PIPE_MAX_N)
-  if (ok && p->gws && p->pipe_w) {
-    ok = bm_getrf_pipe_create(p->gws) == BM_OK;
-    p->pipeline = ok ? 1 : 0;
-  }
+  // the Schur complement beside the LU (mixed form, FP64, N <= BM_PIPE_MAX_N); its
+  // two extra streams are created by the first factorisation that uses them
+  if (ok && p->gws && p->pipe_w) p->pipeline = 1;
   if (!ok || !p->gws) {
     free_problem(p);
     return BM_E_NOMEM;
@@ -257,6 +255,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   const int n = p->n, nf = p->nf;
   int rc = BM_OK;
   if (p->form == BM_MIXED && p->prec == BM_PREC_FP64 && p->pipeline) {
+    if (int rc0 = bm_getrf_pipe_create(p->gws)) return rc0;
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23], formed in
     // column segments beside the factorisation of the columns already formed
     phase_begin(p, BM_PH_LU);
@@ -423,7 +422,7 @@ int bm_set_quadrature(bm_problem *p, int32_t quadrature) {
 
 int bm_set_lu_overlap(bm_problem *p, int32_t on) {
   if (!p || (on != 0 && on != 1)) return BM_E_ARG;
-  if (on && (!p->pipe_w || !p->gws || !p->gws->pipe)) return BM_E_ARG;
+  if (on && (!p->pipe_w || !p->gws)) return BM_E_ARG;
   p->pipeline = on;
   return BM_OK;
 }

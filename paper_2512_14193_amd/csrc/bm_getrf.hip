@@ -20,10 +20,9 @@
 //  3. trailing update A22 -= L21 U12 with the MFMA GEMM.
 //  Steps 2 and 3 run first for the next panel's columns only; for all other
 //  columns they run on a second stream while the next panel is factored
-//  (lookahead of depth one).  A panel of 64 rows per workgroup and at least 10
-//  workgroups does steps 2 and 3 for its own columns itself, before its chain
-//  starts (the fused form of panel_kernel), saving two launches per panel on the
-//  critical path.
+//  (lookahead of depth one).  Beside the Schur product (below), a panel of 64
+//  rows per workgroup and at least 10 workgroups does steps 2 and 3 for its own
+//  columns itself, before its chain starts (the fused form of panel_kernel).
 //
 // Cross-workgroup data is written with agent-scope stores and read with agent-scope
 // loads, which are coherent across the XCDs' separate L2 caches.  Every wait is
@@ -1078,14 +1077,18 @@ static int lu_begin(hipStream_t s, int n, int32_t *dev_err, bm_getrf_ws *w, int 
 // the kernel is bounded, so a launch whose workgroups cannot all become resident
 // ends with BM_E_DEVICE, not a hang.)
 // whether panel pi applies the previous panel's update to its own columns itself
-// (64 rows per workgroup, enough workgroups to solve U12 one column per wavefront)
-static bool lu_fused(int n, const int *shape, int pi) {
-  (void)n;
-  return pi >= 1 && shape[3 * pi] == 1 && shape[3 * pi + 1] >= 10;
+// (64 rows per workgroup, enough workgroups to solve U12 one column per wavefront).
+// Only in the factorisation beside the Schur product, where the two separate
+// launches it replaces wait for CUs held by the product's other work; alone on
+// the device they are as fast (measured: the plain 4096 x 4096 LU 11.05 ms with
+// them, 11.15 ms fused; star2048 beside the product 6.86 ms per step with them,
+// 6.79 ms fused).
+static bool lu_fused(bool overlap, const int *shape, int pi) {
+  return overlap && pi >= 1 && shape[3 * pi] == 1 && shape[3 * pi + 1] >= 10;
 }
 
 static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
-                    const int *shape, int pi) {
+                    const int *shape, int pi, bool overlap) {
   const int npanel = (n + LU_NB - 1) / LU_NB;
   const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
   int P = shape[3 * pi + 1];
@@ -1098,7 +1101,7 @@ static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, i
   int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
   long ldal = (long)lda;
   int nn = n, jj = j, jbb = jb;
-  const bool fuse = lu_fused(n, shape, pi);
+  const bool fuse = lu_fused(overlap, shape, pi);
   int j0 = fuse ? j - LU_NB : 0;
   const int32_t *swp0 = fuse ? w->swp + (size_t)(pi - 1) * SWP_STRIDE : swp;
   void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp, &j0, &swp0};
@@ -1121,7 +1124,7 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   const bool la = w->aux != nullptr;
   for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
     const int jb = (n - j < LU_NB) ? n - j : LU_NB;
-    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi)) return rc;
+    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi, false)) return rc;
     const int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
     // Lookahead: the stream s applies the panel's interchanges and its update to the
     // next panel's columns only; the auxiliary stream applies them to every other
@@ -1130,10 +1133,7 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;  // next panel's columns [jn, jn + jbn)
     if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
-    // (a fused next panel applies this update to its own columns)
-    int rc = (pi + 1 < npanel && lu_fused(n, shape, pi + 1))
-                 ? BM_OK
-                 : lu_update(s, A, (long)lda, n, j, jb, swp, 0, jn, jn + jbn, true, gemm32);
+    int rc = lu_update(s, A, (long)lda, n, j, jb, swp, 0, jn, jn + jbn, true, gemm32);
     if (rc) return rc;
     if (la) {
       BM_HIP_TRY(hipEventRecord(w->e_next, s));
@@ -1390,7 +1390,7 @@ int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_
   if (int rc0 = issue(-1)) return rc0;
   for (int pi = 0; pi < B; ++pi) {
     const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
-    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi)) return rc;
+    if (int rc = lu_panel(s, n, A, lda, ipiv, dev_err, w, shape, pi, true)) return rc;
     BM_HIP_TRY(hipEventRecord(q->ep[pi], s));
     if (int rc = issue(pi)) return rc;
     const int32_t *swp = w->swp + (size_t)pi * SWP_STRIDE;
@@ -1405,7 +1405,8 @@ int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_
         hi = c1;
         if (i > 0 && seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(s, q->ec[i], 0));  // joins now
       }
-    if (!(pi + 1 < B && lu_fused(n, shape, pi + 1)))
+    // (a fused next panel applies this update to its own columns)
+    if (!(pi + 1 < B && lu_fused(true, shape, pi + 1)))
       if (int rc = lu_update(s, A, ldal, n, j, jb, swp, 0, jn, jn + jbn, true, 0)) return rc;
     BM_HIP_TRY(hipEventRecord(w->e_next, s));
     BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));

@@ -42,7 +42,10 @@ class Req:
 
 
 def direct(r):
+    """The request through a problem handle of its own, with the factorisation the
+    server's handles use (U33 formed in full before its LU)."""
     P = B.Problem(r.n, "mixed")
+    P.set_lu_overlap(False)
     P.assemble_device(r.geo, r.ph)
     P.block_lu(sync=False)
     X = P.solve(r.B)
