@@ -461,8 +461,9 @@ def main():
     t_panel = ph["panel_kernel_avg"] * 1e-3
     panel_step_ms = ph["panel_kernel_avg"] * len(panel_rows)
     kern = {
-        "panel": {"kernel": "panel_kernel<1> (one 64-column panel of the LU of U33; 64 dependent pivot steps, "
-                            "one cross-workgroup exchange each)",
+        "panel": {"kernel": "panel_kernel<1, fused|plain> (one 64-column panel of the LU of U33; 64 dependent "
+                            "pivot steps, one cross-workgroup exchange each; the fused form first applies the "
+                            "previous panel's update to its columns)",
                   "bound": "alu", "achieved": panel_flops_mean / t_panel / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
                   "unit": "TFLOP/s", "frac": panel_flops_mean / t_panel / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
                   "traffic": None, "avg_launch_ms": ph["panel_kernel_avg"], "launches_per_step": len(panel_rows),

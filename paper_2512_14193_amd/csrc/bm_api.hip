@@ -283,6 +283,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
         p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
     phase_end(p, BM_PH_SCHUR);
     if (rc) return rc;
+    if (p->after_schur) BM_HIP_TRY(hipEventRecord(p->after_schur, p->stream));
   }
   phase_begin(p, BM_PH_LU);
   // (mixed precision: the trailing updates beside the next panel run on the FP32

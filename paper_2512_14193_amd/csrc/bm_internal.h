@@ -203,6 +203,7 @@ struct bm_problem {
   size_t pipe_w_elems;
   int pipeline;         // 1: U33 formed beside its factorisation (mixed form, FP64)
   int lu_segments;      // column segments of the latest factorisation's product (0: formed in full)
+  hipEvent_t after_schur;  // if set: recorded on the stream once U33 is formed in full (request server)
 
   int profiling;
   hipEvent_t ev[BM_NPHASE][BM_EV_RING][2];

@@ -6,9 +6,11 @@
 // readback, two timing events) and polls the completion events of the requests
 // in flight.  Requests with N <= concurrent_max_n run side by side on different
 // lanes; a larger request is fenced on the device against every other lane (it
-// waits for the work already enqueued there, and later requests wait for it), so
-// it runs alone.  The host enqueues up to max_inflight requests per lane ahead,
-// so the device never waits for the host.
+// waits for the work already enqueued there), so that it assembles and forms its
+// Schur complement alone; later requests wait for that, not for its LU, which
+// runs beside them.  The host enqueues up to max_inflight requests per lane
+// ahead, so the device never waits for the host.  (The lanes' streams only run
+// side by side if the process has enough hardware queues: GPU_MAX_HW_QUEUES.)
 //
 // Why concurrency is limited to small problems: the panel factorisation needs
 // its P workgroups resident at once (P = ceil(rows / 64) <= 16 for N <= 1024).
@@ -284,7 +286,14 @@ int enqueue(bm_server *s, srv_request *rq) {
                                   r.nrhs, hipMemcpyDeviceToDevice, st));
       rq->res.graph = 1;
     } else {
+      // a large request holds the device alone only while it assembles and forms
+      // U33; the small requests after it start beside its LU (the panels of the
+      // lanes together stay within half the CUs, see bm_server_create)
+      const bool big = !is_small(s, r.n) && s->lanes.size() > 1;
+      if (big) h->p->after_schur = s->big_fence;
       rc = bm_block_lu(h->p, nullptr);
+      h->p->after_schur = nullptr;
+      if (big && !rc) s->big_recorded = true;
       if (!rc) rc = bm_solve(h->p, r.nrhs, r.B, r.ldb, r.X, r.ldx);
     }
     if (!rc) {
@@ -296,7 +305,7 @@ int enqueue(bm_server *s, srv_request *rq) {
   BM_HIP_TRY(hipMemcpyAsync(s->pinned + 4 * rq->slot, h->p->dev_err, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   BM_HIP_TRY(hipEventRecord(s->ev_done[rq->slot], st));
   s->lanes[rq->lane].used = true;
-  if (!is_small(s, r.n)) {
+  if (!is_small(s, r.n) && (rq->res.graph || rq->res.reused_factors)) {
     BM_HIP_TRY(hipEventRecord(s->big_fence, st));
     s->big_recorded = true;
   }
