@@ -268,6 +268,9 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
     Xs = [B.fortran_empty(3 * r.n_nodes, sw.n_rhs) for r in sw.requests]
     torch.cuda.synchronize()
 
+    def server_submit(server, r):
+        return server.submit(geos[r.contour], r.physics, Bs[r.index], Xs[r.index])
+
     def run(server, open_loop):
         tickets = []
         t0 = time.perf_counter()
@@ -276,7 +279,7 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
                 dt = t0 + r.arrival - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
-            tickets.append(server.submit(geos[r.contour], r.physics, Bs[r.index], Xs[r.index]))
+            tickets.append(server_submit(server, r))
         res = [server.wait(t) for t in tickets]
         bad = [x["status"] for x in res if x["status"] != 0]
         if bad:
@@ -332,6 +335,25 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
     torch.cuda.synchronize()
     out["bitwise_repeatable"] = all(torch.equal(Xs[i], b) for i, b in zip(sample, before))
     out["server_stats"] = srv.stats()
+    srv.close()
+    # the same sweep in mixed precision (FP32 Schur complement and trailing updates,
+    # refinement decided on the device: 2 passes, target 1e-10), against the FP64
+    # served solutions
+    fp64 = [x.clone() for x in Xs]
+    srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
+                   concurrent_max_n=concurrent_max_n, precision="mixed", refine_steps=2, refine_tol=1e-10)
+    warm(srv, lanes)
+    tickets = []
+    for r in sw.requests:
+        tickets.append(server_submit(srv, r))
+    res = [srv.wait(t) for t in tickets]
+    ok = [x for x in res if x["status"] == 0]
+    torch.cuda.synchronize()
+    rel = [float((torch.linalg.norm(Xs[i] - fp64[i], dim=0) / torch.linalg.norm(fp64[i], dim=0)).max())
+           for i, x in enumerate(res) if x["status"] == 0]
+    out["closed_loop_mixed"] = dict(summary(ok), refine_steps=2, refine_tol=1e-10,
+                                    not_converged=len(res) - len(ok),
+                                    max_rel_diff_vs_fp64=max(rel) if rel else None)
     srv.close()
     return out
 

@@ -78,8 +78,10 @@ enum bm_status {
 
 enum bm_precision {
   BM_PREC_FP64 = 0,  /* FP64 throughout (default)                                   */
-  BM_PREC_MIXED = 1  /* Schur complement on the FP32 matrix cores, FP64 iterative
+  BM_PREC_MIXED = 1, /* Schur complement on the FP32 matrix cores, FP64 iterative
                         refinement in bm_solve (mixed formulation)                 */
+  BM_PREC_MIXED_DEVICE = 2  /* the same factors; the refinement's stopping test is
+                        taken on the device (no host synchronisation)             */
 };
 
 enum bm_quadrature {
@@ -170,6 +172,13 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, i
  * exact mixed system in the residual and the mixed-precision factors F, until
  * ||b - A x||_2 <= tol ||b||_2 or max_iter steps; it synchronises the stream
  * once per step and returns BM_E_NOCONV if a column misses the tolerance.
+ * BM_PREC_MIXED_DEVICE: the same factorisation; bm_solve runs exactly max_iter
+ * correction passes, each applied only while the residual test of the previous
+ * one fails (the test is a kernel), and a final residual test; nothing waits for
+ * the host, so the solve can be captured in a HIP graph or queued behind other
+ * work.  A column missing the tolerance is reported by the next synchronising
+ * call (bm_sync, bm_block_lu with info) as BM_E_NOCONV; bm_refine_stats then
+ * gives the passes applied and the final residual (it synchronises).
  * Defaults: BM_PREC_FP64, tol = 1e-12, max_iter = 10.
  * Errors: BM_E_ARG (unknown precision, mixed precision for BM_ORDINARY, tol <= 0,
  * max_iter < 0). */
@@ -328,8 +337,8 @@ int bm_problem_bytes(int32_t n, int32_t formulation, int64_t *bytes);
  * beside each other (lanes * ceil(concurrent_max_n / 64) <= CUs / 2) and the
  * kernels of small requests are short, whereas a large request's Schur
  * complement occupies every CU for tens of milliseconds.  A request's result
- * does not depend on the other requests (bitwise).  Mixed formulation, FP64
- * precision.  The server is thread-safe. */
+ * does not depend on the other requests (bitwise).  Mixed formulation, FP64 or
+ * mixed precision (config.precision).  The server is thread-safe. */
 typedef struct bm_server bm_server;
 
 typedef struct {
@@ -344,6 +353,12 @@ typedef struct {
                                 with lanes > 1 it must be <= 2048 and
                                 lanes * ceil(concurrent_max_n / 64) <= CUs / 2      */
   int32_t quadrature;        /* BM_QUAD_* of every handle (0: Kress)                 */
+  int32_t precision;         /* BM_PREC_FP64 (0) or BM_PREC_MIXED_DEVICE: the FP32
+                                Schur complement with refinement decided on the
+                                device (a request missing refine_tol ends with
+                                BM_E_NOCONV)                                        */
+  int32_t refine_steps;      /* correction passes of BM_PREC_MIXED_DEVICE; <= 0: 2   */
+  double refine_tol;         /* relative residual target; <= 0: 1e-12               */
 } bm_server_config;
 
 /* One request.  Device arrays: the geometry (as bm_assemble), B (3N x nrhs,

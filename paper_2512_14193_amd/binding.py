@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libbm_mi355x.so")
 BM_MIXED, BM_ORDINARY = 0, 1
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_STATE, BM_E_DEVICE, BM_E_NOCONV = 0, -1, -2, -3, -4, -5, -6
 BM_E_BUDGET, BM_E_CANCELED, BM_E_TIMEOUT, BM_E_DOMAIN = -7, -8, -9, -10
-BM_PREC_FP64, BM_PREC_MIXED = 0, 1
+BM_PREC_FP64, BM_PREC_MIXED, BM_PREC_MIXED_DEVICE = 0, 1, 2
 BM_QUAD_KRESS, BM_QUAD_ZETA1, BM_QUAD_ZETA31 = 0, 1, 2
 QUADRATURES = {"kress": BM_QUAD_KRESS, "zeta": BM_QUAD_ZETA1, "zeta31": BM_QUAD_ZETA31}
 BM_MAX_NRHS = 32
@@ -51,7 +51,8 @@ class BMParams(ctypes.Structure):
 class BMServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("graph_max_n", ctypes.c_int32), ("lanes", ctypes.c_int32), ("concurrent_max_n", ctypes.c_int32),
-                ("quadrature", ctypes.c_int32)]
+                ("quadrature", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double)]
 
 
 class BMRequest(ctypes.Structure):
@@ -287,8 +288,10 @@ class Problem:
         check(lib().bm_sync(self._h), "bm_sync")
 
     def set_precision(self, precision: str = "fp64", tol: float = 1e-12, max_iter: int = 10):
-        """bm_set_precision: "fp64" or "mixed" (FP32 matrix cores + FP64 refinement)."""
-        code = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED}[precision]
+        """bm_set_precision: "fp64", "mixed" (FP32 matrix cores + FP64 refinement) or
+        "mixed_device" (the same, the refinement's test taken on the device:
+        exactly max_iter passes, no host synchronisation)."""
+        code = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED, "mixed_device": BM_PREC_MIXED_DEVICE}[precision]
         check(lib().bm_set_precision(self._h, code, float(tol), int(max_iter)), "bm_set_precision")
 
     def set_lu_overlap(self, on: bool = True):
@@ -352,11 +355,16 @@ class Server:
     returns the request's result."""
 
     def __init__(self, hbm_budget_bytes: int = 0, max_inflight: int = 4, graph_max_n: int = 0, lanes: int = 4,
-                 concurrent_max_n: int = 1024, quadrature: str = "kress"):
+                 concurrent_max_n: int = 1024, quadrature: str = "kress", precision: str = "fp64",
+                 refine_steps: int = 2, refine_tol: float = 1e-12):
+        """precision "fp64" or "mixed" (FP32 Schur complement, refinement decided on
+        the device: refine_steps passes, target refine_tol)."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs on the GPU only")
+        prec = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED_DEVICE}[precision]
         cfg = BMServerConfig(int(hbm_budget_bytes), int(max_inflight), int(graph_max_n), int(lanes),
-                             int(concurrent_max_n), QUADRATURES[quadrature])
+                             int(concurrent_max_n), QUADRATURES[quadrature], prec, int(refine_steps),
+                             float(refine_tol))
         h = ctypes.c_void_p()
         check(lib().bm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bm_server_create")
         self._h = h

@@ -83,7 +83,7 @@ static bm_alloc_sizes problem_sizes(int n, int formulation) {
   z.dev_err = sizeof(int32_t) * 4;
   z.ir_r = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
   z.ir_d = mixed ? c * 3 * N * BM_MAX_NRHS : 0;
-  z.ir_norm = mixed ? sizeof(double) * 2 * BM_MAX_NRHS : 0;
+  z.ir_norm = mixed ? sizeof(double) * (2 * BM_MAX_NRHS + 4) : 0;  // norms, then the device refinement's state
   // split-K partials of the Schur complement computed beside the LU
   z.pipe_w = (mixed && n <= BM_PIPE_MAX_N) ? c * bm_getrf_pipe_w_elems(n) : 0;
   return z;
@@ -242,7 +242,8 @@ static int read_dev_err(bm_problem *p, int32_t *info) {
   BM_HIP_TRY(hipStreamSynchronize(p->stream));
   if (info) *info = h[1];
   if (h[2]) return BM_E_DOMAIN;
-  return h[0] ? BM_E_DEVICE : BM_OK;
+  if (h[0]) return BM_E_DEVICE;
+  return h[3] ? BM_E_NOCONV : BM_OK;  // [3]: a device-decided refinement missed its target
 }
 
 int bm_block_lu(bm_problem *p, int32_t *info) {
@@ -254,6 +255,9 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
   const int n = p->n, nf = p->nf;
   int rc = BM_OK;
+  // a refinement flag left by a solve with the previous factors does not apply
+  if (p->form == BM_MIXED)
+    if (int rc0 = bm_launch_ir_reset(p->stream, p->ir_norm + 2 * BM_MAX_NRHS, p->dev_err + 3, 0)) return rc0;
   if (p->form == BM_MIXED && p->prec == BM_PREC_FP64 && p->pipeline) {
     if (int rc0 = bm_getrf_pipe_create(p->gws)) return rc0;
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23], formed in
@@ -279,7 +283,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
     phase_begin(p, BM_PH_SCHUR);
     // (FP32 matrix cores in mixed precision; bm_solve refines against the FP64 blocks)
-    rc = (p->prec == BM_PREC_MIXED ? bm_launch_zgemm32 : bm_launch_zgemm)(
+    rc = (p->prec != BM_PREC_FP64 ? bm_launch_zgemm32 : bm_launch_zgemm)(
         p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
     phase_end(p, BM_PH_SCHUR);
     if (rc) return rc;
@@ -289,7 +293,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   // (mixed precision: the trailing updates beside the next panel run on the FP32
   // matrix cores; the panels, the next panel's own update and the storage stay FP64)
   p->gws->prof = (p->profiling >= 2) ? p : nullptr;  // per-panel timing (BM_PH_PANEL)
-  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec == BM_PREC_MIXED);
+  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec != BM_PREC_FP64);
   p->gws->prof = nullptr;
   if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
@@ -334,14 +338,19 @@ static int solve_pass(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, cplx *
 // Residual r = b - A x of the mixed system with the FP64 blocks:
 //   [r1; r2] = [b1; b2] - [x1; x2] - Top x3,   r3 = b3 - Bot [x1; x2].
 // Returns max_j ||r_j|| / ||b_j|| (synchronises the stream).
-static int residual(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, const cplx *Xc, int64_t ldx, double *relres) {
+// The residual R = b - A x and its column norms (ir_norm), enqueued only.
+static int residual_enqueue(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, const cplx *Xc, int64_t ldx) {
   const int n = p->n, rows = 3 * n;
   cplx *R = p->ir_r;
   int rc = bm_launch_ir_prep(p->stream, rows, 2 * n, nr, Bc, ldb, Xc, ldx, R, rows);
   if (!rc) rc = bm_launch_gemv_sub(p->stream, 2 * n, n, nr, p->top, 2 * n, Xc + 2 * n, ldx, R, rows, p->work_p);
   if (!rc) rc = bm_launch_gemv_sub(p->stream, n, 2 * n, nr, p->bot, n, Xc, ldx, R + 2 * n, rows, p->work_p);
   if (!rc) rc = bm_launch_colnorms(p->stream, rows, nr, R, rows, Bc, ldb, p->ir_norm);
-  if (rc) return rc;
+  return rc;
+}
+
+static int residual(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, const cplx *Xc, int64_t ldx, double *relres) {
+  if (int rc = residual_enqueue(p, nr, Bc, ldb, Xc, ldx)) return rc;
   double h[2 * BM_MAX_NRHS];
   BM_HIP_TRY(hipMemcpyAsync(h, p->ir_norm, sizeof(double) * 2 * nr, hipMemcpyDeviceToHost, p->stream));
   BM_HIP_TRY(hipStreamSynchronize(p->stream));
@@ -366,16 +375,36 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv,
   const cplx *B = (const cplx *)Bv;
   cplx *X = (cplx *)Xv;
   const bool refine = (p->factored_prec == BM_PREC_MIXED);
+  const bool refine_dev = (p->factored_prec == BM_PREC_MIXED_DEVICE);
+  double *ctl = p->ir_norm + 2 * BM_MAX_NRHS;  // the device refinement's state
   int status = BM_OK;
   p->ir_iters = 0;
   p->ir_relres = 0.0;
+  p->ir_dev_stats = refine_dev;
   phase_begin(p, BM_PH_SOLVE);
+  if (refine_dev) {
+    if (int rc = bm_launch_ir_reset(p->stream, ctl, p->dev_err + 3, 0)) return rc;
+  }
   for (int r0 = 0; r0 < nrhs; r0 += BM_MAX_NRHS) {
     const int nr = (nrhs - r0 < BM_MAX_NRHS) ? nrhs - r0 : BM_MAX_NRHS;
     const cplx *Bc = B + (size_t)r0 * ldb;
     cplx *Xc = X + (size_t)r0 * ldx;
     int rc = solve_pass(p, nr, Bc, ldb, Xc, ldx);
     if (rc) return rc;
+    if (refine_dev) {
+      // exactly ir_maxit passes, each applied only while the previous residual
+      // test fails; the tests are kernels (nothing waits for the host)
+      rc = bm_launch_ir_reset(p->stream, ctl, p->dev_err + 3, 1);
+      for (int it = 0; !rc && it < p->ir_maxit; ++it) {
+        rc = residual_enqueue(p, nr, Bc, ldb, Xc, ldx);
+        if (!rc) rc = bm_launch_ir_check(p->stream, nr, p->ir_norm, p->ir_tol, ctl, p->dev_err + 3, 0);
+        if (!rc) rc = solve_pass(p, nr, p->ir_r, rows, p->ir_d, rows);
+        if (!rc) rc = bm_launch_axpy_if(p->stream, rows, nr, p->ir_d, rows, Xc, ldx, ctl);
+      }
+      if (!rc) rc = residual_enqueue(p, nr, Bc, ldb, Xc, ldx);
+      if (!rc) rc = bm_launch_ir_check(p->stream, nr, p->ir_norm, p->ir_tol, ctl, p->dev_err + 3, 1);
+      if (rc) return rc;
+    }
     if (refine) {
       // FP64 iterative refinement: x += A_f^{-1} (b - A x) with the FP64 blocks in
       // the residual and the mixed-precision factors in the correction
@@ -401,8 +430,8 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv,
 
 int bm_set_precision(bm_problem *p, int32_t precision, double tol, int32_t max_iter) {
   if (!p) return BM_E_ARG;
-  if (precision != BM_PREC_FP64 && precision != BM_PREC_MIXED) return BM_E_ARG;
-  if (precision == BM_PREC_MIXED && p->form != BM_MIXED) return BM_E_ARG;
+  if (precision != BM_PREC_FP64 && precision != BM_PREC_MIXED && precision != BM_PREC_MIXED_DEVICE) return BM_E_ARG;
+  if (precision != BM_PREC_FP64 && p->form != BM_MIXED) return BM_E_ARG;
   if (!(tol > 0.0) || max_iter < 0) return BM_E_ARG;
   p->prec = precision;
   p->ir_tol = tol;
@@ -437,6 +466,14 @@ int bm_lu_overlap_info(bm_problem *p, int32_t *enabled, int32_t *segments) {
 
 int bm_refine_stats(bm_problem *p, int32_t *iterations, double *rel_residual) {
   if (!p || !iterations || !rel_residual) return BM_E_ARG;
+  if (p->ir_dev_stats) {  // the device refinement's record of the latest solve
+    double h[4];
+    BM_HIP_TRY(hipMemcpyAsync(h, p->ir_norm + 2 * BM_MAX_NRHS, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+    BM_HIP_TRY(hipStreamSynchronize(p->stream));
+    p->ir_iters = (int)h[3];
+    p->ir_relres = h[2];
+    p->ir_dev_stats = 0;
+  }
   *iterations = p->ir_iters;
   *rel_residual = p->ir_relres;
   return BM_OK;

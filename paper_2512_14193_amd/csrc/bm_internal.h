@@ -203,6 +203,7 @@ struct bm_problem {
   size_t pipe_w_elems;
   int pipeline;         // 1: U33 formed beside its factorisation (mixed form, FP64)
   int lu_segments;      // column segments of the latest factorisation's product (0: formed in full)
+  int ir_dev_stats;     // 1: the latest solve's refinement statistics are on the device
   hipEvent_t after_schur;  // if set: recorded on the stream once U33 is formed in full (request server)
 
   int profiling;
@@ -321,6 +322,17 @@ int bm_launch_ir_prep(hipStream_t s, int rows, int n12, int nrhs, const cplx *B,
 int bm_launch_axpy(hipStream_t s, int rows, int nrhs, const cplx *D, int64_t ldd, cplx *X, int64_t ldx);
 int bm_launch_colnorms(hipStream_t s, int rows, int nrhs, const cplx *R, int64_t ldr, const cplx *B, int64_t ldb,
                        double *out);
+// Refinement decided on the device.  ctl (4 doubles): [0] the latest
+// max_j ||r_j|| / ||b_j||, [1] two int32: converged flag, passes applied in this
+// chunk, [2] the largest final residual and [3] the most passes over the chunks
+// of a solve.  reset: chunk = 1 clears [0], [1]; chunk = 0 also [2], [3] and
+// *noconv.  check: sets the converged flag when [0] <= tol; final: also records
+// [2], [3] and sets *noconv if not converged.  axpy_if: X += D unless converged.
+int bm_launch_ir_reset(hipStream_t s, double *ctl, int32_t *noconv, int chunk);
+int bm_launch_ir_check(hipStream_t s, int nrhs, const double *norms, double tol, double *ctl, int32_t *noconv,
+                       int final);
+int bm_launch_axpy_if(hipStream_t s, int rows, int nrhs, const cplx *D, int64_t ldd, cplx *X, int64_t ldx,
+                      double *ctl);
 
 
 #define BM_HIP_TRY(expr)                         \

@@ -86,6 +86,9 @@ struct bm_server {
   int graph_max_n = 0;
   int concurrent_max_n = 0;
   int quad = BM_QUAD_KRESS;    // quadrature of every handle
+  int prec = BM_PREC_FP64;     // precision of every handle (FP64 or mixed, refined on the device)
+  int refine_steps = 2;
+  double refine_tol = 1e-12;
 
   std::mutex mu;
   std::condition_variable cv_work;   // worker: new request or stop
@@ -186,6 +189,10 @@ int acquire(bm_server *s, const bm_request &r, int lane, srv_handle **out) {
   // served factorisations form U33 first: the segmented product holds most CUs
   // for its whole length, which requests overlapping on other lanes would share
   if (!rc) (void)bm_set_lu_overlap(h->p, 0);
+  if (!rc && s->prec != BM_PREC_FP64) {
+    rc = bm_set_precision(h->p, s->prec, s->refine_tol, s->refine_steps);
+    if (rc) bm_destroy(h->p);
+  }
   if (rc) {
     delete h;
     return rc;
@@ -355,6 +362,7 @@ bool poll(bm_server *s) {
       if (w[2]) status = BM_E_DOMAIN;
       else if (w[0]) status = BM_E_DEVICE;
       else if (w[1] > 0) status = w[1];
+      else if (w[3]) status = BM_E_NOCONV;  // the device refinement missed its target
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, s->ev_start[rq->slot], s->ev_done[rq->slot]) == hipSuccess)
         rq->res.device_ms = ms;
@@ -455,6 +463,7 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
   if (cfg) c = *cfg;
   if (c.graph_max_n < 0 || c.lanes < 0 || c.lanes > 16 || c.concurrent_max_n < 0) return BM_E_ARG;
   if (c.quadrature != BM_QUAD_KRESS && c.quadrature != BM_QUAD_ZETA1 && c.quadrature != BM_QUAD_ZETA31) return BM_E_ARG;
+  if (c.precision != BM_PREC_FP64 && c.precision != BM_PREC_MIXED_DEVICE) return BM_E_ARG;
   const int lanes = c.lanes > 0 ? c.lanes : 4;
   const int cmax = c.concurrent_max_n > 0 ? c.concurrent_max_n : 1024;
   int dev = 0, ncu = 0;
@@ -469,6 +478,9 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
   s->graph_max_n = c.graph_max_n;
   s->concurrent_max_n = cmax;
   s->quad = c.quadrature;
+  s->prec = c.precision;
+  s->refine_steps = c.refine_steps > 0 ? c.refine_steps : 2;
+  s->refine_tol = c.refine_tol > 0.0 ? c.refine_tol : 1e-12;
   size_t free_b = 0, total_b = 0;
   bool ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
   s->budget = c.hbm_budget_bytes > 0 ? c.hbm_budget_bytes : (int64_t)(0.9 * (double)free_b);

@@ -428,3 +428,76 @@ int bm_launch_colnorms(hipStream_t s, int rows, int nrhs, const cplx *R, int64_t
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// refinement decided on the device (BM_PREC_MIXED_DEVICE)
+// ---------------------------------------------------------------------------
+__global__ void ir_reset_kernel(double *ctl, int32_t *noconv, int chunk) {
+  if (threadIdx.x != 0) return;
+  ctl[0] = 0.0;
+  int32_t *f = reinterpret_cast<int32_t *>(ctl + 1);
+  f[0] = 0;
+  f[1] = 0;
+  if (!chunk) {
+    ctl[2] = 0.0;
+    ctl[3] = 0.0;
+    *noconv = 0;
+  }
+}
+
+// one wavefront: q = max_j ||r_j|| / ||b_j|| (||r_j|| where b_j = 0); a NaN
+// counts as not converged
+__global__ void ir_check_kernel(int nrhs, const double *norms, double tol, double *ctl, int32_t *noconv, int final) {
+  const int lane = threadIdx.x;
+  double q = 0.0;
+  for (int j = lane; j < nrhs; j += 64) {
+    const double rn = sqrt(norms[2 * j]), bn = sqrt(norms[2 * j + 1]);
+    double qj = (bn > 0.0) ? rn / bn : rn;
+    if (qj != qj) qj = INFINITY;
+    q = fmax(q, qj);
+  }
+  for (int off = 32; off > 0; off >>= 1) q = fmax(q, __shfl_xor(q, off));
+  if (lane == 0) {
+    int32_t *f = reinterpret_cast<int32_t *>(ctl + 1);
+    ctl[0] = q;
+    if (q <= tol) f[0] = 1;
+    if (final) {
+      ctl[2] = fmax(ctl[2], q);
+      ctl[3] = fmax(ctl[3], (double)f[1]);
+      if (!f[0]) *noconv = 1;
+    }
+  }
+}
+
+__global__ void axpy_if_kernel(int rows, int nrhs, const cplx *D, long ldd, cplx *X, long ldx, double *ctl) {
+  int32_t *f = reinterpret_cast<int32_t *>(ctl + 1);
+  if (f[0]) return;  // converged: the pass is not applied
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0) f[1] += 1;
+  if (idx >= (long)rows * nrhs) return;
+  const int i = (int)(idx % rows), j = (int)(idx / rows);
+  X[i + (long)j * ldx] = cadd(X[i + (long)j * ldx], D[i + (long)j * ldd]);
+}
+
+int bm_launch_ir_reset(hipStream_t s, double *ctl, int32_t *noconv, int chunk) {
+  hipLaunchKernelGGL(ir_reset_kernel, dim3(1), dim3(64), 0, s, ctl, noconv, chunk);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_ir_check(hipStream_t s, int nrhs, const double *norms, double tol, double *ctl, int32_t *noconv,
+                       int final) {
+  hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(64), 0, s, nrhs, norms, tol, ctl, noconv, final);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_axpy_if(hipStream_t s, int rows, int nrhs, const cplx *D, int64_t ldd, cplx *X, int64_t ldx,
+                      double *ctl) {
+  const long tot = (long)rows * nrhs;
+  if (tot == 0) return BM_OK;
+  hipLaunchKernelGGL(axpy_if_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, nrhs, D, (long)ldd,
+                     X, (long)ldx, ctl);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}

@@ -114,3 +114,45 @@ def test_mixed_precision_rejected_for_ordinary():
     with pytest.raises(B.BMError) as e:
         P.set_precision("mixed")
     assert e.value.code == B.BM_E_ARG
+
+
+@pytest.mark.parametrize("name,bnd,ph", CASES[:2] + CASES[3:], ids=[c[0] for c in CASES[:2] + CASES[3:]])
+def test_device_decided_refinement(name, bnd, ph):
+    """BM_PREC_MIXED_DEVICE: the same factors and corrections as the host-decided
+    refinement (a pass is applied only while the previous residual test failed), so
+    the solution is bitwise the host-decided one; against the oracle to 1e-10; a
+    target that cannot be met within the passes is reported by the next
+    synchronising call as BM_E_NOCONV."""
+    N = bnd.n_nodes
+    print(f"[mixed-device] {name}", flush=True)
+    Bh = I.probing_rhs(3 * N, 5, 11)
+    sols, stats = {}, {}
+    for mode in ("mixed", "mixed_device"):
+        P = B.Problem(N, "mixed")
+        P.set_precision(mode, tol=1e-12, max_iter=4)
+        P.assemble(bnd, ph)
+        assert P.block_lu() == 0
+        sols[mode] = to_np(P.solve(to_dev(Bh)))
+        P.sync()
+        stats[mode] = P.refine_stats()
+        P.close()
+    assert stats["mixed"][0] == stats["mixed_device"][0] >= 1  # passes applied
+    assert stats["mixed_device"][1] <= 1e-12
+    assert np.array_equal(sols["mixed"], sols["mixed_device"])
+    Xo = O.zgesv(O.build_mixed(bnd, ph), Bh)
+    assert rel_cols(sols["mixed_device"], Xo) < 1e-10
+    # no pass allowed: the FP32 factors alone miss 1e-12
+    P = B.Problem(N, "mixed")
+    P.set_precision("mixed_device", tol=1e-12, max_iter=0)
+    P.assemble(bnd, ph)
+    assert P.block_lu() == 0
+    P.solve(to_dev(Bh))
+    with pytest.raises(B.BMError) as e:
+        P.sync()
+    assert e.value.code == B.BM_E_NOCONV
+    it, rr = P.refine_stats()
+    assert it == 0 and rr > 1e-12
+    # a new factorisation clears the flag
+    assert P.block_lu() == 0
+    P.sync()
+    P.close()

@@ -130,6 +130,39 @@ def test_served_request_in_sweep_range_vs_oracle():
     assert rel_cols(X.cpu().numpy(), Xo) < 1e-10
 
 
+@pytest.mark.parametrize("graph_max_n", [0, 256])
+def test_served_mixed_precision(graph_max_n):
+    """precision "mixed": the FP32 Schur complement with the refinement decided on
+    the device (inside the captured graph for graph_max_n = 256): against the
+    oracle to 1e-10, the same request alone and in the mix bitwise equal, and a
+    target out of reach ends the request with BM_E_NOCONV."""
+    reqs = contour_mix()[:6]
+    print(f"[serving] mixed precision, graph_max_n {graph_max_n}", flush=True)
+
+    def mk(lanes):
+        return B.Server(max_inflight=2, graph_max_n=graph_max_n, lanes=lanes, precision="mixed", refine_steps=3)
+
+    alone = []
+    for r in reqs:
+        s = mk(1)
+        (res, X), = serve(s, [r])
+        s.close()
+        assert res["status"] == 0
+        alone.append(X)
+    s = mk(3)
+    mix = serve(s, reqs)
+    s.close()
+    for r, Xa, (res, Xm) in zip(reqs, alone, mix):
+        assert res["status"] == 0 and res["graph"] == (1 if r.n <= graph_max_n else 0)
+        assert torch.equal(Xa, Xm)
+        Xo = O.zgesv(O.build_mixed(r.bnd, r.ph), r.Bh)
+        assert rel_cols(Xm.cpu().numpy(), Xo) < 1e-10
+    s = B.Server(lanes=1, graph_max_n=graph_max_n, precision="mixed", refine_steps=1, refine_tol=1e-30)
+    (res, X), = serve(s, [reqs[0]])
+    s.close()
+    assert res["status"] == B.BM_E_NOCONV
+
+
 def test_graph_replays_with_eager_work_between():
     """One handle's captured graph replayed for new wavenumbers, with the
     program's own eager work and synchronisations between the replays: every
