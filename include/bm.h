@@ -453,7 +453,8 @@ int bm_block_moments(void *hip_stream, int32_t rows, int32_t L, const void *U, i
  * pivots with |R_jj| > tol |R_00|, the same count for rows and columns per type
  * (the larger).  The compressed system eq. (compressed), with diagonal blocks
  * (R_i A_ii^{-1} L_i)^{-1}, is compressed again level by level (recursive
- * skeletonisation) up to a dense root.  Leaf blocks use Theorem (thm:LU)
+ * skeletonisation) up to a dense root: the compressed system of all cells of the
+ * first level (going up) whose skeletons number at most root_max.  Leaf blocks use Theorem (thm:LU)
  * (U33 = -[M31 M32][M13; M23]), A_ii^{-1} L_i Corollary (lem:block_LU) and
  * A_ii^{-1} f_i Corollary (lem:for_ssm_RHS).  Quadrature: the one-point
  * zeta-corrected trapezoid rule (BM_QUAD_ZETA1), whose entries between distinct
@@ -466,6 +467,9 @@ typedef struct {
   int32_t leaf;      /* leaf cell size, 16..320 (default 256)                      */
   int32_t n_proxy;   /* proxy points per circle at least, >= 8 (default 128)       */
   double tol;        /* rank tolerance of the column-pivoted QR, (0, 1) (1e-10)    */
+  int32_t root_max;  /* order up to which the compressed system of a level is
+                        factored densely as the root; <= 0: 4096 (1: compress
+                        up to the two cells of level 1)                           */
 } bm_fds_config;
 
 /* Create a solver for N nodes (N <= 65536, N / leaf a power of two >= 2), cfg NULL

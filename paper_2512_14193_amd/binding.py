@@ -68,7 +68,8 @@ class BMRequestResult(ctypes.Structure):
 
 
 class BMFdsConfig(ctypes.Structure):
-    _fields_ = [("leaf", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("tol", ctypes.c_double)]
+    _fields_ = [("leaf", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("root_max", ctypes.c_int32)]
 
 
 class BMServerCounters(ctypes.Structure):
@@ -486,13 +487,13 @@ class FDS:
     """Proxy-compressed fast direct solver of the mixed system (bm_fds_*)."""
 
     def __init__(self, n_nodes: int, leaf: int = 256, n_proxy: int = 128, tol: float = 1e-10,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, root_max: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs on the GPU only")
         self.n = int(n_nodes)
         self.rows = 3 * self.n
         self.stream = stream or torch.cuda.current_stream()
-        cfg = BMFdsConfig(int(leaf), int(n_proxy), float(tol))
+        cfg = BMFdsConfig(int(leaf), int(n_proxy), float(tol), int(root_max))
         h = ctypes.c_void_p()
         check(lib().bm_fds_create(self.n, ctypes.byref(cfg), _stream_handle(self.stream), ctypes.byref(h)),
               "bm_fds_create")

@@ -71,6 +71,9 @@ struct bm_fds {
   // per-level statistics
   std::vector<int> rank_sum, rank_max;
   int root_n = 0;
+  int root_max = 4096;       // order up to which a level's compressed system is the root
+  int top = 1;               // the level whose cells make up the root
+  std::vector<long> root_off;  // offset of each top-level cell's skeletons in the root
   // scratch reused by the solve
   std::vector<bm_gemm_desc> hg;
   bm_gemm_desc *dg = nullptr;
@@ -797,6 +800,47 @@ int assemble_parents(bm_fds *f, std::vector<fds_cell> &kids, std::vector<fds_cel
   return entries(f, arena, ej);
 }
 
+// The root: the compressed system of every cell of the top level together, the
+// cells' Lambda blocks on the diagonal and the matrix entries between one cell's
+// row skeletons and another's column skeletons elsewhere (what assemble_parents
+// does for two cells).
+int assemble_root(bm_fds *f, std::vector<fds_cell> &kids) {
+  std::vector<fds_cell> &top = f->lv[0];
+  top.clear();
+  top.resize(1);
+  fds_cell &P = top[0];
+  P.level = 0;
+  P.index = 0;
+  P.node0 = 0;
+  P.nn = f->n;
+  f->root_off.assign(kids.size(), 0);
+  long o = 0;
+  for (size_t i = 0; i < kids.size(); ++i) {
+    f->root_off[i] = o;
+    o += kids[i].ktot;
+    P.rows.insert(P.rows.end(), kids[i].rskel.begin(), kids[i].rskel.end());
+    P.cols.insert(P.cols.end(), kids[i].cskel.begin(), kids[i].cskel.end());
+  }
+  P.m = (int)P.rows.size();
+  const int m = P.m;
+  if (int rc = dmalloc(f, &P.Abar, (size_t)m * m)) return rc;
+  std::vector<bm_copy_desc> cp;
+  std::vector<entry_job> ej;
+  for (size_t a = 0; a < kids.size(); ++a) {
+    const int ka = kids[a].ktot;
+    const long oa = f->root_off[a];
+    if (!ka) continue;
+    cp.push_back(copyd(kids[a].Lam, ka, P.Abar + oa + oa * m, m, ka, ka));
+    for (size_t b = 0; b < kids.size(); ++b) {
+      if (b == a || !kids[b].ktot) continue;
+      entry_job e = {&kids[a].rskel, &kids[b].cskel, oa + f->root_off[b] * m, m};
+      ej.push_back(e);
+    }
+  }
+  if (int rc = run_copies(f, cp)) return rc;
+  return entries(f, P.Abar, ej);
+}
+
 int factor_all(bm_fds *f) {
   const int L = f->levels, n = f->leaf, N = f->n;
   f->lv.assign(L + 1, std::vector<fds_cell>());
@@ -890,9 +934,18 @@ int factor_all(bm_fds *f) {
     if (verbose())
       fprintf(stderr, "[bm_fds] level %d: %zu cells, block order <= %d, skeletons %d (max %d per cell)\n", l,
               cells.size(), mmax, f->rank_sum[l], f->rank_max[l]);
+    // the root: this level's compressed system, once it is small enough to be
+    // factored densely (compressing the few large cells above it would cost more
+    // than it saves: a wave problem's ranks grow with the cell size)
+    if (l == 1 || f->rank_sum[l] <= f->root_max) {
+      f->top = l;
+      if (int rc = assemble_root(f, cells)) return rc;
+      break;
+    }
     if (int rc = assemble_parents(f, cells, f->lv[l - 1], l - 1)) return rc;
   }
-  // root: the dense compressed system of the two level-1 cells
+  if (verbose()) fprintf(stderr, "[bm_fds] root: the %zu cells of level %d\n", f->lv[f->top].size(), f->top);
+  // root: the dense compressed system of the top level's cells
   fds_cell &root = f->lv[0][0];
   f->root_n = root.m;
   if (int rc = dmalloc(f, &root.Ainv, (size_t)root.m * root.m)) return rc;
@@ -935,7 +988,12 @@ int solve_chunk(bm_fds *f, int nr, const cplx *B, long ldb, cplx *X, long ldx) {
   for (auto &c : f->lv[L])
     if (int rc = bm_fds_rows(s, c.m, nr, c.gidx, const_cast<cplx *>(B), ldb, c.fb, c.m, 0)) return rc;
   // upward pass: z = A_bar^{-1} f_bar, g = Lambda R z (into the parent's f_bar)
-  for (int l = L; l >= 1; --l) {
+  const int T = f->top;
+  fds_cell &root = f->lv[0][0];
+  // a cell's parent block and its offset there (the root for the top level's cells)
+  auto parent = [&](int l, size_t ci) -> fds_cell & { return (l == T) ? root : f->lv[l - 1][ci / 2]; };
+  auto poff = [&](int l, size_t ci) -> long { return (l == T) ? f->root_off[ci] : child_off(f, l, (int)ci); };
+  for (int l = L; l >= T; --l) {
     std::vector<fds_cell> &cells = f->lv[l];
     std::vector<bm_copy_desc> cp;
     std::vector<bm_gemm_desc> g1, g2, g3;
@@ -962,34 +1020,32 @@ int solve_chunk(bm_fds *f, int nr, const cplx *B, long ldb, cplx *X, long ldx) {
       if (c.ktot) h1.push_back(gemm(c.ktot, nr, c.m, ONE, c.R, c.ktot, c.z, c.m, ZERO, c.t, c.ktot));
     if (int rc = run_gemms(f, h1)) return rc;
     for (size_t ci = 0; ci < cells.size(); ++ci) {
-      fds_cell &c = cells[ci], &P = f->lv[l - 1][ci / 2];
-      if (c.ktot)
-        h2.push_back(gemm(c.ktot, nr, c.ktot, ONE, c.Lam, c.ktot, c.t, c.ktot, ZERO, P.fb + child_off(f, l, (int)ci), P.m));
+      fds_cell &c = cells[ci], &P = parent(l, ci);
+      if (c.ktot) h2.push_back(gemm(c.ktot, nr, c.ktot, ONE, c.Lam, c.ktot, c.t, c.ktot, ZERO, P.fb + poff(l, ci), P.m));
     }
     if (int rc = run_gemms(f, h2)) return rc;
   }
   // root
   {
-    fds_cell &r = f->lv[0][0];
-    std::vector<bm_gemm_desc> g{gemm(r.m, nr, r.m, ONE, r.Ainv, r.m, r.fb, r.m, ZERO, r.xb, r.m)};
+    std::vector<bm_gemm_desc> g{gemm(root.m, nr, root.m, ONE, root.Ainv, root.m, root.fb, root.m, ZERO, root.xb,
+                                     root.m)};
     if (int rc = run_gemms(f, g)) return rc;
   }
   // downward pass: x_bar = z - W (g - Lambda y), y the cell's part of the parent's x_bar
-  for (int l = 1; l <= L; ++l) {
+  for (int l = T; l <= L; ++l) {
     std::vector<fds_cell> &cells = f->lv[l];
     std::vector<bm_copy_desc> cp;
     std::vector<bm_gemm_desc> g1, g2;
     for (size_t ci = 0; ci < cells.size(); ++ci) {
-      fds_cell &c = cells[ci], &P = f->lv[l - 1][ci / 2];
-      const long o = child_off(f, l, (int)ci);
+      fds_cell &c = cells[ci], &P = parent(l, ci);
+      const long o = poff(l, ci);
       if (c.ktot) cp.push_back(copyd(P.fb + o, P.m, c.t, c.ktot, c.ktot, nr));  // t = g
       cp.push_back(copyd(c.z, c.m, c.xb, c.m, c.m, nr));                         // x_bar = z
     }
     if (int rc = run_copies(f, cp)) return rc;
     for (size_t ci = 0; ci < cells.size(); ++ci) {
-      fds_cell &c = cells[ci], &P = f->lv[l - 1][ci / 2];
-      if (c.ktot)
-        g1.push_back(gemm(c.ktot, nr, c.ktot, MONE, c.Lam, c.ktot, P.xb + child_off(f, l, (int)ci), P.m, ONE, c.t, c.ktot));
+      fds_cell &c = cells[ci], &P = parent(l, ci);
+      if (c.ktot) g1.push_back(gemm(c.ktot, nr, c.ktot, MONE, c.Lam, c.ktot, P.xb + poff(l, ci), P.m, ONE, c.t, c.ktot));
     }
     if (int rc = run_gemms(f, g1)) return rc;
     for (auto &c : cells)
@@ -1012,8 +1068,9 @@ extern "C" {
 int bm_fds_create(int32_t n, const bm_fds_config *cfg, void *hip_stream, bm_fds **out) {
   if (!out) return BM_E_ARG;
   *out = nullptr;
-  bm_fds_config c = {256, 128, 1e-10};
+  bm_fds_config c = {256, 128, 1e-10, 0};
   if (cfg) c = *cfg;
+  if (c.root_max <= 0) c.root_max = 4096;
   if (c.leaf < 16 || c.leaf > BM_FDS_GJ_MAX || n < 2 * c.leaf || n > 65536 || (n % c.leaf) != 0) return BM_E_ARG;
   const int p = n / c.leaf;
   if (p & (p - 1)) return BM_E_ARG;
@@ -1024,6 +1081,7 @@ int bm_fds_create(int32_t n, const bm_fds_config *cfg, void *hip_stream, bm_fds 
   f->leaf = c.leaf;
   f->n_proxy = c.n_proxy;
   f->tol = c.tol;
+  f->root_max = c.root_max;
   f->levels = 0;
   while ((c.leaf << f->levels) < n) ++f->levels;
   f->stream = (hipStream_t)hip_stream;

@@ -51,7 +51,8 @@ SMALL = [
 def test_fds_small_against_oracle(name, bnd, ph, leaf):
     N = bnd.n_nodes
     print(f"[fds] {name}", flush=True)
-    f = B.FDS(N, leaf=leaf, n_proxy=64, tol=1e-10)
+    # root_max = 1: compressed up to the two cells of level 1, as the oracle does
+    f = B.FDS(N, leaf=leaf, n_proxy=64, tol=1e-10, root_max=1)
     f.factor(geo(bnd), ph)
     th = I.plane_wave_angles(3, 4)
     Bd = f.rhs_plane_wave(torch.as_tensor(th))
@@ -76,6 +77,35 @@ def test_fds_small_against_oracle(name, bnd, ph, leaf):
     Fo = O.far_field(bnd, ph, X[:N, :3], X[N:2 * N, :3], th_obs)
     assert rel_cols(Fd, Fo) < 1e-10
     f.close()
+
+
+@pytest.mark.parametrize("root_max", [0, 1500, 700, 1])
+def test_fds_root_level(root_max):
+    """The root is the compressed system of the first level (going up) whose
+    skeletons number at most root_max (default 4096; level 1 if none does): every
+    choice solves the same system to the tolerance, and the levels above the root
+    are not compressed."""
+    N, leaf = 1024, 32
+    bnd, ph = I.ellipse(N, 10.0, 1.0), I.Physics.from_wavenumbers(8.0, 12.0)
+    f = B.FDS(N, leaf=leaf, n_proxy=64, tol=1e-10, root_max=root_max)
+    f.factor(geo(bnd), ph)
+    Bh = I.probing_rhs(3 * N, 3, 31)
+    X = to_np(f.solve(to_dev(Bh)))
+    info = f.info()
+    f.close()
+    Xd = np.linalg.solve(O.build_mixed(bnd, ph, "zeta"), Bh)
+    assert rel_cols(X, Xd) < 1e-8
+    sums = info["skeletons_sum"]
+    top = min(l for l in range(1, info["levels"] + 1) if sums[l] > 0)
+    assert all(sums[l] > 0 for l in range(top, info["levels"] + 1))
+    assert info["root_n"] == sums[top]
+    limit = 4096 if root_max == 0 else root_max
+    if root_max == 1:
+        assert top == 1
+    else:
+        # the first level (going up) within the limit, else level 1
+        assert (sums[top] <= limit or top == 1) and all(sums[l] > limit for l in range(top + 1, info["levels"] + 1))
+    print(f"[fds] root_max {root_max}: root at level {top}, order {info['root_n']}", flush=True)
 
 
 def test_fds_matches_dense_zeta_solve_on_ellipse_config():
