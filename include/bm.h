@@ -165,9 +165,11 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *B, int64_t ldb, void *X, i
 
 /* Precision of the following bm_block_lu calls and of the solves with their
  * factors.  BM_PREC_MIXED (mixed formulation only): U33 = -Bot * Top runs on the
- * FP32 matrix cores (operands rounded to complex64, FP32 accumulation, FP64
- * storage), and so do the LU's trailing updates beyond the next panel (its panels,
- * the next panel's update and the factors' storage stay FP64).  bm_solve then refines
+ * FP32 matrix cores (operands rounded to complex64, FP32 accumulation) into a
+ * complex64 U33, which is factored in complex64 storage: partial pivoting as in
+ * FP64, each panel factored in FP64 registers and rounded on its store, the
+ * trailing updates beyond the next panel on the FP32 matrix cores, the factors
+ * complex64 (bm_copy_factors widens them to complex128).  bm_solve then refines
  * every right-hand side, x <- x + F^{-1} (b - A x) with the FP64 blocks of the
  * exact mixed system in the residual and the mixed-precision factors F, until
  * ||b - A x||_2 <= tol ||b||_2 or max_iter steps; it synchronises the stream
@@ -246,8 +248,9 @@ int bm_far_field(bm_problem *p, int32_t nrhs, const void *X, int64_t ldx, int32_
 int bm_copy_blocks(bm_problem *p, void *a, int64_t lda, void *b, int64_t ldb);
 
 /* Copy the factors out (after bm_block_lu): the packed L\U of U33 (mixed,
- * N x N) or of the 2N x 2N matrix (ordinary) and the pivots (device int32,
- * 0-based: row i was swapped with ipiv[i] at step i). */
+ * N x N) or of the 2N x 2N matrix (ordinary) as complex128, and the pivots
+ * (device int32, 0-based: row i was swapped with ipiv[i] at step i).  Factors of
+ * a mixed-precision factorisation are complex64 values, widened exactly. */
 int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv);
 
 /* Synchronise the problem's stream and report device-side errors of the calls

@@ -282,20 +282,32 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   if (p->form == BM_MIXED) {
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
     phase_begin(p, BM_PH_SCHUR);
-    // (FP32 matrix cores in mixed precision; bm_solve refines against the FP64 blocks)
-    rc = (p->prec != BM_PREC_FP64 ? bm_launch_zgemm32 : bm_launch_zgemm)(
-        p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
+    // (mixed precision: on the FP32 matrix cores, into a complex64 U33 that takes
+    // the first half of the factor storage; bm_solve refines against the FP64 blocks)
+    if (p->prec != BM_PREC_FP64)
+      rc = bm_launch_zgemm32_c(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0),
+                               (cplx32 *)p->lu, n);
+    else
+      rc = bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu,
+                           n);
     phase_end(p, BM_PH_SCHUR);
     if (rc) return rc;
     if (p->after_schur) BM_HIP_TRY(hipEventRecord(p->after_schur, p->stream));
   }
   phase_begin(p, BM_PH_LU);
-  // (mixed precision: the trailing updates beside the next panel run on the FP32
-  // matrix cores; the panels, the next panel's own update and the storage stay FP64)
+  // (mixed precision: the LU of the complex64 U33, its factors stored in complex64;
+  // the panels factor in FP64 registers and round on their store, the trailing
+  // updates beside the next panel run on the FP32 matrix cores)
   p->gws->prof = (p->profiling >= 2) ? p : nullptr;  // per-panel timing (BM_PH_PANEL)
-  rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, p->prec != BM_PREC_FP64);
+  const bool c64 = (p->prec != BM_PREC_FP64);
+  if (c64)
+    rc = bm_getrf_run_c64(p->stream, nf, (cplx32 *)p->lu, nf, p->ipiv, p->dev_err, p->gws);
+  else
+    rc = bm_getrf_run(p->stream, nf, p->lu, nf, p->ipiv, p->dev_err, p->gws, 0);
   p->gws->prof = nullptr;
-  if (!rc) rc = bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
+  if (!rc)
+    rc = c64 ? bm_launch_diag_inverses_c64(p->stream, nf, (const cplx32 *)p->lu, nf, p->dinv)
+             : bm_launch_diag_inverses(p->stream, nf, p->lu, nf, p->dinv);
   if (!rc) rc = bm_launch_perm(p->stream, p->gws, nf, p->perm);
   phase_end(p, BM_PH_LU);
   if (rc) return rc;
@@ -322,8 +334,14 @@ static int solve_pass(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, cplx *
   }
   rc = bm_launch_gather(p->stream, nf, nr, p->perm, X3, ldx, Y, nf);
   if (!rc) rc = bm_trsv_reset(p->stream, p->gws, nf);
-  if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
-  if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+  if (p->factored_prec != BM_PREC_FP64) {  // complex64 factors
+    const cplx32 *lu32 = (const cplx32 *)p->lu;
+    if (!rc) rc = bm_launch_trsv_c64(p->stream, p->gws, 1, nf, lu32, nf, p->dinv, Y, nf, nr, p->dev_err);
+    if (!rc) rc = bm_launch_trsv_c64(p->stream, p->gws, 0, nf, lu32, nf, p->dinv, Y, nf, nr, p->dev_err);
+  } else {
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 1, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+    if (!rc) rc = bm_launch_trsv(p->stream, p->gws, 0, nf, p->lu, nf, p->dinv, Y, nf, nr, p->dev_err);
+  }
   if (rc) return rc;
   BM_HIP_TRY(hipMemcpy2DAsync(X3, sizeof(cplx) * ldx, Y, sizeof(cplx) * nf, sizeof(cplx) * nf, nr,
                               hipMemcpyDeviceToDevice, p->stream));
@@ -528,8 +546,13 @@ int bm_copy_factors(bm_problem *p, void *lu, int64_t ld, int32_t *ipiv) {
   const size_t nf = (size_t)p->nf;
   if (ld < (int64_t)nf) return BM_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
-  BM_HIP_TRY(hipMemcpy2DAsync(lu, sizeof(cplx) * ld, p->lu, sizeof(cplx) * nf, sizeof(cplx) * nf, nf,
-                              hipMemcpyDeviceToDevice, p->stream));
+  if (p->factored_prec != BM_PREC_FP64) {  // complex64 factors, widened
+    if (int rc = bm_launch_widen(p->stream, (int)nf, (int)nf, (const cplx32 *)p->lu, (int64_t)nf, (cplx *)lu, ld))
+      return rc;
+  } else {
+    BM_HIP_TRY(hipMemcpy2DAsync(lu, sizeof(cplx) * ld, p->lu, sizeof(cplx) * nf, sizeof(cplx) * nf, nf,
+                                hipMemcpyDeviceToDevice, p->stream));
+  }
   BM_HIP_TRY(hipMemcpyAsync(ipiv, p->ipiv, sizeof(int32_t) * nf, hipMemcpyDeviceToDevice, p->stream));
   return BM_OK;
 }

@@ -210,8 +210,8 @@ __device__ inline pdbl4 pmfma16(double a, double b, pdbl4 c) {
 // of these columns (U12 itself) are written back by workgroup 0 at the end, when
 // every workgroup has long finished reading the old values (it has published its
 // candidate of column 0, which workgroup 0 waited for).  RPL = 1 and P >= 10 only.
-template <int RPL, bool FUSE>
-__global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, int j, int jb, int P, int32_t *ipiv,
+template <int RPL, bool FUSE, class T>
+__global__ __launch_bounds__(SNT) void panel_kernel(int N, T *A, long lda, int j, int jb, int P, int32_t *ipiv,
                                                     int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
                                                     int next_jb, int32_t *swp, int j0, const int32_t *swp0) {
   constexpr int RPW = 64 * RPL;  // rows per workgroup
@@ -235,6 +235,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 
   if constexpr (FUSE) {
     static_assert(RPL == 1, "the fused update holds U12 beside a 64-row panel");
+    static_assert(sizeof(T) == sizeof(cplx), "the fused update is built for the FP64 factorisation");
     constexpr int UOFF = LU_NB * (64 + 1);  // U12 in LDS after the panel block
     cplx *Ls = pan;                         // L11, then this workgroup's rows of L21 (ld 64)
     cplx *Us = pan + UOFF;                  // all of U12 (ld 64)
@@ -256,12 +257,13 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
     // interchanged rows j0 .. j0 + 63) into registers
     for (int idx = tid; idx < LU_NB * LU_NB; idx += SNT) {
       const int r = idx & 63, c = idx >> 6;
-      st_st(Ls, idx, st_ld(A, (long)(j0 + r) + (long)(j0 + c) * lda));
+      st_st(Ls, idx, ld_z(A, (long)(j0 + r) + (long)(j0 + c) * lda));
     }
     __syncthreads();
     const int cown = g + P * wave;  // this wavefront's column of U12
     if (wave < SNT / 64 && cown < jb) {
-      cplx x = A[(long)s_srcx[lane] + (long)(j + cown) * lda];
+      const st_v2 x0 = ld_z(A, (long)s_srcx[lane] + (long)(j + cown) * lda);
+      cplx x = cmk(x0.x, x0.y);
       for (int c0 = 0; c0 < LU_NB - 1; c0 += 8) {
         cplx lv[8];
 #pragma unroll
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
         const int idx = tid + SNT * q;
         if (idx < LU_NB * LU_NB) {
           const int r = idx & 63, kc = idx >> 6;  // L21: row r, column kc of the previous panel
-          st_st(Ls, kc * 64 + r, (r < nv) ? st_ld(A, (r0 + r) + (long)(j0 + kc) * lda) : st_v2{0.0, 0.0});
+          st_st(Ls, kc * 64 + r, (r < nv) ? ld_z(A, (r0 + r) + (long)(j0 + kc) * lda) : st_v2{0.0, 0.0});
         }
       }
       const unsigned long long t0 = wall_clock64();
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = wm * 32 + a * 16 + fi, c = wn * 32 + b * 16 + 4 * q + fq;
-            old[a][b][q] = st_ld(A, (r < nv && c < jb) ? (long)s_src[r] + (long)(j + c) * lda : (long)j + (long)j * lda);
+            old[a][b][q] = ld_z(A, (r < nv && c < jb) ? (long)s_src[r] + (long)(j + c) * lda : (long)j + (long)j * lda);
           }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int idx = tid + SNT * q, r = idx % RPW, c = idx / RPW;
-      v[q] = st_ld(A, (r < nv && c < jb) ? (r0 + r) + (long)(j + c) * lda : a0);
+      v[q] = ld_z(A, (r < nv && c < jb) ? (r0 + r) + (long)(j + c) * lda : a0);
     }
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 
   for (int idx = tid; idx < RPW * jb; idx += SNT) {
     const int r = idx % RPW, c = idx / RPW;
-    if (r < nv) A[(r0 + r) + (long)(j + c) * lda] = pan[c * LDP + r];
+    if (r < nv) st_z(A, (r0 + r) + (long)(j + c) * lda, to_v2(pan[c * LDP + r]));
   }
   // refill the words the next panel uses in the other slot buffer with the empty pattern
   if (next_P > 0) {
@@ -760,7 +762,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
       const cplx *Us = pan + LU_NB * (64 + 1);
       for (int idx = tid; idx < LU_NB * jb; idx += SNT) {
         const int k = idx & 63, cc = idx >> 6;
-        A[(long)(j0 + k) + (long)(j + cc) * lda] = Us[cc * 64 + k];
+        st_z(A, (long)(j0 + k) + (long)(j + cc) * lda, to_v2(Us[cc * 64 + k]));
       }
     }
   }
@@ -792,8 +794,8 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, cplx *A, long lda, in
 #define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
 #define ST_LDS(cw) ((size_t)(LU_NB * LU_NB + (cw) * LU_NB) * sizeof(cplx))
 
-template <int CW>
-__global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j, int jb, int lcols, int c0, int c1,
+template <int CW, class T>
+__global__ __launch_bounds__(256) void swap_trsm_kernel(T *A, long lda, int j, int jb, int lcols, int c0, int c1,
                                                         const int32_t *swp, int nleft) {
   extern __shared__ cplx sm[];
   __shared__ int s_pair[2 * ST_NPAIR];  // (dst, src) rows of the interchange
@@ -810,13 +812,13 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     for (int q = 0; q < LPT; ++q) {
       const int idx = tid + 256 * q, e = idx % ST_NPAIR, col = cbase + idx / ST_NPAIR;
       const bool ok = e < np && col < lcols;
-      v[q] = st_ld(A, ok ? s_pair[2 * e + 1] + (long)col * lda : (long)j);
+      v[q] = ld_z(A, ok ? s_pair[2 * e + 1] + (long)col * lda : (long)j);
     }
     __syncthreads();  // every source read before any row is overwritten
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int idx = tid + 256 * q, e = idx % ST_NPAIR, col = cbase + idx / ST_NPAIR;
-      if (e < np && col < lcols) st_st(A, s_pair[2 * e] + (long)col * lda, v[q]);
+      if (e < np && col < lcols) st_z(A, s_pair[2 * e] + (long)col * lda, v[q]);
     }
     return;
   }
@@ -834,12 +836,12 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
 #pragma unroll
   for (int q = 0; q < LPT_L; ++q) {
     const int idx = tid + 256 * q, r = idx % LU_NB, c = idx / LU_NB;
-    lv[q] = st_ld(A, (r < jb && c < jb) ? (j + r) + (long)(j + c) * lda : a0);
+    lv[q] = ld_z(A, (r < jb && c < jb) ? (j + r) + (long)(j + c) * lda : a0);
   }
 #pragma unroll
   for (int q = 0; q < LPT_X; ++q) {
     const int idx = tid + 256 * q, r = idx % LU_NB, cl = idx / LU_NB;
-    xv[q] = st_ld(A, (r < jb && cl < ncw) ? (j + r) + (long)(cw0 + cl) * lda : a0);
+    xv[q] = ld_z(A, (r < jb && cl < ncw) ? (j + r) + (long)(cw0 + cl) * lda : a0);
   }
   if (tid < 2 * np) s_pair[tid] = pr_v;
   __syncthreads();
@@ -848,7 +850,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
 #pragma unroll
   for (int q = 0; q < LPT_S; ++q) {
     const int idx = tid + 256 * q, e = idx % ST_NPAIR, cl = idx / ST_NPAIR;
-    sv[q] = st_ld(A, (e < np && cl < ncw) ? s_pair[2 * e + 1] + (long)(cw0 + cl) * lda : a0);
+    sv[q] = ld_z(A, (e < np && cl < ncw) ? s_pair[2 * e + 1] + (long)(cw0 + cl) * lda : a0);
   }
 #pragma unroll
   for (int q = 0; q < LPT_L; ++q) {
@@ -867,7 +869,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
     if (e < np && cl < ncw) {
       const int dst = s_pair[2 * e];
       if (dst < j + jb) st_st(X, cl * LU_NB + (dst - j), sv[q]);
-      else st_st(A, dst + (long)(cw0 + cl) * lda, sv[q]);
+      else st_z(A, dst + (long)(cw0 + cl) * lda, sv[q]);
     }
   }
   __syncthreads();
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(cplx *A, long lda, int j
 #pragma unroll
     for (int q = 0; q < CPW; ++q) {
       const int cl = CPW * wave + q;
-      if (cl < ncw) A[(j + lane) + (long)(cw0 + cl) * lda] = xs[q];
+      if (cl < ncw) st_z(A, (j + lane) + (long)(cw0 + cl) * lda, to_v2(xs[q]));
     }
   }
 }
@@ -951,14 +953,21 @@ void bm_getrf_ws_destroy(bm_getrf_ws *w) {
   delete w;
 }
 
-__global__ void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv);
+template <class TS>
+__global__ void diag_inv_kernel(int n, const TS *LU, long ld, cplx *dinv);
 
 #define TI_LDS ((size_t)(2 * TI_N * (TI_N + 1) + 1024) * sizeof(cplx))  // M, X, T of tri_inv64
 
-typedef void (*panel_fn)(int, cplx *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int,
-                         int32_t *, int, const int32_t *);
+template <class T>
+using panel_fn = void (*)(int, T *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int, int32_t *,
+                          int, const int32_t *);
 // 64 and 128 rows per workgroup; 64 rows with the previous panel's update fused
-static const panel_fn panel_fns[3] = {panel_kernel<1, false>, panel_kernel<2, false>, panel_kernel<1, true>};
+// (FP64 storage only)
+static const panel_fn<cplx> panel_fns[3] = {panel_kernel<1, false, cplx>, panel_kernel<2, false, cplx>,
+                                            panel_kernel<1, true, cplx>};
+static const panel_fn<cplx32> panel_fns_c64[2] = {panel_kernel<1, false, cplx32>, panel_kernel<2, false, cplx32>};
+static const void *panel_fn_of(const cplx *, int k) { return (const void *)panel_fns[k]; }
+static const void *panel_fn_of(const cplx32 *, int k) { return (k < 2) ? (const void *)panel_fns_c64[k] : nullptr; }
 
 static int panel_attr_done[64];
 
@@ -1003,45 +1012,65 @@ int bm_getrf_prepare() {
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
-    for (int k = 0; k < 3; ++k)
-      BM_HIP_TRY(hipFuncSetAttribute((const void *)panel_fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)PANEL_LDS_ALLOC));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel<ST_CW_NEXT>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_NEXT)));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)swap_trsm_kernel<ST_CW_REST>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_REST)));
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const void *big[] = {(const void *)panel_fns[0], (const void *)panel_fns[1], (const void *)panel_fns[2],
+                         (const void *)panel_fns_c64[0], (const void *)panel_fns_c64[1]};
+    for (const void *f : big)
+      BM_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PANEL_LDS_ALLOC));
+    const void *st_next[] = {(const void *)swap_trsm_kernel<ST_CW_NEXT, cplx>,
+                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx32>};
+    const void *st_rest[] = {(const void *)swap_trsm_kernel<ST_CW_REST, cplx>,
+                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx32>};
+    for (int t = 0; t < 2; ++t) {
+      BM_HIP_TRY(hipFuncSetAttribute(st_next[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_NEXT)));
+      BM_HIP_TRY(hipFuncSetAttribute(st_rest[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_REST)));
+    }
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel<cplx>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)TI_LDS));
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)diag_inv_kernel<cplx32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)TI_LDS));
     panel_attr_done[dev] = 1;
   }
   return BM_OK;
 }
 
+// The k = 64 update C -= L21 U12 of an LU step: FP64 storage on the FP64 matrix
+// cores or, with gemm32, beyond the next panel on the FP32 ones; complex64 storage
+// on the FP64 shallow kernel for the next panel, on the FP32 matrix cores beyond.
+static int lu_gemm(hipStream_t st, int m, int n, int k, const cplx *A, long lda, const cplx *B, long ldb, cplx *C,
+                   long ldc, bool next, int gemm32) {
+  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  return ((gemm32 && !next) ? bm_launch_zgemm32 : bm_launch_zgemm)(st, m, n, k, mone, A, lda, B, ldb, one, C, ldc);
+}
+static int lu_gemm(hipStream_t st, int m, int n, int k, const cplx32 *A, long lda, const cplx32 *B, long ldb,
+                   cplx32 *C, long ldc, bool next, int) {
+  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  return (next ? bm_launch_zgemm_shallow_c64 : bm_launch_zgemm32_cc)(st, m, n, k, mone, A, lda, B, ldb, one, C, ldc);
+}
+
 // The interchanges of the panel at column j (jb columns, list swp) on the columns
 // [0, lcols), and on the columns [c0, c1) right of it also U12 = L11^{-1} A12 and
 // the trailing update A22 -= L21 U12 (FP32 matrix cores with gemm32).  `next`:
 // the narrow column split for the next panel's columns (critical path).
-static int lu_update(hipStream_t st, cplx *A, long lda, int n, int j, int jb, const int32_t *swp, int lcols, int c0,
+template <class T>
+static int lu_update(hipStream_t st, T *A, long lda, int n, int j, int jb, const int32_t *swp, int lcols, int c0,
                      int c1, bool next, int gemm32) {
-  const cplx one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   const int cw = next ? ST_CW_NEXT : ST_CW_REST;
   const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 > c0) ? (c1 - c0 + cw - 1) / cw : 0;
   if (nleft + nright > 0) {
     if (next)
-      hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_NEXT>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A, lda,
-                         j, jb, lcols, c0, c1, swp, nleft);
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_NEXT, T>), dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A,
+                         lda, j, jb, lcols, c0, c1, swp, nleft);
     else
-      hipLaunchKernelGGL(swap_trsm_kernel<ST_CW_REST>, dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A, lda,
-                         j, jb, lcols, c0, c1, swp, nleft);
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_REST, T>), dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A,
+                         lda, j, jb, lcols, c0, c1, swp, nleft);
     BM_HIP_TRY(hipGetLastError());
   }
   const int nr = n - j - jb, jn = j + jb;
   if (nr > 0 && c1 > c0)
     // gemm32: the FP32 matrix cores for the columns beyond the next panel (the
     // next panel's 64 columns, on the critical path, keep the FP64 shallow kernel)
-    return ((gemm32 && !next) ? bm_launch_zgemm32 : bm_launch_zgemm)(st, nr, c1 - c0, jb, mone, A + jn + (long)j * lda,
-                                                                     lda, A + j + (long)c0 * lda, lda, one,
-                                                                     A + jn + (long)c0 * lda, lda);
+    return lu_gemm(st, nr, c1 - c0, jb, A + jn + (long)j * lda, lda, A + j + (long)c0 * lda, lda,
+                   A + jn + (long)c0 * lda, lda, next, gemm32);
   return BM_OK;
 }
 
@@ -1087,7 +1116,8 @@ static bool lu_fused(bool overlap, const int *shape, int pi) {
   return overlap && pi >= 1 && shape[3 * pi] == 1 && shape[3 * pi + 1] >= 10;
 }
 
-static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+template <class T>
+static int lu_panel(hipStream_t s, int n, T *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
                     const int *shape, int pi, bool overlap) {
   const int npanel = (n + LU_NB - 1) / LU_NB;
   const int j = pi * LU_NB, jb = (n - j < LU_NB) ? n - j : LU_NB;
@@ -1107,14 +1137,14 @@ static int lu_panel(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, i
   void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp, &j0, &swp0};
   const int rpl = shape[3 * pi];
   if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
-  BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns[fuse ? 2 : rpl - 1], dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC,
-                             s));
+  BM_HIP_TRY(hipLaunchKernel(panel_fn_of(A, fuse ? 2 : rpl - 1), dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
   if (w->prof) bm_phase_end(w->prof, BM_PH_PANEL);
   return BM_OK;
 }
 
-int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
-                 int gemm32) {
+template <class T>
+static int getrf_run(hipStream_t s, int n, T *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                     int gemm32) {
   if (!w || w->n < n) return BM_E_ARG;
   int shape[3 * 1024];  // rows per lane, P per panel
   int ncu = 0;
@@ -1145,6 +1175,16 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
   }
   if (w->aux && npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
   return BM_OK;
+}
+
+int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err, bm_getrf_ws *w,
+                 int gemm32) {
+  return getrf_run(s, n, A, lda, ipiv, dev_err, w, gemm32);
+}
+
+int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
+                     bm_getrf_ws *w) {
+  return getrf_run(s, n, A, lda, ipiv, dev_err, w, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1466,7 +1506,7 @@ extern "C" int bm_zgetrf_noalloc(void *hip_stream, int32_t n, void *A, int64_t l
   BM_HIP_TRY(hipGetDevice(&dev));
   unsigned char *sp = nullptr;
   if (int rc = na_scratch(dev, &sp)) return rc;
-  bm_getrf_ws w;  // host view of the scratch; no stream, no events
+  bm_getrf_ws w{};  // host view of the scratch; no stream, no events, no profiling
   w.n = BM_NOALLOC_MAX_N;
   w.npanel = BM_NOALLOC_MAX_N / LU_NB;
   w.slots = (cplx *)sp;
@@ -1494,7 +1534,8 @@ extern "C" int bm_zgetrf_noalloc(void *hip_stream, int32_t n, void *A, int64_t l
 // dinv layout: block b at dinv + b * 4 * 64 * 64: [Linv, Uinv, WL, WU] (col-major 64x64;
 // a tile that does not exist, WL_0 or WU_last, is not written)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, long ld, cplx *dinv) {
+template <class TS>
+__global__ __launch_bounds__(256) void diag_inv_kernel(int n, const TS *LU, long ld, cplx *dinv) {
   extern __shared__ cplx sm[];
   cplx *Ms = sm, *Xs = sm + TI_N * (TI_N + 1), *T = sm + 2 * TI_N * (TI_N + 1);
   const int b = blockIdx.x;
@@ -1508,7 +1549,7 @@ __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, lo
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
-      v[q] = st_ld(LU, (r < nb && c < nb) ? (o + r) + (long)(o + c) * ld : o + (long)o * ld);
+      v[q] = ld_z(LU, (r < nb && c < nb) ? (o + r) + (long)(o + c) * ld : o + (long)o * ld);
     }
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
@@ -1537,7 +1578,7 @@ __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, lo
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int idx = threadIdx.x + 256 * q, r = idx % TI_N, c = idx / TI_N;
-      v[q] = st_ld(LU, (r < nb && c < cn) ? (o + r) + (long)(co + c) * ld : o + (long)co * ld);
+      v[q] = ld_z(LU, (r < nb && c < cn) ? (o + r) + (long)(co + c) * ld : o + (long)co * ld);
     }
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
@@ -1570,10 +1611,19 @@ __global__ __launch_bounds__(256) void diag_inv_kernel(int n, const cplx *LU, lo
   }
 }
 
-int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv) {
+template <class T>
+static int diag_inverses(hipStream_t s, int n, const T *LU, int64_t ld, cplx *dinv) {
   const int nblk = (n + BM_DIAG_NB - 1) / BM_DIAG_NB;
-  hipLaunchKernelGGL(diag_inv_kernel, dim3(nblk, 2), dim3(256), TI_LDS, s, n, LU, (long)ld, dinv);
+  hipLaunchKernelGGL(diag_inv_kernel<T>, dim3(nblk, 2), dim3(256), TI_LDS, s, n, LU, (long)ld, dinv);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
+}
+
+int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv) {
+  return diag_inverses(s, n, LU, ld, dinv);
+}
+
+int bm_launch_diag_inverses_c64(hipStream_t s, int n, const cplx32 *LU, int64_t ld, cplx *dinv) {
+  return diag_inverses(s, n, LU, ld, dinv);
 }
 

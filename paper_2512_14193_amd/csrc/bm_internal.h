@@ -7,6 +7,7 @@
 #include "../../include/bm.h"
 
 typedef double2 cplx;  // (re, im), the layout of torch.complex128
+typedef float2 cplx32;  // (re, im), the layout of torch.complex64: storage of the FP32 factorisation
 
 #define BM_PI 3.14159265358979323846
 #define BM_EULER 0.57721566490153286061
@@ -69,15 +70,15 @@ __device__ inline cplx csqrt_d(cplx w) {
 #define SWP_STRIDE (1 + 4 * LU_NB) // per panel: count, then (dst, src) row pairs
 
 struct bm_getrf_ws {
-  int n, npanel;
-  cplx *slots;         // 2 buffers of per-column exchange records (candidates and diagonal row)
-  int32_t *swp;        // per panel: count, then (dst, src) pairs
-  cplx *zbuf;          // triangular solves: [ticket counters][lower solve's blocks][upper solve's blocks]
-  hipStream_t aux;     // second stream: the trailing update of panel k runs beside panel k + 1
-  hipEvent_t e_next, e_rest;
-  struct bm_problem *prof;  // non-null: time each panel launch in that problem's BM_PH_PANEL phase
-  struct bm_problem *prof_schur;  // non-null: the segmented product's span in its BM_PH_SCHUR phase
-  struct bm_lu_pipe *pipe;  // streams and events of the LU with the Schur complement beside it (or null)
+  int n = 0, npanel = 0;
+  cplx *slots = nullptr;     // 2 buffers of per-column exchange records (candidates and diagonal row)
+  int32_t *swp = nullptr;    // per panel: count, then (dst, src) pairs
+  cplx *zbuf = nullptr;      // triangular solves: [ticket counters][lower solve's blocks][upper solve's blocks]
+  hipStream_t aux = nullptr;  // second stream: the trailing update of panel k runs beside panel k + 1
+  hipEvent_t e_next = nullptr, e_rest = nullptr;
+  struct bm_problem *prof = nullptr;  // non-null: time each panel launch in that problem's BM_PH_PANEL phase
+  struct bm_problem *prof_schur = nullptr;  // non-null: the segmented product's span in its BM_PH_SCHUR phase
+  struct bm_lu_pipe *pipe = nullptr;  // streams and events of the LU with the Schur complement beside it (or null)
 };
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {
@@ -111,6 +112,19 @@ __device__ inline double l1abs(cplx v) { return fabs(v.x) + fabs(v.y); }
 typedef double st_v2 __attribute__((ext_vector_type(2)));
 __device__ inline st_v2 st_ld(const cplx *A, long i) { return *reinterpret_cast<const st_v2 *>(A + i); }
 __device__ inline void st_st(cplx *A, long i, st_v2 v) { *reinterpret_cast<st_v2 *>(A + i) = v; }
+// The same for a matrix stored in complex64 (the FP32 factorisation): loads widen
+// to FP64, stores round to nearest.  ld_z / st_z take either storage type.
+typedef float st_f2 __attribute__((ext_vector_type(2)));
+__device__ inline st_v2 ld_z(const cplx *A, long i) { return st_ld(A, i); }
+__device__ inline st_v2 ld_z(const cplx32 *A, long i) {
+  const st_f2 v = *reinterpret_cast<const st_f2 *>(A + i);
+  return st_v2{(double)v.x, (double)v.y};
+}
+__device__ inline void st_z(cplx *A, long i, st_v2 v) { st_st(A, i, v); }
+__device__ inline void st_z(cplx32 *A, long i, st_v2 v) {
+  *reinterpret_cast<st_f2 *>(A + i) = st_f2{(float)v.x, (float)v.y};
+}
+__device__ inline st_v2 to_v2(cplx v) { return st_v2{v.x, v.y}; }
 // Product of a 64 x 64 complex tile with a group of eight complex columns on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64), both operands in registers, for a
 // workgroup whose wavefront w owns rows 16 w .. 16 w + 15.  Lane (fi, fq) =
@@ -231,6 +245,16 @@ int bm_launch_zgemm_persist(hipStream_t s, int m, int n, int k, cplx alpha, cons
 // the same product on the FP32 matrix cores (operands rounded to complex64, FP32 accumulation)
 int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda,
                       const cplx *B, int64_t ldb, cplx beta, cplx *C, int64_t ldc);
+// The FP32 factorisation's products, every operand stored in complex64: the FP32
+// matrix cores for C = alpha A B + beta C (c64 result; A and B FP64 or c64), and the
+// FP64 shallow kernel for the next panel's update (k <= 64, n <= 64, FP64
+// arithmetic on the widened values)
+int bm_launch_zgemm32_c(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
+                        int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
+int bm_launch_zgemm32_cc(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
+                         const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
+int bm_launch_zgemm_shallow_c64(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
+                                const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
 
 // Batched complex GEMM C = alpha A B + beta C, one descriptor per product
 struct bm_gemm_desc {
@@ -299,10 +323,16 @@ int bm_check_params(const bm_params *prm);
 int bm_fill_u64(hipStream_t s, void *p, size_t n, unsigned long long v);
 int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                  bm_getrf_ws *w, int gemm32);
+// The same blocked LU of a matrix stored in complex64 (the FP32 factorisation: the
+// panels in FP64 registers, every store rounded to complex64, the trailing updates
+// on the FP32 matrix cores)
+int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
+                     bm_getrf_ws *w);
 // Per 64-row block b, BM_DINV_TILES column-major 64 x 64 tiles at dinv + b * BM_DINV_TILES * 4096:
 //   Linv_b, Uinv_b, WL_b = Linv_b L(b, b - 1) (b > 0), WU_b = Uinv_b U(b, b + 1) (b < last)
 #define BM_DINV_TILES 4
 int bm_launch_diag_inverses(hipStream_t s, int n, const cplx *LU, int64_t ld, cplx *dinv);
+int bm_launch_diag_inverses_c64(hipStream_t s, int n, const cplx32 *LU, int64_t ld, cplx *dinv);
 
 // solve support (bm_solve.hip): the composed row permutation, gathers, the skinny
 // GEMM C -= A B, and the blocked triangular solves (lower: unit L, else U) on X
@@ -316,6 +346,10 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 int bm_trsv_reset(hipStream_t s, bm_getrf_ws *w, int n);
 int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
                    cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
+int bm_launch_trsv_c64(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx32 *LU, int64_t ld,
+                       const cplx *dinv, cplx *X, int64_t ldx, int nrhs, int32_t *dev_err);
+// Y (complex128) = X (complex64), an n x m column-major block
+int bm_launch_widen(hipStream_t s, int n, int m, const cplx32 *X, int64_t ldx, cplx *Y, int64_t ldy);
 // refinement support: R = B - [X(0:n12, :); 0] (rows), X += D, per-column squared norms
 int bm_launch_ir_prep(hipStream_t s, int rows, int n12, int nrhs, const cplx *B, int64_t ldb, const cplx *X,
                       int64_t ldx, cplx *R, int64_t ldr);

@@ -184,8 +184,8 @@ int bm_launch_gemv_sub(hipStream_t s, int m, int k, int nr, const cplx *A, int64
 #define ZSENT 0xFFFFFFFFFFFFFFFFULL
 
 // NG groups of eight right-hand sides (nrhs <= 8 NG): each lane holds 2 NG of them
-template <bool LOWER, int NG>
-__global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long ld, const cplx *dinv, cplx *X, long ldx,
+template <bool LOWER, int NG, class T>
+__global__ __launch_bounds__(256) void trsv_kernel(int n, const T *LU, long ld, const cplx *dinv, cplx *X, long ldx,
                                                    int nrhs, int32_t *ticket, cplx *zbuf, int32_t *dev_err) {
   __shared__ int s_t;
   __shared__ cplx Z[TS_NB][8 * NG + 1];
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(int n, const cplx *LU, long l
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int c = 4 * s + fq;
-        tl[s] = st_ld(LU, (rr < nb && c < kn) ? (o + rr) + (long)(ko + c) * ld : o + (long)ko * ld);
+        tl[s] = ld_z(LU, (rr < nb && c < kn) ? (o + rr) + (long)(ko + c) * ld : o + (long)ko * ld);
       }
     } else {
       const cplx *D = Dt + (i > nd1 ? 2 * TS_NB * TS_NB : 0);
@@ -336,20 +336,49 @@ int bm_trsv_reset(hipStream_t s, bm_getrf_ws *w, int n) {
 }
 
 // Needs bm_trsv_reset on the same stream since the last solve of the same kind.
-int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
-                   cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
+template <class T>
+static int launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const T *LU, int64_t ld, const cplx *dinv,
+                       cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
   if (nrhs > BM_MAX_NRHS) return BM_E_ARG;
   if (nrhs <= 0 || n <= 0) return BM_OK;
   const int nblk = (n + TS_NB - 1) / TS_NB;
   int32_t *ticket = (int32_t *)w->zbuf + (lower ? 0 : 1);
   cplx *zb = w->zbuf + 1 + (lower ? 0 : (size_t)nblk * TS_NB * BM_MAX_NRHS);
-  typedef void (*trsv_fn)(int, const cplx *, long, const cplx *, cplx *, long, int, int32_t *, cplx *, int32_t *);
-  static const trsv_fn fns[2][3] = {{trsv_kernel<false, 1>, trsv_kernel<false, 2>, trsv_kernel<false, 4>},
-                                    {trsv_kernel<true, 1>, trsv_kernel<true, 2>, trsv_kernel<true, 4>}};
+  typedef void (*trsv_fn)(int, const T *, long, const cplx *, cplx *, long, int, int32_t *, cplx *, int32_t *);
+  static const trsv_fn fns[2][3] = {{trsv_kernel<false, 1, T>, trsv_kernel<false, 2, T>, trsv_kernel<false, 4, T>},
+                                    {trsv_kernel<true, 1, T>, trsv_kernel<true, 2, T>, trsv_kernel<true, 4, T>}};
   const int gi = (nrhs <= 8) ? 0 : (nrhs <= 16) ? 1 : 2;
   static_assert(BM_MAX_NRHS <= 32, "the triangular solves take at most four groups of eight right-hand sides");
   hipLaunchKernelGGL(fns[lower ? 1 : 0][gi], dim3(nblk), dim3(256), 0, s, n, LU, (long)ld, dinv, X, (long)ldx, nrhs,
                      ticket, zb, dev_err);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_trsv(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx *LU, int64_t ld, const cplx *dinv,
+                   cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
+  return launch_trsv(s, w, lower, n, LU, ld, dinv, X, ldx, nrhs, dev_err);
+}
+
+int bm_launch_trsv_c64(hipStream_t s, bm_getrf_ws *w, int lower, int n, const cplx32 *LU, int64_t ld,
+                       const cplx *dinv, cplx *X, int64_t ldx, int nrhs, int32_t *dev_err) {
+  return launch_trsv(s, w, lower, n, LU, ld, dinv, X, ldx, nrhs, dev_err);
+}
+
+// Y (complex128) = X (complex64), n x m, column-major
+__global__ void widen_kernel(int n, int m, const cplx32 *X, long ldx, cplx *Y, long ldy) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * m) return;
+  const int i = (int)(idx % n), j = (int)(idx / n);
+  const cplx32 v = X[i + (long)j * ldx];
+  Y[i + (long)j * ldy] = cmk((double)v.x, (double)v.y);
+}
+
+int bm_launch_widen(hipStream_t s, int n, int m, const cplx32 *X, int64_t ldx, cplx *Y, int64_t ldy) {
+  const long tot = (long)n * m;
+  if (tot <= 0) return BM_OK;
+  hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, m, X, (long)ldx, Y,
+                     (long)ldy);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

@@ -326,10 +326,12 @@ int bm_launch_zgemm_batched(hipStream_t s, int count, const bm_gemm_desc *d_dev,
 // workgroup waits for one round of global loads instead of one per stage.
 #define GS_T 32
 #define GS_K 64
+// (T: the storage of all three operands, complex128 or complex64; FP64 arithmetic)
+template <class T>
 __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k, cplx alpha,
-                                                            const cplx *__restrict__ A, long lda,
-                                                            const cplx *__restrict__ B, long ldb, cplx beta,
-                                                            cplx *__restrict__ C, long ldc, int tiles_m) {
+                                                            const T *__restrict__ A, long lda,
+                                                            const T *__restrict__ B, long ldb, cplx beta,
+                                                            T *__restrict__ C, long ldc, int tiles_m) {
   __shared__ cplx As[GS_K][GS_T];
   __shared__ cplx Bs[GS_K][GS_T + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -341,9 +343,9 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
   for (int u = 0; u < GU; ++u) {
     const int idx = tid + 256 * u;
     const int ar = idx % GS_T, ak = idx / GS_T;  // A: row fastest (coalesced columns)
-    av_[u] = st_ld(A, (row0 + ar < m && ak < k) ? (row0 + ar) + (long)ak * lda : 0);
+    av_[u] = ld_z(A, (row0 + ar < m && ak < k) ? (row0 + ar) + (long)ak * lda : 0);
     const int bk = idx % GS_K, bc = idx / GS_K;  // B: k fastest (coalesced columns)
-    bv_[u] = st_ld(B, (bk < k && col0 + bc < n) ? bk + (long)(col0 + bc) * ldb : 0);
+    bv_[u] = ld_z(B, (bk < k && col0 + bc < n) ? bk + (long)(col0 + bc) * ldb : 0);
   }
 #pragma unroll
   for (int u = 0; u < GU; ++u) {
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = row0 + wm * 16 + fi, col = col0 + wn * 16 + 4 * r + fq;
-    cv[r] = st_ld(C, (row < m && col < n) ? row + (long)col * ldc : 0);
+    cv[r] = ld_z(C, (row < m && col < n) ? row + (long)col * ldc : 0);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
       cplx out = cmul(alpha, cmk(accr[r], acci[r]));
       // beta = 0: C's old value is not used (it may hold anything, NaN included)
       if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, cmk(cv[r].x, cv[r].y)));
-      C[row + (long)col * ldc] = out;
+      st_z(C, row + (long)col * ldc, to_v2(out));
     }
   }
 }
@@ -392,8 +394,8 @@ int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *
     const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
     const long tiles = (long)tm * tn;
     if (tiles > 0x7fffffffL) return BM_E_ARG;
-    hipLaunchKernelGGL(zgemm_shallow_kernel, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda,
-                       B, (long)ldb, beta, C, (long)ldc, tm);
+    hipLaunchKernelGGL(zgemm_shallow_kernel<cplx>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
+                       (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
     BM_HIP_TRY(hipGetLastError());
     return BM_OK;
   }
@@ -414,6 +416,19 @@ int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *
   else
     hipLaunchKernelGGL((zgemm_kernel<false, false>), grid, dim3(256), 0, s, m, n, k, alpha, A, (long)lda, B,
                        (long)ldb, beta, C, (long)ldc, tm);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_zgemm_shallow_c64(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
+                                const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  if (k > GS_K || n > 64) return BM_E_ARG;
+  const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
+  const long tiles = (long)tm * tn;
+  if (tiles > 0x7fffffffL) return BM_E_ARG;
+  hipLaunchKernelGGL(zgemm_shallow_kernel<cplx32>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
+                     (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

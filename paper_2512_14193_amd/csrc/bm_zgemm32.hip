@@ -1,12 +1,15 @@
-// Complex GEMM on the FP32 matrix cores with FP64 operands and result:
-//   C = alpha A B + beta C,  A m x k, B k x n, C m x n, column-major complex128.
-// The operands are rounded to complex64 when they are staged into LDS, the
-// products are accumulated in FP32 by v_mfma_f32_32x32x2f32, and the result is
-// widened back to FP64 for the update of C.
+// Complex GEMM on the FP32 matrix cores:
+//   C = alpha A B + beta C,  A m x k, B k x n, C m x n, column-major.
+// Each operand is stored in complex128 or complex64.  The operands are rounded to
+// complex64 when they are staged into LDS, the products are accumulated in FP32
+// by v_mfma_f32_32x32x2f32, and the update of C is formed in FP64 and stored in
+// C's type.
 //
-// Used in the mixed-precision factorisation for the Schur complement
-// U33 = -[M31 M32][M13; M23] of Theorem (thm:LU); FP64 iterative refinement
-// against the FP64 blocks then recovers the FP64 solution.
+// Used in the mixed-precision factorisation: the Schur complement
+// U33 = -[M31 M32][M13; M23] of Theorem (thm:LU) from the FP64 blocks into a
+// complex64 U33, and the trailing updates of its FP32 LU (all three operands
+// complex64); FP64 iterative refinement against the FP64 blocks then recovers the
+// FP64 solution.
 //
 // Tiling: a workgroup of 256 threads (4 wave64s, 2 x 2) owns a 128 x 128 tile of
 // C, two workgroups per CU (accumulators in VGPRs, no spills); each wave owns
@@ -43,11 +46,11 @@ __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-template <bool BETA0>
+template <bool BETA0, class TA, class TB, class TC>
 __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int k, cplx alpha,
-                                                           const cplx *__restrict__ A, long lda,
-                                                           const cplx *__restrict__ B, long ldb, cplx beta,
-                                                           cplx *__restrict__ C, long ldc, int tiles_m) {
+                                                           const TA *__restrict__ A, long lda,
+                                                           const TB *__restrict__ B, long ldb, cplx beta,
+                                                           TC *__restrict__ C, long ldc, int tiles_m) {
   __shared__ float As[2][G2_LP][G2_BK][G2_BM];
   __shared__ float Bs[2][G2_LP][G2_BK][G2_BN];
 
@@ -63,14 +66,14 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
   const int a_r = tid & 127, a_k = tid >> 7;
   const int b_c = tid >> 1, b_k = (tid & 1) * G2_LPT;
 
-  cplx ra[G2_LPT], rb[G2_LPT];
+  st_v2 ra[G2_LPT], rb[G2_LPT];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < G2_LPT; ++u) {
       const int kk = k0 + a_k + (256 / G2_BM) * u, rr = row0 + a_r;
-      ra[u] = (rr < m && kk < k) ? A[rr + (long)kk * lda] : cmk(0, 0);
+      ra[u] = (rr < m && kk < k) ? ld_z(A, rr + (long)kk * lda) : st_v2{0.0, 0.0};
       const int kb = k0 + b_k + u, cc = col0 + b_c;
-      rb[u] = (kb < k && cc < n) ? B[kb + (long)cc * ldb] : cmk(0, 0);
+      rb[u] = (kb < k && cc < n) ? ld_z(B, kb + (long)cc * ldb) : st_v2{0.0, 0.0};
     }
   };
   auto sstore = [&](int buf) {
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
             const int r = 8 * h + rr;
             const int row = row0 + wm * 64 + a * 32 + fi;
             const int col = col0 + wn * 64 + b * 32 + (r & 3) + 8 * (r >> 2) + 4 * fh;
-            cin[rr] = st_ld(C, (row < m && col < n) ? row + (long)col * ldc : 0);
+            cin[rr] = ld_z(C, (row < m && col < n) ? row + (long)col * ldc : 0);
           }
         }
 #pragma unroll
@@ -168,24 +171,40 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
           const cplx v = cmk((double)re, (double)im);
           cplx out = cmul(alpha, v);
           if constexpr (!BETA0) out = cadd(out, cmul(beta, cmk(cin[rr].x, cin[rr].y)));
-          C[row + (long)col * ldc] = out;
+          st_z(C, row + (long)col * ldc, to_v2(out));
         }
       }
       }
 }
 
-int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
-                      int64_t ldb, cplx beta, cplx *C, int64_t ldc) {
+template <class TA, class TB, class TC>
+static int launch32(hipStream_t s, int m, int n, int k, cplx alpha, const TA *A, int64_t lda, const TB *B,
+                    int64_t ldb, cplx beta, TC *C, int64_t ldc) {
   if (m <= 0 || n <= 0) return BM_OK;
   const int tm = (m + G2_BM - 1) / G2_BM, tn = (n + G2_BN - 1) / G2_BN;
   const long tiles = (long)tm * tn;
   if (tiles > 0x7fffffffL) return BM_E_ARG;
   if (beta.x == 0.0 && beta.y == 0.0)
-    hipLaunchKernelGGL(zgemm32_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A, (long)lda,
-                       B, (long)ldb, beta, C, (long)ldc, tm);
-  else
-    hipLaunchKernelGGL(zgemm32_kernel<false>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
+    hipLaunchKernelGGL((zgemm32_kernel<true, TA, TB, TC>), dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
                        (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
+  else
+    hipLaunchKernelGGL((zgemm32_kernel<false, TA, TB, TC>), dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha,
+                       A, (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
+}
+
+int bm_launch_zgemm32(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
+                      int64_t ldb, cplx beta, cplx *C, int64_t ldc) {
+  return launch32(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int bm_launch_zgemm32_c(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
+                        int64_t ldb, cplx beta, cplx32 *C, int64_t ldc) {
+  return launch32(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int bm_launch_zgemm32_cc(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
+                         const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc) {
+  return launch32(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }

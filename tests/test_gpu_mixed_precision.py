@@ -1,5 +1,6 @@
-"""Mixed precision: FP32 matrix-core Schur complement, FP64 iterative refinement
-against the FP64 blocks of the mixed system.
+"""Mixed precision: FP32 matrix-core Schur complement into a complex64 U33, its LU
+stored in complex64 (trailing updates on the FP32 matrix cores), FP64 iterative
+refinement against the FP64 blocks of the mixed system.
 
 The refined solution must meet the same bar as the FP64 path: 1e-10 relative
 per right-hand side against the CPU oracle, with the refinement's own residual
@@ -155,4 +156,41 @@ def test_device_decided_refinement(name, bnd, ph):
     # a new factorisation clears the flag
     assert P.block_lu() == 0
     P.sync()
+    P.close()
+
+
+@pytest.mark.parametrize("name,bnd,ph", [CASES[0], CASES[1], ("star700-ragged", I.star(700),
+                                                               I.Physics.from_wavenumbers(9.0, 13.5))],
+                         ids=["disk256", "star200-complexk", "star700-ragged"])
+def test_fp32_factors(name, bnd, ph):
+    """The mixed-precision factors are complex64 values (every entry of the copied
+    factors is exactly a complex64), and L U reproduces the row-interchanged U33 of
+    the oracle's FP64 blocks to FP32 rounding, not better: the LU itself ran in FP32
+    storage.  The pivots (partial pivoting on the FP32 matrix) may differ from the
+    FP64 ones only where two candidates tie to FP32 rounding, so the check is on
+    the product, not on the pivot list."""
+    N = bnd.n_nodes
+    print(f"[fp32-factors] {name}", flush=True)
+    P = B.Problem(N, "mixed")
+    P.set_precision("mixed", tol=1e-12, max_iter=10)
+    P.assemble(bnd, ph)
+    assert P.block_lu() == 0
+    lu, piv = P.copy_factors()
+    lu, piv = to_np(lu), to_np(piv)
+    assert np.array_equal(lu, lu.astype(np.complex64).astype(np.complex128))
+    A = O.build_mixed(bnd, ph)
+    u33 = A[2 * N:, 2 * N:] - A[2 * N:, :N] @ A[:N, 2 * N:] - A[2 * N:, N:2 * N] @ A[N:2 * N, 2 * N:]
+    pu = u33.copy()
+    for i in range(N):
+        assert i <= piv[i] < N
+        if piv[i] != i:
+            pu[[i, piv[i]]] = pu[[piv[i], i]]
+    L = np.tril(lu, -1) + np.eye(N)
+    U = np.triu(lu)
+    err = np.linalg.norm(L @ U - pu) / np.linalg.norm(u33)
+    assert 1e-10 < err < 2e-6, err
+    # and the refined solve reaches the FP64 bar
+    Bh = I.probing_rhs(3 * N, 3, 5)
+    X = to_np(P.solve(to_dev(Bh)))
+    assert rel_cols(X, O.zgesv(A, Bh)) < 1e-10
     P.close()
