@@ -300,6 +300,22 @@ int bm_zgetrf_noalloc(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t
 int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha,
                  const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
                  void *C, int64_t ldc);
+/* bm_zgemm_f16x3: C = alpha A B with A (m x k) and B (k x n) complex128 and C
+ * complex64 (column-major), on the FP16 matrix cores with FP32-level accuracy: each
+ * row of A and column of B is scaled by a power of two that brings its largest
+ * real or imaginary part into [2^13, 2^14), every scaled value is split into two
+ * FP16 numbers (hi + lo), the products are formed from hi*hi + hi*lo + lo*hi with
+ * FP32 accumulation, and the result is scaled back exactly.  The operands' packed
+ * planes go through the caller's device workspace ws (ws_bytes, 256-byte aligned,
+ * at least bm_zgemm_f16x3_ws_bytes(m, n, k, 16)); a larger workspace takes k in
+ * fewer chunks (bm_zgemm_f16x3_ws_bytes(m, n, k, k) holds all of k at once), the
+ * chunks summed into C in complex64.  The mixed-precision Schur complement of
+ * bm_block_lu runs on this product (in the factor storage left free by the
+ * complex64 U33).  Errors: BM_E_ARG (sizes, null pointers, workspace too small or
+ * misaligned). */
+int bm_zgemm_f16x3(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha, const void *A,
+                   int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc, void *ws, int64_t ws_bytes);
+int64_t bm_zgemm_f16x3_ws_bytes(int32_t m, int32_t n, int32_t k, int32_t k_chunk);
 
 /* Device bytes that bm_create(n, formulation, ...) allocates (*bytes, host).
  * Errors: BM_E_ARG (as bm_create). */

@@ -29,7 +29,7 @@ BM_MAX_NRHS = 32
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
-            "bm_zgemm_f32", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
+            "bm_zgemm_f32", "bm_zgemm_f16x3", "bm_zgemm_f16x3_ws_bytes", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
             "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
             "bm_set_lu_overlap", "bm_lu_overlap_info",
             "bm_zgetrf_noalloc", "bm_fds_create", "bm_fds_factor", "bm_fds_solve", "bm_fds_rhs_plane_wave",
@@ -137,6 +137,9 @@ def lib():
         L.bm_fds_destroy.argtypes = [vp]
         L.bm_fds_destroy.restype = None
         L.bm_zgemm_f32.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, dp, vp, i64]
+        L.bm_zgemm_f16x3.argtypes = [vp, i32, i32, i32, dp, vp, i64, vp, i64, vp, i64, vp, i64]
+        L.bm_zgemm_f16x3_ws_bytes.argtypes = [i32, i32, i32, i32]
+        L.bm_zgemm_f16x3_ws_bytes.restype = i64
         L.bm_set_precision.argtypes = [vp, i32, ctypes.c_double, i32]
         L.bm_refine_stats.argtypes = [vp, ctypes.POINTER(i32), dp]
         L.bm_problem_bytes.argtypes = [i32, i32, ctypes.POINTER(i64)]
@@ -174,6 +177,12 @@ def fortran_empty(rows, cols, device="cuda", dtype=torch.complex128) -> torch.Te
 def _ld(t: torch.Tensor) -> int:
     if t.dim() != 2 or t.dtype != torch.complex128 or not t.is_cuda or (t.shape[0] > 1 and t.stride(0) != 1):
         raise ValueError("expected a column-major complex128 CUDA matrix")
+    return max(t.stride(1) if t.shape[1] > 1 else t.shape[0], t.shape[0], 1)
+
+
+def _ld64(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.dtype != torch.complex64 or not t.is_cuda or (t.shape[0] > 1 and t.stride(0) != 1):
+        raise ValueError("expected a column-major complex64 CUDA matrix")
     return max(t.stride(1) if t.shape[1] > 1 else t.shape[0], t.shape[0], 1)
 
 
@@ -440,6 +449,24 @@ def zgemm(alpha, A, B, beta, C, stream=None):
     be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
     check(lib().bm_zgemm(_stream_handle(stream), m, n, k, al, _ptr(A), _ld(A), _ptr(B), _ld(B), be, _ptr(C), _ld(C)),
           "bm_zgemm")
+    return C
+
+
+def zgemm_f16x3(alpha, A, B, C, k_chunk=None, stream=None):
+    """C (complex64) = alpha A B (complex128 operands) on the FP16 matrix cores with
+    FP32-level accuracy (split operands); k is taken in chunks of k_chunk (default:
+    all of k at once) through a workspace allocated here."""
+    stream = stream or torch.cuda.current_stream()
+    m, k = A.shape
+    n = B.shape[1]
+    kc = k if k_chunk is None else int(k_chunk)
+    nbytes = lib().bm_zgemm_f16x3_ws_bytes(m, n, k, max(kc, 1))
+    if nbytes < 0:
+        raise BMError(BM_E_ARG, "bm_zgemm_f16x3_ws_bytes")
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    check(lib().bm_zgemm_f16x3(_stream_handle(stream), m, n, k, al, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C),
+                               _ld64(C), _ptr(ws), int(nbytes)), "bm_zgemm_f16x3")
     return C
 
 

@@ -284,10 +284,19 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
     phase_begin(p, BM_PH_SCHUR);
     // (mixed precision: on the FP32 matrix cores, into a complex64 U33 that takes
     // the first half of the factor storage; bm_solve refines against the FP64 blocks)
-    if (p->prec != BM_PREC_FP64)
-      rc = bm_launch_zgemm32_c(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0),
-                               (cplx32 *)p->lu, n);
-    else
+    if (p->prec != BM_PREC_FP64) {
+      // the split-FP16 product where its packed operands fit in the half of the
+      // factor storage the complex64 U33 leaves free, else the FP32 one
+      const size_t half = (size_t)n * n * sizeof(cplx32);
+      char *ws = (char *)p->lu + (half + 255) / 256 * 256;
+      const size_t wsb = 2 * half - (size_t)(ws - (char *)p->lu);
+      if (n >= BM_F16X3_MIN_N && wsb >= bm_zgemm16_ws_bytes(n, n, 16))
+        rc = bm_launch_zgemm16(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, (cplx32 *)p->lu, n,
+                               ws, wsb, nullptr);
+      else
+        rc = bm_launch_zgemm32_c(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0),
+                                 (cplx32 *)p->lu, n);
+    } else
       rc = bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu,
                            n);
     phase_end(p, BM_PH_SCHUR);
@@ -604,6 +613,21 @@ int bm_zgemm_f32(void *hip_stream, int32_t m, int32_t n, int32_t k, const double
   if (lda < m || ldb < k || ldc < m) return BM_E_ARG;
   return bm_launch_zgemm32((hipStream_t)hip_stream, m, n, k, cmk(alpha[0], alpha[1]), (const cplx *)A, lda,
                            (const cplx *)B, ldb, cmk(beta[0], beta[1]), (cplx *)C, ldc);
+}
+
+int bm_zgemm_f16x3(void *hip_stream, int32_t m, int32_t n, int32_t k, const double *alpha, const void *A,
+                   int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc, void *ws, int64_t ws_bytes) {
+  if (m < 0 || n < 0 || k < 0 || !alpha || ws_bytes < 0) return BM_E_ARG;
+  if (m == 0 || n == 0) return BM_OK;
+  if (!C || (k > 0 && (!A || !B)) || !ws) return BM_E_ARG;
+  if (lda < m || ldb < k || ldc < m) return BM_E_ARG;
+  return bm_launch_zgemm16((hipStream_t)hip_stream, m, n, k, cmk(alpha[0], alpha[1]), (const cplx *)A, lda,
+                           (const cplx *)B, ldb, (cplx32 *)C, ldc, ws, (size_t)ws_bytes, nullptr);
+}
+
+int64_t bm_zgemm_f16x3_ws_bytes(int32_t m, int32_t n, int32_t k, int32_t k_chunk) {
+  if (m < 0 || n < 0 || k < 0 || k_chunk < 1) return -1;
+  return (int64_t)bm_zgemm16_ws_bytes(m, n, k_chunk < k ? k_chunk : (k > 0 ? k : 1));
 }
 
 int bm_zgetrf(void *hip_stream, int32_t n, void *A, int64_t lda, int32_t *ipiv, int32_t *info) {

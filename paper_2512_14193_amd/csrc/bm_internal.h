@@ -253,6 +253,13 @@ int bm_launch_zgemm32_c(hipStream_t s, int m, int n, int k, cplx alpha, const cp
                         int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
 int bm_launch_zgemm32_cc(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
                          const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
+// The split-FP16 product into complex64 C (bm_zgemm16.hip): workspace bytes for
+// k chunks of kc, and the launcher (chunks_out: the number of k-chunks taken)
+// (the mixed-precision Schur complement takes it from this N on)
+#define BM_F16X3_MIN_N 256
+size_t bm_zgemm16_ws_bytes(int m, int n, int kc);
+int bm_launch_zgemm16(hipStream_t s, int m, int n, int K, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
+                      int64_t ldb, cplx32 *C, int64_t ldc, void *ws, size_t ws_bytes, int *chunks_out);
 int bm_launch_zgemm_shallow_c64(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
                                 const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
 

@@ -49,6 +49,68 @@ def test_zgemm_f32_vs_numpy(m, n, k, beta):
         assert rel > 1e-12, rel  # the products really ran in FP32
 
 
+@pytest.mark.parametrize("m,n,k,chunk", [(128, 128, 16, None), (130, 77, 45, None), (1, 3, 200, 32),
+                                         (257, 300, 129, None), (257, 300, 129, 48), (33, 1, 1000, 96),
+                                         (256, 384, 2048, None), (256, 384, 2048, 400)])
+def test_zgemm_f16x3_vs_numpy(m, n, k, chunk):
+    """The split-FP16 product (complex64 result) at the accuracy of an FP32 one,
+    normwise, with k in one chunk or several (ragged tiles, ragged k)."""
+    rng = np.random.default_rng(m * 7919 + n * 31 + k + 5)
+    g = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)  # noqa: E731
+    A, Bm = g(m, k), g(k, n)
+    alpha = -0.7 + 0.2j
+    C = torch.full((n, m), 7.0 + 7.0j, dtype=torch.complex64, device="cuda").t()  # column-major, overwritten
+    B.zgemm_f16x3(alpha, to_dev(A), to_dev(Bm), C, k_chunk=chunk)
+    got = to_np(C).astype(np.complex128)
+    ref = alpha * (A @ Bm)
+    rel = np.linalg.norm(got - ref) / (abs(alpha) * np.linalg.norm(A) * np.linalg.norm(Bm))
+    assert rel < 1e-6, rel
+    if k >= 45:
+        assert rel > 1e-12, rel  # not an FP64 product
+
+
+def test_zgemm_f16x3_empty_depth():
+    """k = 0: C = 0 (A and B may be null), and a workspace below one 16-deep
+    chunk is rejected."""
+    import ctypes
+    m, n = 384, 256
+    C = torch.full((n, m), 3.0 + 1.0j, dtype=torch.complex64, device="cuda").t()
+    lib = B.lib()
+    nbytes = lib.bm_zgemm_f16x3_ws_bytes(m, n, 0, 1)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    al = (ctypes.c_double * 2)(1.0, 0.0)
+    cp = ctypes.c_void_p(C.data_ptr())
+    assert lib.bm_zgemm_f16x3(None, m, n, 0, al, None, m, None, 1, cp, m, ctypes.c_void_p(ws.data_ptr()),
+                              int(nbytes)) == B.BM_OK
+    assert not torch.any(C.cpu() != 0)
+    A = to_dev(np.ones((m, 64)))
+    Bm = to_dev(np.ones((64, n)))
+    small = lib.bm_zgemm_f16x3_ws_bytes(m, n, 64, 16) - 256
+    assert lib.bm_zgemm_f16x3(None, m, n, 64, al, ctypes.c_void_p(A.data_ptr()), m, ctypes.c_void_p(Bm.data_ptr()), 64,
+                              cp, m, ctypes.c_void_p(ws.data_ptr()), int(small)) == B.BM_E_ARG
+
+
+def test_zgemm_f16x3_line_scales():
+    """Rows of A and columns of B over 16 and 12 decades: each output row and column
+    keeps FP32-level accuracy relative to its own scale (the per-line powers of two;
+    a single scale for the whole operand would leave the small rows in the FP16
+    subnormals), and entries far beyond the FP16 range do not overflow."""
+    m, n, k = 200, 150, 700
+    rng = np.random.default_rng(12)
+    g = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)  # noqa: E731
+    ra = 10.0 ** rng.uniform(-8, 8, m)
+    cb = 10.0 ** rng.uniform(-6, 6, n)
+    A = g(m, k) * ra[:, None]
+    Bm = g(k, n) * cb[None, :]
+    C = torch.zeros((n, m), dtype=torch.complex64, device="cuda").t()
+    B.zgemm_f16x3(1.0, to_dev(A), to_dev(Bm), C, k_chunk=160)
+    got = to_np(C).astype(np.complex128)
+    ref = A @ Bm
+    scale = np.outer(np.linalg.norm(A, axis=1), np.linalg.norm(Bm, axis=0))
+    err = np.abs(got - ref) / scale
+    assert np.max(err) < 1e-6, np.max(err)
+
+
 CASES = [
     ("disk256", I.disk(256, 1.0), I.Physics.from_wavenumbers(2.0, 3.0)),
     ("star200-complexk", I.star(200), I.Physics.from_wavenumbers(6.0 + 0.4j, 9.0 + 0.6j)),
