@@ -132,8 +132,10 @@ typedef struct {
  * Errors: BM_E_ARG, BM_E_NOMEM, BM_E_HIP. */
 int bm_create(int32_t n, int32_t formulation, void *hip_stream, bm_problem **out);
 
-/* Release the problem and its device memory (after synchronising its stream). */
+/* Release the problem and its device memory (after synchronising its stream).
+ * bm_free is the same call. */
 void bm_destroy(bm_problem *p);
+void bm_free(bm_problem *p);
 
 /* Nystrom assembly (eq. dis_mixedBM / eq. dis_BM; kernels of Sec. 2.2 with
  * G = (i/4) H0^(1)(k|x-y|)).  Mixed: fills Top and Bot.  Ordinary: fills the
@@ -142,6 +144,26 @@ void bm_destroy(bm_problem *p);
  * Errors: BM_E_ARG (null pointers, eps <= 0, Im beta == 0, Re k <= 0 or
  * Im k > Re k / 2); BM_E_DOMAIN later (see bm_params). */
 int bm_assemble(bm_problem *p, const bm_geometry *geometry, const bm_params *params);
+
+/* One-shot form: create a problem for a->n nodes and a->formulation on hip_stream
+ * and assemble it (as bm_create, bm_set_quadrature and bm_assemble), complete on
+ * return.  Without BM_INPUT_DEVICE in a->flags the geometry arrays are host memory,
+ * and so are, for this handle, the arrays of every later bm_assemble, bm_solve,
+ * bm_rhs_plane_wave and bm_far_field call (B, X, theta, F): those calls copy
+ * through device buffers they allocate and return once their outputs are in host
+ * memory.  With BM_INPUT_DEVICE every pointer is a device pointer, as for a handle
+ * from bm_create.  Release with bm_free (or bm_destroy).
+ * Errors: as bm_create and bm_assemble; BM_E_ARG for unknown flags. */
+#define BM_INPUT_DEVICE 1
+typedef struct {
+  int32_t n;            /* nodes N (as bm_create)                                   */
+  int32_t formulation;  /* BM_MIXED or BM_ORDINARY                                  */
+  int32_t quadrature;   /* BM_QUAD_* (0: Kress)                                     */
+  int32_t flags;        /* 0 (host arrays) or BM_INPUT_DEVICE                       */
+  bm_geometry geometry; /* as for bm_assemble: 2N interleaved doubles per array     */
+  bm_params params;
+} bm_assemble_args;
+int bm_assemble_create(const bm_assemble_args *a, void *hip_stream, bm_problem **out);
 
 /* Factorisation.  Mixed (Theorem thm:LU): U33 = -M31 M13 - M32 M23 = -Bot * Top
  * (one complex GEMM, m = n = N, k = 2N), then partial-pivot LU of U33;

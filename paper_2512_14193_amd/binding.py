@@ -29,7 +29,7 @@ BM_MAX_NRHS = 32
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
-            "bm_zgemm_f32", "bm_zgemm_f16x3", "bm_zgemm_f16x3_ws_bytes", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
+            "bm_zgemm_f32", "bm_assemble_create", "bm_free", "bm_zgemm_f16x3", "bm_zgemm_f16x3_ws_bytes", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
             "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
             "bm_set_lu_overlap", "bm_lu_overlap_info",
             "bm_zgetrf_noalloc", "bm_fds_create", "bm_fds_factor", "bm_fds_solve", "bm_fds_rhs_plane_wave",
@@ -46,6 +46,14 @@ class BMParams(ctypes.Structure):
                 ("k1_re", ctypes.c_double), ("k1_im", ctypes.c_double),
                 ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
                 ("beta_re", ctypes.c_double), ("beta_im", ctypes.c_double)]
+
+
+class BMAssembleArgs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("formulation", ctypes.c_int32), ("quadrature", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("geometry", BMGeometry), ("params", BMParams)]
+
+
+BM_INPUT_DEVICE = 1
 
 
 class BMServerConfig(ctypes.Structure):
@@ -115,6 +123,9 @@ def lib():
         L.bm_destroy.argtypes = [vp]
         L.bm_destroy.restype = None
         L.bm_assemble.argtypes = [vp, ctypes.POINTER(BMGeometry), ctypes.POINTER(BMParams)]
+        L.bm_assemble_create.argtypes = [ctypes.POINTER(BMAssembleArgs), vp, ctypes.POINTER(vp)]
+        L.bm_free.argtypes = [vp]
+        L.bm_free.restype = None
         L.bm_block_lu.argtypes = [vp, ctypes.POINTER(i32)]
         L.bm_solve.argtypes = [vp, i32, vp, i64, vp, i64]
         L.bm_rhs_plane_wave.argtypes = [vp, i32, vp, vp, i64]
@@ -341,6 +352,60 @@ class Problem:
         cnt = (ctypes.c_int32 * 6)()
         check(lib().bm_phase_times(self._h, ms, cnt, 6), "bm_phase_times")
         return list(ms), list(cnt)
+
+
+class HostProblem:
+    """A problem made by bm_assemble_create from host arrays (no BM_INPUT_DEVICE):
+    its solve, right-hand-side and far-field calls take and return numpy arrays
+    (column-major complex128), each complete on return.  Argument marshalling
+    only; the work runs in the library on the device."""
+
+    def __init__(self, boundary, physics, formulation: str = "mixed", quadrature: str = "kress"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs on the GPU only")
+        self.n = int(boundary.n_nodes)
+        self.form = {"mixed": BM_MIXED, "ordinary": BM_ORDINARY}[formulation]
+        self.rows = (3 if self.form == BM_MIXED else 2) * self.n
+        self._geo = [np.ascontiguousarray(a, dtype=np.float64) for a in (boundary.x, boundary.dx, boundary.ddx,
+                                                                          boundary.d3x)]
+        g = BMGeometry(*[a.ctypes.data for a in self._geo])
+        a = BMAssembleArgs(self.n, self.form, QUADRATURES[quadrature], 0, g, _params(physics))
+        h = ctypes.c_void_p()
+        check(lib().bm_assemble_create(ctypes.byref(a), None, ctypes.byref(h)), "bm_assemble_create")
+        self._h = h
+        _live.add(self)
+
+    def block_lu(self) -> int:
+        info = ctypes.c_int32(0)
+        check(lib().bm_block_lu(self._h, ctypes.byref(info)), "bm_block_lu")
+        return int(info.value)
+
+    def solve(self, B):
+        B = np.asfortranarray(B, dtype=np.complex128)
+        X = np.zeros_like(B, order="F")
+        check(lib().bm_solve(self._h, B.shape[1], B.ctypes.data, self.rows, X.ctypes.data, self.rows), "bm_solve")
+        return X
+
+    def rhs_plane_wave(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        B = np.zeros((self.rows, th.size), dtype=np.complex128, order="F")
+        check(lib().bm_rhs_plane_wave(self._h, th.size, th.ctypes.data, B.ctypes.data, self.rows),
+              "bm_rhs_plane_wave")
+        return B
+
+    def far_field(self, X, theta):
+        X = np.asfortranarray(X, dtype=np.complex128)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        F = np.zeros((th.size, X.shape[1]), dtype=np.complex128, order="F")
+        check(lib().bm_far_field(self._h, X.shape[1], X.ctypes.data, X.shape[0], th.size, th.ctypes.data,
+                                 F.ctypes.data, th.size), "bm_far_field")
+        return F
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bm_free(self._h)
+            self._h = None
+            _live.discard(self)
 
 
 def _params(physics) -> BMParams:

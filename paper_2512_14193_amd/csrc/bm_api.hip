@@ -152,6 +152,8 @@ void bm_destroy(bm_problem *p) {
   free_problem(p);
 }
 
+void bm_free(bm_problem *p) { bm_destroy(p); }
+
 }  // extern "C"
 
 // Phase timing: each call of a phase records an event pair in a ring of
@@ -224,15 +226,61 @@ int bm_assemble(bm_problem *p, const bm_geometry *g, const bm_params *prm) {
   p->phys.eps1 = prm->eps1;
   phase_begin(p, BM_PH_ASSEMBLE);
   const size_t bytes = sizeof(double) * 2 * (size_t)p->n;
-  BM_HIP_TRY(hipMemcpyAsync(p->geo, g->x, bytes, hipMemcpyDeviceToDevice, p->stream));
-  BM_HIP_TRY(hipMemcpyAsync(p->geo + 2 * p->n, g->dx, bytes, hipMemcpyDeviceToDevice, p->stream));
-  BM_HIP_TRY(hipMemcpyAsync(p->geo + 4 * p->n, g->ddx, bytes, hipMemcpyDeviceToDevice, p->stream));
-  BM_HIP_TRY(hipMemcpyAsync(p->geo + 6 * p->n, g->d3x, bytes, hipMemcpyDeviceToDevice, p->stream));
+  const hipMemcpyKind kind = p->host_io ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  BM_HIP_TRY(hipMemcpyAsync(p->geo, g->x, bytes, kind, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 2 * p->n, g->dx, bytes, kind, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 4 * p->n, g->ddx, bytes, kind, p->stream));
+  BM_HIP_TRY(hipMemcpyAsync(p->geo + 6 * p->n, g->d3x, bytes, kind, p->stream));
   bm_geometry gd = {p->geo, p->geo + 2 * p->n, p->geo + 4 * p->n, p->geo + 6 * p->n};
   int rc = bm_launch_assemble(p, &gd);
   phase_end(p, BM_PH_ASSEMBLE);
   if (rc) return rc;
   p->state = BM_ST_ASSEMBLED;
+  if (p->host_io) BM_HIP_TRY(hipStreamSynchronize(p->stream));  // the host arrays may go
+  return BM_OK;
+}
+
+// Host-array calls of a handle made by bm_assemble_create without BM_INPUT_DEVICE:
+// device copies of the inputs, the device call, the outputs copied back, all
+// complete on return.
+namespace {
+struct dev_buf {
+  void *p = nullptr;
+  ~dev_buf() { (void)hipFree(p); }
+  int alloc(size_t bytes) { return (bytes == 0 || hipMalloc(&p, bytes) == hipSuccess) ? BM_OK : BM_E_NOMEM; }
+};
+int to_dev(bm_problem *p, dev_buf &d, const void *h, size_t rows, size_t cols, int64_t ld, size_t elem) {
+  if (int rc = d.alloc(rows * cols * elem)) return rc;
+  if (rows * cols == 0) return BM_OK;
+  BM_HIP_TRY(hipMemcpy2DAsync(d.p, rows * elem, h, (size_t)ld * elem, rows * elem, cols, hipMemcpyHostToDevice,
+                              p->stream));
+  return BM_OK;
+}
+int to_host(bm_problem *p, void *h, int64_t ld, const dev_buf &d, size_t rows, size_t cols, size_t elem) {
+  if (rows * cols == 0) return BM_OK;
+  BM_HIP_TRY(hipMemcpy2DAsync(h, (size_t)ld * elem, d.p, rows * elem, rows * elem, cols, hipMemcpyDeviceToHost,
+                              p->stream));
+  BM_HIP_TRY(hipStreamSynchronize(p->stream));
+  return BM_OK;
+}
+}  // namespace
+
+int bm_assemble_create(const bm_assemble_args *a, void *hip_stream, bm_problem **out) {
+  if (!out) return BM_E_ARG;
+  *out = nullptr;
+  if (!a || (a->flags & ~BM_INPUT_DEVICE) != 0) return BM_E_ARG;
+  bm_problem *p = nullptr;
+  if (int rc = bm_create(a->n, a->formulation, hip_stream, &p)) return rc;
+  int rc = BM_OK;
+  if (a->quadrature != BM_QUAD_KRESS) rc = bm_set_quadrature(p, a->quadrature);
+  p->host_io = (a->flags & BM_INPUT_DEVICE) ? 0 : 1;
+  if (!rc) rc = bm_assemble(p, &a->geometry, &a->params);
+  if (!rc) rc = bm_sync(p);  // complete on return
+  if (rc) {
+    bm_destroy(p);
+    return rc;
+  }
+  *out = p;
   return BM_OK;
 }
 
@@ -399,6 +447,17 @@ int bm_solve(bm_problem *p, int32_t nrhs, const void *Bv, int64_t ldb, void *Xv,
   if (ldb < rows || ldx < rows) return BM_E_ARG;
   if (Bv == Xv) return BM_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  if (p->host_io) {
+    if (nrhs == 0) return BM_OK;
+    dev_buf db, dx;
+    if (int rc = to_dev(p, db, Bv, rows, nrhs, ldb, sizeof(cplx))) return rc;
+    if (int rc = dx.alloc(sizeof(cplx) * rows * (size_t)nrhs)) return rc;
+    p->host_io = 0;
+    int rc = bm_solve(p, nrhs, db.p, rows, dx.p, rows);
+    p->host_io = 1;
+    if (!rc) rc = to_host(p, Xv, ldx, dx, rows, nrhs, sizeof(cplx));
+    return rc;
+  }
   const cplx *B = (const cplx *)Bv;
   cplx *X = (cplx *)Xv;
   const bool refine = (p->factored_prec == BM_PREC_MIXED);
@@ -513,6 +572,14 @@ int bm_rhs_plane_wave(bm_problem *p, int32_t nrhs, const double *theta_inc, void
   if (ldb < rows) return BM_E_ARG;
   if (nrhs == 0) return BM_OK;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  if (p->host_io) {
+    dev_buf dt, dbuf;
+    if (int rc = to_dev(p, dt, theta_inc, nrhs, 1, nrhs, sizeof(double))) return rc;
+    if (int rc = dbuf.alloc(sizeof(cplx) * rows * (size_t)nrhs)) return rc;
+    int rc = bm_launch_rhs_plane_wave(p, nrhs, (const double *)dt.p, (cplx *)dbuf.p, rows);
+    if (!rc) rc = to_host(p, B, ldb, dbuf, rows, nrhs, sizeof(cplx));
+    return rc;
+  }
   return bm_launch_rhs_plane_wave(p, nrhs, theta_inc, (cplx *)B, ldb);
 }
 
@@ -524,6 +591,18 @@ int bm_far_field(bm_problem *p, int32_t nrhs, const void *X, int64_t ldx, int32_
   if (ldx < 2 * p->n || ldf < nang) return BM_E_ARG;
   if (nrhs == 0 || nang == 0) return BM_OK;
   if (hipSetDevice(p->device) != hipSuccess) return BM_E_HIP;
+  if (p->host_io) {
+    const size_t rx = 2 * (size_t)p->n;  // the traces [u; q] the far field reads
+    dev_buf dxb, dt, df;
+    if (int rc = to_dev(p, dxb, X, rx, nrhs, ldx, sizeof(cplx))) return rc;
+    if (int rc = to_dev(p, dt, theta, nang, 1, nang, sizeof(double))) return rc;
+    if (int rc = df.alloc(sizeof(cplx) * nang * (size_t)nrhs)) return rc;
+    p->host_io = 0;
+    int rc = bm_far_field(p, nrhs, dxb.p, (int64_t)rx, nang, (const double *)dt.p, df.p, nang);
+    p->host_io = 1;
+    if (!rc) rc = to_host(p, F, ldf, df, nang, nrhs, sizeof(cplx));
+    return rc;
+  }
   phase_begin(p, BM_PH_FAR);
   int rc = bm_launch_far_field(p, nrhs, (const cplx *)X, ldx, nang, theta, (cplx *)F, ldf);
   phase_end(p, BM_PH_FAR);

@@ -219,6 +219,7 @@ struct bm_problem {
   int lu_segments;      // column segments of the latest factorisation's product (0: formed in full)
   int ir_dev_stats;     // 1: the latest solve's refinement statistics are on the device
   hipEvent_t after_schur;  // if set: recorded on the stream once U33 is formed in full (request server)
+  int host_io;           // 1: geometry, right-hand sides, solutions and far fields are host arrays
 
   int profiling;
   hipEvent_t ev[BM_NPHASE][BM_EV_RING][2];
