@@ -178,6 +178,20 @@ int bm_assemble_create(const bm_assemble_args *a, void *hip_stream, bm_problem *
  * Errors: BM_E_STATE before bm_assemble, BM_E_DEVICE. */
 int bm_block_lu(bm_problem *p, int32_t *info);
 
+/* The same factorisation for `count` (1..BM_LU_BATCH_MAX) problems of one order N
+ * (mixed formulation, FP64, assembled, the same device and stream), factored
+ * together: each Schur complement as in bm_block_lu (U33 formed in full before its
+ * LU), then one LU in which every panel, interchange and update launch covers all
+ * of the problems, so that the CUs one problem's panel chain leaves idle serve the
+ * others (the panels of the batch together need count * ceil(N / 64) workgroups
+ * resident, at most the CU count).  Each problem gets bitwise the factors that
+ * bm_block_lu without the segmented product gives it.  info: NULL (asynchronous)
+ * or a host array of count entries, filled as bm_block_lu's (then it waits).
+ * Errors: BM_E_ARG (count, differing N, device or stream, a repeated or ordinary or
+ * mixed-precision problem, too many panel workgroups), BM_E_STATE. */
+#define BM_LU_BATCH_MAX 4
+int bm_block_lu_batch(bm_problem *const *ps, int32_t count, int32_t *info);
+
 /* Solve for `nrhs` right-hand sides (Corollary lem:for_ssm_RHS for the mixed
  * form):  z3 = U33^{-1} (b3 - M31 b1 - M32 b2),  x1 = b1 - M13 z3,
  * x2 = b2 - M23 z3,  x3 = z3.  B and X are (3N | 2N) x nrhs, column-major,

@@ -29,7 +29,7 @@ BM_MAX_NRHS = 32
 EXPORTED = ["bm_create", "bm_destroy", "bm_assemble", "bm_block_lu", "bm_solve", "bm_rhs_plane_wave",
             "bm_far_field", "bm_copy_blocks", "bm_copy_factors", "bm_sync", "bm_set_profiling",
             "bm_phase_times", "bm_zgemm", "bm_zgetrf", "bm_strerror", "bm_set_precision", "bm_refine_stats",
-            "bm_zgemm_f32", "bm_assemble_create", "bm_free", "bm_zgemm_f16x3", "bm_zgemm_f16x3_ws_bytes", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
+            "bm_zgemm_f32", "bm_block_lu_batch", "bm_assemble_create", "bm_free", "bm_zgemm_f16x3", "bm_zgemm_f16x3_ws_bytes", "bm_problem_bytes", "bm_server_create", "bm_server_submit", "bm_server_wait",
             "bm_server_cancel", "bm_server_stats", "bm_server_destroy", "bm_block_moments", "bm_set_quadrature",
             "bm_set_lu_overlap", "bm_lu_overlap_info",
             "bm_zgetrf_noalloc", "bm_fds_create", "bm_fds_factor", "bm_fds_solve", "bm_fds_rhs_plane_wave",
@@ -127,6 +127,7 @@ def lib():
         L.bm_free.argtypes = [vp]
         L.bm_free.restype = None
         L.bm_block_lu.argtypes = [vp, ctypes.POINTER(i32)]
+        L.bm_block_lu_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32)]
         L.bm_solve.argtypes = [vp, i32, vp, i64, vp, i64]
         L.bm_rhs_plane_wave.argtypes = [vp, i32, vp, vp, i64]
         L.bm_far_field.argtypes = [vp, i32, vp, i64, i32, vp, vp, i64]
@@ -352,6 +353,18 @@ class Problem:
         cnt = (ctypes.c_int32 * 6)()
         check(lib().bm_phase_times(self._h, ms, cnt, 6), "bm_phase_times")
         return list(ms), list(cnt)
+
+
+BM_LU_BATCH_MAX = 4
+
+
+def block_lu_batch(problems, sync: bool = True):
+    """bm_block_lu_batch over Problem objects of one order (same stream): their
+    factorisations in shared launches; returns the infos when sync."""
+    hs = (ctypes.c_void_p * len(problems))(*[p._h.value for p in problems])
+    info = (ctypes.c_int32 * len(problems))() if sync else None
+    check(lib().bm_block_lu_batch(hs, len(problems), info), "bm_block_lu_batch")
+    return list(info) if sync else None
 
 
 class HostProblem:

@@ -374,6 +374,54 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   return BM_OK;
 }
 
+int bm_block_lu_batch(bm_problem *const *ps, int32_t count, int32_t *info) {
+  if (!ps || count < 1 || count > BM_LU_BATCH_MAX) return BM_E_ARG;
+  for (int b = 0; b < count; ++b) {
+    bm_problem *p = ps[b];
+    if (!p || p->form != BM_MIXED || p->prec != BM_PREC_FP64) return BM_E_ARG;
+    if (p->n != ps[0]->n || p->device != ps[0]->device || p->stream != ps[0]->stream) return BM_E_ARG;
+    for (int c = 0; c < b; ++c)
+      if (ps[c] == p) return BM_E_ARG;
+    if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
+  }
+  bm_problem *p0 = ps[0];
+  if (hipSetDevice(p0->device) != hipSuccess) return BM_E_HIP;
+  const int n = p0->n;
+  const hipStream_t st = p0->stream;
+  cplx *A[BM_LU_BATCH_MAX];
+  int32_t *ipiv[BM_LU_BATCH_MAX], *err[BM_LU_BATCH_MAX];
+  bm_getrf_ws *ws[BM_LU_BATCH_MAX];
+  for (int b = 0; b < count; ++b) {
+    bm_problem *p = ps[b];
+    if (int rc0 = bm_launch_ir_reset(st, p->ir_norm + 2 * BM_MAX_NRHS, p->dev_err + 3, 0)) return rc0;
+    // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
+    if (int rc0 = bm_launch_zgemm(st, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu,
+                                  n))
+      return rc0;
+    if (p->after_schur) BM_HIP_TRY(hipEventRecord(p->after_schur, st));
+    p->lu_segments = 0;
+    A[b] = p->lu;
+    ipiv[b] = p->ipiv;
+    err[b] = p->dev_err;
+    ws[b] = p->gws;
+  }
+  if (int rc0 = bm_getrf_run_batch(st, n, count, A, n, ipiv, err, ws)) return rc0;
+  for (int b = 0; b < count; ++b) {
+    bm_problem *p = ps[b];
+    if (int rc0 = bm_launch_diag_inverses(st, n, p->lu, n, p->dinv)) return rc0;
+    if (int rc0 = bm_launch_perm(st, p->gws, n, p->perm)) return rc0;
+    p->state = BM_ST_FACTORED;
+    p->factored_prec = BM_PREC_FP64;
+  }
+  if (!info) return BM_OK;
+  int status = BM_OK;
+  for (int b = 0; b < count; ++b) {
+    const int rc0 = read_dev_err(ps[b], &info[b]);
+    if (rc0 && !status) status = rc0;
+  }
+  return status;
+}
+
 // One pass of the direct solve for nr <= BM_MAX_NRHS right-hand sides (X may
 // not alias B).  Mixed form, Corollary lem:for_ssm_RHS.
 static int solve_pass(bm_problem *p, int nr, const cplx *Bc, int64_t ldb, cplx *Xc, int64_t ldx) {

@@ -210,10 +210,23 @@ __device__ inline pdbl4 pmfma16(double a, double b, pdbl4 c) {
 // of these columns (U12 itself) are written back by workgroup 0 at the end, when
 // every workgroup has long finished reading the old values (it has published its
 // candidate of column 0, which workgroup 0 waited for).  RPL = 1 and P >= 10 only.
-template <int RPL, bool FUSE, class T>
+// (BAT: a batch of problems, blockIdx.y selecting the problem's matrix, pivots,
+// flags, exchange slots and interchange list from bb)
+template <int RPL, bool FUSE, class T, bool BAT = false>
 __global__ __launch_bounds__(SNT) void panel_kernel(int N, T *A, long lda, int j, int jb, int P, int32_t *ipiv,
                                                     int32_t *dev_err, cplx *slots, cplx *next_slots, int next_P,
-                                                    int next_jb, int32_t *swp, int j0, const int32_t *swp0) {
+                                                    int next_jb, int32_t *swp, int j0, const int32_t *swp0,
+                                                    bm_lu_batch bb) {
+  if constexpr (BAT) {
+    static_assert(!FUSE && sizeof(T) == sizeof(cplx), "batched panels: FP64 storage, no fused update");
+    const int b = blockIdx.y;
+    A = (T *)bb.A[b];
+    ipiv = bb.ipiv[b];
+    dev_err = bb.err[b];
+    slots = bb.cur[b];
+    next_slots = bb.nxt[b];
+    swp = bb.swp[b];
+  }
   constexpr int RPW = 64 * RPL;  // rows per workgroup
   constexpr int LDP = RPW + 1;   // column stride of the LDS panel (odd: conflict-free row reads)
   extern __shared__ cplx pan[];  // jb x LDP
@@ -794,9 +807,13 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, T *A, long lda, int j
 #define ST_NPAIR (2 * LU_NB)  // at most 2 jb rows change place
 #define ST_LDS(cw) ((size_t)(LU_NB * LU_NB + (cw) * LU_NB) * sizeof(cplx))
 
-template <int CW, class T>
+template <int CW, class T, bool BAT = false>
 __global__ __launch_bounds__(256) void swap_trsm_kernel(T *A, long lda, int j, int jb, int lcols, int c0, int c1,
-                                                        const int32_t *swp, int nleft) {
+                                                        const int32_t *swp, int nleft, bm_lu_batch bb) {
+  if constexpr (BAT) {
+    A = (T *)bb.A[blockIdx.y];
+    swp = bb.swp[blockIdx.y];
+  }
   extern __shared__ cplx sm[];
   __shared__ int s_pair[2 * ST_NPAIR];  // (dst, src) rows of the interchange
   const int np = swp[0];
@@ -960,12 +977,13 @@ __global__ void diag_inv_kernel(int n, const TS *LU, long ld, cplx *dinv);
 
 template <class T>
 using panel_fn = void (*)(int, T *, long, int, int, int, int32_t *, int32_t *, cplx *, cplx *, int, int, int32_t *,
-                          int, const int32_t *);
+                          int, const int32_t *, bm_lu_batch);
 // 64 and 128 rows per workgroup; 64 rows with the previous panel's update fused
 // (FP64 storage only)
 static const panel_fn<cplx> panel_fns[3] = {panel_kernel<1, false, cplx>, panel_kernel<2, false, cplx>,
                                             panel_kernel<1, true, cplx>};
 static const panel_fn<cplx32> panel_fns_c64[2] = {panel_kernel<1, false, cplx32>, panel_kernel<2, false, cplx32>};
+static const panel_fn<cplx> panel_fns_bat[2] = {panel_kernel<1, false, cplx, true>, panel_kernel<2, false, cplx, true>};
 static const void *panel_fn_of(const cplx *, int k) { return (const void *)panel_fns[k]; }
 static const void *panel_fn_of(const cplx32 *, int k) { return (k < 2) ? (const void *)panel_fns_c64[k] : nullptr; }
 
@@ -1012,15 +1030,19 @@ int bm_getrf_prepare() {
   int dev = 0;
   BM_HIP_TRY(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !panel_attr_done[dev]) {
-    const void *big[] = {(const void *)panel_fns[0], (const void *)panel_fns[1], (const void *)panel_fns[2],
-                         (const void *)panel_fns_c64[0], (const void *)panel_fns_c64[1]};
+    const void *big[] = {(const void *)panel_fns[0],     (const void *)panel_fns[1],
+                         (const void *)panel_fns[2],     (const void *)panel_fns_c64[0],
+                         (const void *)panel_fns_c64[1], (const void *)panel_fns_bat[0],
+                         (const void *)panel_fns_bat[1]};
     for (const void *f : big)
       BM_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PANEL_LDS_ALLOC));
     const void *st_next[] = {(const void *)swap_trsm_kernel<ST_CW_NEXT, cplx>,
-                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx32>};
+                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx32>,
+                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx, true>};
     const void *st_rest[] = {(const void *)swap_trsm_kernel<ST_CW_REST, cplx>,
-                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx32>};
-    for (int t = 0; t < 2; ++t) {
+                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx32>,
+                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx, true>};
+    for (int t = 0; t < 3; ++t) {
       BM_HIP_TRY(hipFuncSetAttribute(st_next[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_NEXT)));
       BM_HIP_TRY(hipFuncSetAttribute(st_rest[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_REST)));
     }
@@ -1059,10 +1081,10 @@ static int lu_update(hipStream_t st, T *A, long lda, int n, int j, int jb, const
   if (nleft + nright > 0) {
     if (next)
       hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_NEXT, T>), dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_NEXT), st, A,
-                         lda, j, jb, lcols, c0, c1, swp, nleft);
+                         lda, j, jb, lcols, c0, c1, swp, nleft, bm_lu_batch{});
     else
       hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_REST, T>), dim3(nleft + nright), dim3(256), ST_LDS(ST_CW_REST), st, A,
-                         lda, j, jb, lcols, c0, c1, swp, nleft);
+                         lda, j, jb, lcols, c0, c1, swp, nleft, bm_lu_batch{});
     BM_HIP_TRY(hipGetLastError());
   }
   const int nr = n - j - jb, jn = j + jb;
@@ -1134,7 +1156,8 @@ static int lu_panel(hipStream_t s, int n, T *A, int64_t lda, int32_t *ipiv, int3
   const bool fuse = lu_fused(overlap, shape, pi);
   int j0 = fuse ? j - LU_NB : 0;
   const int32_t *swp0 = fuse ? w->swp + (size_t)(pi - 1) * SWP_STRIDE : swp;
-  void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp, &j0, &swp0};
+  bm_lu_batch bb{};
+  void *args[] = {&nn, &A, &ldal, &jj, &jbb, &P, &ipiv, &dev_err, &cur, &nxt, &next_P, &next_jb, &swp, &j0, &swp0, &bb};
   const int rpl = shape[3 * pi];
   if (w->prof) bm_phase_begin(w->prof, BM_PH_PANEL);
   BM_HIP_TRY(hipLaunchKernel(panel_fn_of(A, fuse ? 2 : rpl - 1), dim3(P), dim3(SNT), args, PANEL_LDS_ALLOC, s));
@@ -1185,6 +1208,92 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
 int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                      bm_getrf_ws *w) {
   return getrf_run(s, n, A, lda, ipiv, dev_err, w, 1);
+}
+
+// ---------------------------------------------------------------------------
+// The LU of a batch of problems of one order: the single-problem sequence (panel,
+// the next panel's update on s, the other columns' update on the second stream),
+// each launch covering every problem (blockIdx.y), so that the CUs one problem's
+// panel chain leaves idle work on the others.  Every problem sees the kernels and
+// the arithmetic of its own factorisation (bitwise the same factors).
+// ---------------------------------------------------------------------------
+static int lu_update_batch(hipStream_t st, int count, const bm_lu_batch &bb, long lda, int n, int j, int jb,
+                           int lcols, int c0, int c1, bool next) {
+  const int cw = next ? ST_CW_NEXT : ST_CW_REST;
+  const int nleft = (lcols + SWAP_COLS - 1) / SWAP_COLS, nright = (c1 > c0) ? (c1 - c0 + cw - 1) / cw : 0;
+  if (nleft + nright > 0) {
+    const dim3 grid(nleft + nright, count);
+    if (next)
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_NEXT, cplx, true>), grid, dim3(256), ST_LDS(ST_CW_NEXT), st,
+                         (cplx *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
+    else
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_REST, cplx, true>), grid, dim3(256), ST_LDS(ST_CW_REST), st,
+                         (cplx *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
+    BM_HIP_TRY(hipGetLastError());
+  }
+  const int nr = n - j - jb, jn = j + jb;
+  if (nr > 0 && c1 > c0)
+    return bm_launch_zgemm_lu_batch(st, count, bb, nr, c1 - c0, jb, jn + (long)j * lda, lda, j + (long)c0 * lda, lda,
+                                    jn + (long)c0 * lda, lda);
+  return BM_OK;
+}
+
+int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t lda, int32_t *const *ipiv,
+                       int32_t *const *dev_err, bm_getrf_ws *const *ws) {
+  if (count < 1 || count > BM_LU_BATCH_MAX || n < 1 || lda < n) return BM_E_ARG;
+  for (int b = 0; b < count; ++b)
+    if (!ws[b] || ws[b]->n < n || !A[b] || !ipiv[b] || !dev_err[b]) return BM_E_ARG;
+  int shape[3 * 1024];
+  int ncu = 0;
+  for (int b = 0; b < count; ++b)  // per problem: flags and the first panel's exchange words
+    if (int rc0 = lu_begin(s, n, dev_err[b], ws[b], shape, &ncu)) return rc0;
+  // every workgroup of a batched panel must be resident at once
+  if ((long)count * shape[1] > ncu) return BM_E_ARG;
+  bm_getrf_ws *w = ws[0];
+  const bool la = w->aux != nullptr;
+  bm_lu_batch bb{};
+  for (int b = 0; b < count; ++b) {
+    bb.A[b] = A[b];
+    bb.ipiv[b] = ipiv[b];
+    bb.err[b] = dev_err[b];
+  }
+  const long ldal = (long)lda;
+  const int npanel = (n + LU_NB - 1) / LU_NB;
+  for (int j = 0, pi = 0; j < n; j += LU_NB, ++pi) {
+    const int jb = (n - j < LU_NB) ? n - j : LU_NB;
+    int P = shape[3 * pi + 1], next_P = 0, next_jb = 0;
+    if (pi + 1 < npanel) {
+      next_jb = (n - j - LU_NB < LU_NB) ? n - j - LU_NB : LU_NB;
+      next_P = shape[3 * (pi + 1) + 1];
+    }
+    for (int b = 0; b < count; ++b) {
+      bb.cur[b] = ws[b]->slots + (size_t)(pi & 1) * SLOT_ELEMS;
+      bb.nxt[b] = ws[b]->slots + (size_t)((pi + 1) & 1) * SLOT_ELEMS;
+      bb.swp[b] = ws[b]->swp + (size_t)pi * SWP_STRIDE;
+    }
+    {
+      int nn = n, jj = j, jbb = jb, j0 = 0;
+      cplx *a0 = nullptr, *c0p = nullptr, *c1p = nullptr;
+      int32_t *p0 = nullptr, *e0 = nullptr, *s0 = nullptr;
+      const int32_t *sw0 = nullptr;
+      void *args[] = {&nn, &a0, (void *)&ldal, &jj, &jbb, &P, &p0, &e0, &c0p, &c1p, &next_P, &next_jb, &s0, &j0,
+                      &sw0, &bb};
+      BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns_bat[shape[3 * pi] - 1], dim3(P, count), dim3(SNT), args,
+                                 PANEL_LDS_ALLOC, s));
+    }
+    const int nr = n - j - jb;
+    const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;
+    if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+    if (int rc = lu_update_batch(s, count, bb, ldal, n, j, jb, 0, jn, jn + jbn, true)) return rc;
+    if (la) {
+      BM_HIP_TRY(hipEventRecord(w->e_next, s));
+      BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+    }
+    if (int rc = lu_update_batch(la ? w->aux : s, count, bb, ldal, n, j, jb, j, jn + jbn, n, false)) return rc;
+    if (la) BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
+  }
+  if (la && npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
+  return BM_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -254,6 +254,17 @@ int bm_launch_zgemm32_c(hipStream_t s, int m, int n, int k, cplx alpha, const cp
                         int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
 int bm_launch_zgemm32_cc(hipStream_t s, int m, int n, int k, cplx alpha, const cplx32 *A, int64_t lda,
                          const cplx32 *B, int64_t ldb, cplx beta, cplx32 *C, int64_t ldc);
+// Per-problem pointers of a batched LU launch (blockIdx.y selects the problem):
+// same order, same leading dimension, one workspace each
+struct bm_lu_batch {  // (BM_LU_BATCH_MAX: include/bm.h)
+  cplx *A[BM_LU_BATCH_MAX];
+  int32_t *ipiv[BM_LU_BATCH_MAX], *err[BM_LU_BATCH_MAX], *swp[BM_LU_BATCH_MAX];
+  cplx *cur[BM_LU_BATCH_MAX], *nxt[BM_LU_BATCH_MAX];  // the panel's exchange-slot buffers
+};
+// C -= A B for every problem of a batch, the operands at element offsets oa, ob,
+// oc of that problem's matrix (the kernels and tiling of bm_launch_zgemm)
+int bm_launch_zgemm_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                             long lda, long ob, long ldb, long oc, long ldc);
 // The split-FP16 product into complex64 C (bm_zgemm16.hip): workspace bytes for
 // k chunks of kc, and the launcher (chunks_out: the number of k-chunks taken)
 // (the mixed-precision Schur complement takes it from this N on)
@@ -336,6 +347,11 @@ int bm_getrf_run(hipStream_t s, int n, cplx *A, int64_t lda, int32_t *ipiv, int3
 // on the FP32 matrix cores)
 int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv, int32_t *dev_err,
                      bm_getrf_ws *w);
+// The LU of `count` (<= BM_LU_BATCH_MAX) matrices of the same order n and leading
+// dimension, each launch covering all of them; ws[b] is problem b's workspace and
+// ws[0]'s second stream and events order the lookahead
+int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t lda, int32_t *const *ipiv,
+                       int32_t *const *dev_err, bm_getrf_ws *const *ws);
 // Per 64-row block b, BM_DINV_TILES column-major 64 x 64 tiles at dinv + b * BM_DINV_TILES * 4096:
 //   Linv_b, Uinv_b, WL_b = Linv_b L(b, b - 1) (b > 0), WU_b = Uinv_b U(b, b + 1) (b < last)
 #define BM_DINV_TILES 4

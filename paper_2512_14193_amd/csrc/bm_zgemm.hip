@@ -328,15 +328,14 @@ int bm_launch_zgemm_batched(hipStream_t s, int count, const bm_gemm_desc *d_dev,
 #define GS_K 64
 // (T: the storage of all three operands, complex128 or complex64; FP64 arithmetic)
 template <class T>
-__global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k, cplx alpha,
-                                                            const T *__restrict__ A, long lda,
-                                                            const T *__restrict__ B, long ldb, cplx beta,
-                                                            T *__restrict__ C, long ldc, int tiles_m) {
+__device__ __forceinline__ void shallow_tile(int tile, int m, int n, int k, cplx alpha, const T *__restrict__ A,
+                                             long lda, const T *__restrict__ B, long ldb, cplx beta,
+                                             T *__restrict__ C, long ldc, int tiles_m) {
   __shared__ cplx As[GS_K][GS_T];
   __shared__ cplx Bs[GS_K][GS_T + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int row0 = (blockIdx.x % tiles_m) * GS_T, col0 = (blockIdx.x / tiles_m) * GS_T;
+  const int row0 = (tile % tiles_m) * GS_T, col0 = (tile / tiles_m) * GS_T;
   constexpr int GU = GS_K * GS_T / 256;
   st_v2 av_[GU], bv_[GU];  // every load of the stage in flight together
 #pragma unroll
@@ -385,6 +384,49 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
       st_z(C, row + (long)col * ldc, to_v2(out));
     }
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k, cplx alpha,
+                                                            const T *__restrict__ A, long lda,
+                                                            const T *__restrict__ B, long ldb, cplx beta,
+                                                            T *__restrict__ C, long ldc, int tiles_m) {
+  shallow_tile<T>(blockIdx.x, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
+}
+
+// The LU's k <= 64 updates C -= A B for a batch of problems (blockIdx.y), each
+// operand at an element offset into that problem's matrix: the same tiles as the
+// single-problem kernels
+__global__ __launch_bounds__(256) void zgemm_shallow_batch_kernel(bm_lu_batch bb, int m, int n, int k, long oa,
+                                                                  long lda, long ob, long ldb, long oc, long ldc,
+                                                                  int tiles_m) {
+  cplx *M = bb.A[blockIdx.y];
+  shallow_tile<cplx>(blockIdx.x, m, n, k, cmk(-1.0, 0.0), M + oa, lda, M + ob, ldb, cmk(1.0, 0.0), M + oc, ldc,
+                     tiles_m);
+}
+__global__ __launch_bounds__(256, GM_OCC) void zgemm_update_batch_kernel(bm_lu_batch bb, int m, int n, int k, long oa,
+                                                                         long lda, long ob, long ldb, long oc, long ldc,
+                                                                         int tiles_m) {
+  cplx *M = bb.A[blockIdx.y];
+  zgemm_tile<false, false>(blockIdx.x, m, n, k, cmk(-1.0, 0.0), M + oa, lda, M + ob, ldb, cmk(1.0, 0.0), M + oc, ldc,
+                           tiles_m);
+}
+
+int bm_launch_zgemm_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                             long lda, long ob, long ldb, long oc, long ldc) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  if (count < 1 || count > BM_LU_BATCH_MAX || k > GM_3M_MIN_K - 1) return BM_E_ARG;
+  if (k <= GS_K && n <= 64) {
+    const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
+    hipLaunchKernelGGL(zgemm_shallow_batch_kernel, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n, k, oa,
+                       lda, ob, ldb, oc, ldc, tm);
+  } else {
+    const int tm = (m + GM_BM - 1) / GM_BM, tn = (n + GM_BN - 1) / GM_BN;
+    hipLaunchKernelGGL(zgemm_update_batch_kernel, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n, k, oa,
+                       lda, ob, ldb, oc, ldc, tm);
+  }
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
 }
 
 int bm_launch_zgemm(hipStream_t s, int m, int n, int k, cplx alpha, const cplx *A, int64_t lda, const cplx *B,
