@@ -252,7 +252,7 @@ def cpu_baseline(w, X_gpu=None, F_gpu=None):
     return out
 
 
-def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
+def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n, batch_max=2):
     """The served contour sweep (256 requests on 8 circles |k - c| = 0.5, stars
     with N in {512, ..., 4096}, 16 probing right-hand sides each) through the
     request server: closed-loop capacity (all requests queued at once, with and
@@ -325,15 +325,22 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
                        "Poisson arrivals",
            "sizes_per_contour": [int(n) for n in sw.sizes], "requests": len(sw.requests), "nrhs": sw.n_rhs,
            "rate_req_per_s": rate, "max_inflight_per_lane": max_inflight, "graph_max_n": graph_max_n,
-           "lanes": lanes, "concurrent_max_n": concurrent_max_n}
+           "lanes": lanes, "concurrent_max_n": concurrent_max_n, "batch_max": batch_max}
     srv = B.Server(max_inflight=max_inflight, graph_max_n=0, lanes=1)
     warm(srv)
     out["closed_loop_one_lane_eager"] = summary(run(srv, False))
     srv.close()
+    if batch_max > 1:  # the same server factoring one request at a time
+        srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
+                       concurrent_max_n=concurrent_max_n)
+        warm(srv, lanes)
+        out["closed_loop_unbatched"] = summary(run(srv, False))
+        srv.close()
     srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
-                   concurrent_max_n=concurrent_max_n)
+                   concurrent_max_n=concurrent_max_n, batch_max=batch_max)
     warm(srv, lanes)
     closed = run(srv, False)
+    out["batched_requests"] = int(sum(x["batched"] > 1 for x in closed))
     out["closed_loop"] = summary(closed)
     out["capacity_req_per_s"] = out["closed_loop"]["throughput_req_per_s"]
     sample = [0, 1, 2, 3, len(Xs) - 1]
@@ -343,9 +350,9 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n):
     out["bitwise_repeatable"] = all(torch.equal(Xs[i], b) for i, b in zip(sample, before))
     out["server_stats"] = srv.stats()
     srv.close()
-    # the same sweep in mixed precision (FP32 Schur complement and trailing updates,
-    # refinement decided on the device: 2 passes, target 1e-10), against the FP64
-    # served solutions
+    # the same sweep in mixed precision (split-FP16 Schur complement, complex64 LU,
+    # refinement decided on the device: 2 passes, target 1e-10; one request at a
+    # time per lane), against the FP64 served solutions
     fp64 = [x.clone() for x in Xs]
     srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
                    concurrent_max_n=concurrent_max_n, precision="mixed", refine_steps=2, refine_tol=1e-10)
@@ -436,6 +443,8 @@ def main():
     ap.add_argument("--serving-inflight", type=int, default=4)
     ap.add_argument("--serving-lanes", type=int, default=4)
     ap.add_argument("--serving-concurrent-max-n", type=int, default=2048)
+    ap.add_argument("--serving-batch-max", type=int, default=2,
+                    help="queued FP64 requests of one N factored together (1: one at a time)")
     ap.add_argument("--no-ssm", action="store_true", help="skip the Sakurai-Sugiura eigenvalue section")
     ap.add_argument("--no-fds", action="store_true", help="skip the fast direct solver section (N = 65536)")
     ap.add_argument("--fds-steps", type=int, default=3)
@@ -552,7 +561,8 @@ def main():
         rec["mixed_precision"] = mixed_precision_section(args.mixed_workload, args.mixed_steps, 1, args.mixed_tol)
     if not args.no_serving:
         rec["serving"] = serving_section(args.serving_rate, args.serving_graph_max_n, args.serving_inflight,
-                                         args.serving_lanes, args.serving_concurrent_max_n)
+                                         args.serving_lanes, args.serving_concurrent_max_n,
+                                         args.serving_batch_max)
     if not args.no_ssm:
         rec["ssm"] = ssm_section(args.ssm_n, args.ssm_per_side, args.ssm_quadrature)
     if not args.no_fds:

@@ -414,6 +414,13 @@ typedef struct {
                                 BM_E_NOCONV)                                        */
   int32_t refine_steps;      /* correction passes of BM_PREC_MIXED_DEVICE; <= 0: 2   */
   double refine_tol;         /* relative residual target; <= 0: 1e-12               */
+  int32_t batch_max;         /* FP64: up to this many queued requests of one N
+                                (<= BM_LU_BATCH_MAX, no reuse key) are factored
+                                together on one lane (bm_block_lu_batch), as many
+                                as their panels fit a lane's share of the panel
+                                workgroups, CUs / 2 / lanes: at N = 1024 two with
+                                4 lanes, four with 2.  Each gets bitwise its own
+                                factors.  <= 1: one at a time                      */
 } bm_server_config;
 
 /* One request.  Device arrays: the geometry (as bm_assemble), B (3N x nrhs,
@@ -442,12 +449,15 @@ typedef struct {
   double t_start;            /* ... the request's work was enqueued on the device */
   double t_done;             /* ... the server saw the request's work complete    */
   double device_ms;          /* device time of the request's work (HIP events)    */
+  int32_t batched;           /* requests factored together with it (itself counted;
+                                1: alone), see config.batch_max                    */
 } bm_request_result;
 
 typedef struct {
   int64_t submitted, completed, failed, rejected, canceled;
   int64_t handles_created, evictions, factor_reuses, graph_launches;
   int64_t handles_live, bytes_live, bytes_peak, budget;
+  int64_t batched;           /* requests factored in a batch of two or more       */
 } bm_server_counters;
 
 /* Create a server on the current HIP device (cfg may be NULL for defaults).

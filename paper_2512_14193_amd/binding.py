@@ -60,7 +60,7 @@ class BMServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("graph_max_n", ctypes.c_int32), ("lanes", ctypes.c_int32), ("concurrent_max_n", ctypes.c_int32),
                 ("quadrature", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double)]
+                ("refine_tol", ctypes.c_double), ("batch_max", ctypes.c_int32)]
 
 
 class BMRequest(ctypes.Structure):
@@ -72,7 +72,7 @@ class BMRequest(ctypes.Structure):
 class BMRequestResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reused_factors", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
-                ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double), ("batched", ctypes.c_int32)]
 
 
 class BMFdsConfig(ctypes.Structure):
@@ -83,7 +83,7 @@ class BMFdsConfig(ctypes.Structure):
 class BMServerCounters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "submitted", "completed", "failed", "rejected", "canceled", "handles_created", "evictions",
-        "factor_reuses", "graph_launches", "handles_live", "bytes_live", "bytes_peak", "budget")]
+        "factor_reuses", "graph_launches", "handles_live", "bytes_live", "bytes_peak", "budget", "batched")]
 
 
 class BMError(RuntimeError):
@@ -444,15 +444,16 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 0, max_inflight: int = 4, graph_max_n: int = 0, lanes: int = 4,
                  concurrent_max_n: int = 1024, quadrature: str = "kress", precision: str = "fp64",
-                 refine_steps: int = 2, refine_tol: float = 1e-12):
-        """precision "fp64" or "mixed" (FP32 Schur complement, refinement decided on
-        the device: refine_steps passes, target refine_tol)."""
+                 refine_steps: int = 2, refine_tol: float = 1e-12, batch_max: int = 1):
+        """precision "fp64" or "mixed" (split-FP16 Schur complement, refinement decided
+        on the device: refine_steps passes, target refine_tol).  batch_max: queued
+        requests of one N factored together (FP64; see bm_server_config)."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs on the GPU only")
         prec = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED_DEVICE}[precision]
         cfg = BMServerConfig(int(hbm_budget_bytes), int(max_inflight), int(graph_max_n), int(lanes),
                              int(concurrent_max_n), QUADRATURES[quadrature], prec, int(refine_steps),
-                             float(refine_tol))
+                             float(refine_tol), int(batch_max))
         h = ctypes.c_void_p()
         check(lib().bm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bm_server_create")
         self._h = h
@@ -488,7 +489,7 @@ class Server:
 
     def wait(self, ticket: int, timeout: float = -1.0) -> dict:
         """Result of a request as a dict (status, reused_factors, graph, n,
-        t_submit, t_start, t_done, device_ms); raises BMError(BM_E_TIMEOUT)."""
+        t_submit, t_start, t_done, device_ms, batched); raises BMError(BM_E_TIMEOUT)."""
         res = BMRequestResult()
         check(lib().bm_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(res)),
               "bm_server_wait")

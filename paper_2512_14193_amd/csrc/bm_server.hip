@@ -22,6 +22,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -44,6 +45,7 @@ struct srv_handle {
   int lane = 0;
   int n = 0;
   uint64_t key = 0;
+  int bslot = 0;           // position in a batched factorisation (one handle each)
   int64_t bytes = 0;
   bool factored = false;   // factors for `prm` are (or will be, in stream order) held
   bm_params prm{};
@@ -85,6 +87,8 @@ struct bm_server {
   int max_inflight = 4;        // per lane
   int graph_max_n = 0;
   int concurrent_max_n = 0;
+  int batch_max = 1;       // requests of one N factored together (FP64)
+  int ncu = 0;
   int quad = BM_QUAD_KRESS;    // quadrature of every handle
   int prec = BM_PREC_FP64;     // precision of every handle (FP64 or mixed, refined on the device)
   int refine_steps = 2;
@@ -136,6 +140,17 @@ void release_handle(srv_handle *h) {
 }
 
 bool is_small(const bm_server *s, int n) { return s->lanes.size() > 1 && n <= s->concurrent_max_n; }
+// workgroups of the widest panel of an N-node factorisation (64 rows each up to
+// 32 workgroups, then 128)
+int panel_p(int n) { return (n <= 64 * 32) ? (n + 63) / 64 : (n + 127) / 128; }
+// requests of N nodes that may be factored together: their panels within one
+// lane's share of the panel workgroups all lanes may hold, half the CUs
+int batch_limit(const bm_server *s, int n) {
+  if (s->batch_max < 2 || s->prec != BM_PREC_FP64 || !is_small(s, n)) return 1;
+  const int fit = (s->ncu / 2 / (int)s->lanes.size()) / panel_p(n);
+  const int b = (s->batch_max < fit) ? s->batch_max : fit;
+  return (b < BM_LU_BATCH_MAX) ? (b > 1 ? b : 1) : BM_LU_BATCH_MAX;
+}
 
 // Lane for a request: the lane that holds its keyed factors, else the least
 // loaded lane for a small request, else lane 0.
@@ -153,10 +168,10 @@ int choose_lane(const bm_server *s, const bm_request &r) {
 // Find the handle for request r on `lane` or make room for it and create it.
 // Returns BM_OK with *out set, BM_OK with *out == nullptr (wait for
 // completions) or an error for the request.
-int acquire(bm_server *s, const bm_request &r, int lane, srv_handle **out) {
+int acquire(bm_server *s, const bm_request &r, int lane, int bslot, srv_handle **out) {
   *out = nullptr;
   for (srv_handle *h : s->handles)
-    if (h->lane == lane && h->n == r.n && h->key == r.reuse_key) {
+    if (h->lane == lane && h->n == r.n && h->key == r.reuse_key && h->bslot == bslot) {
       *out = h;
       return BM_OK;
     }
@@ -200,6 +215,7 @@ int acquire(bm_server *s, const bm_request &r, int lane, srv_handle **out) {
   h->lane = lane;
   h->n = r.n;
   h->key = r.reuse_key;
+  h->bslot = bslot;
   h->bytes = need;
   s->handles.push_back(h);
   std::lock_guard<std::mutex> g(s->mu);
@@ -319,6 +335,37 @@ int enqueue(bm_server *s, srv_request *rq) {
   return BM_OK;
 }
 
+// Enqueue requests of one N (no reuse key, FP64) on one lane with their
+// factorisations in shared launches: each is assembled on its own handle, the
+// handles are factored together, then each is solved.
+int enqueue_batch(bm_server *s, const std::vector<srv_request *> &rqs) {
+  const hipStream_t st = s->lanes[rqs[0]->lane].stream;
+  bm_problem *ps[BM_LU_BATCH_MAX];
+  const int count = (int)rqs.size();
+  for (int k = 0; k < count; ++k) {
+    srv_request *rq = rqs[k];
+    if (int rc = fence(s, rq)) return rc;
+    BM_HIP_TRY(hipEventRecord(s->ev_start[rq->slot], st));
+    rq->h->factored = false;
+    if (int rc = bm_assemble(rq->h->p, &rq->req.geometry, &rq->req.params)) return rc;
+    ps[k] = rq->h->p;
+  }
+  if (int rc = bm_block_lu_batch(ps, count, nullptr)) return rc;
+  for (int k = 0; k < count; ++k) {
+    srv_request *rq = rqs[k];
+    const bm_request &r = rq->req;
+    if (int rc = bm_solve(rq->h->p, r.nrhs, r.B, r.ldb, r.X, r.ldx)) return rc;
+    rq->h->factored = true;
+    rq->h->prm = r.params;
+    rq->res.batched = count;
+    BM_HIP_TRY(hipMemcpyAsync(s->pinned + 4 * rq->slot, rq->h->p->dev_err, 4 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+    BM_HIP_TRY(hipEventRecord(s->ev_done[rq->slot], st));
+  }
+  s->lanes[rqs[0]->lane].used = true;
+  return BM_OK;
+}
+
 void finish(bm_server *s, srv_request *rq, int status) {
   if (rq->h) --rq->h->pending;
   if (rq->slot >= 0) {
@@ -332,6 +379,7 @@ void finish(bm_server *s, srv_request *rq, int status) {
   rq->state = RQ_DONE;
   if (status == BM_OK) {
     ++s->st.completed;
+    if (rq->res.batched > 1) ++s->st.batched;
     if (rq->res.reused_factors) ++s->st.factor_reuses;
     if (rq->res.graph) ++s->st.graph_launches;
   } else if (status == BM_E_CANCELED) {
@@ -376,18 +424,34 @@ bool poll(bm_server *s) {
 
 void worker_main(bm_server *s) {
   (void)hipSetDevice(s->device);
+  // a batch takes same-N requests from this many queue positions after the front
+  constexpr size_t kBatchWindow = 8;
   for (;;) {
     const bool progress = poll(s);
     srv_request *next = nullptr;
     bm_request req{};
     int lane = 0;
+    std::vector<srv_request *> extra;  // requests factored together with `next`
+    std::vector<bm_request> extra_req;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->queue.empty() && s->inflight.empty()) break;
       if (!s->queue.empty()) {
         req = s->queue.front()->req;  // a copy: the request may be canceled once the lock is released
         lane = choose_lane(s, req);
-        if (s->lanes[lane].inflight < s->max_inflight) next = s->queue.front();
+        if (s->lanes[lane].inflight < s->max_inflight) {
+          next = s->queue.front();
+          // (a batch may take the lane up to batch_max - 1 requests beyond max_inflight)
+          int lim = batch_limit(s, req.n);
+          if (req.reuse_key == 0)
+            for (size_t qi = 1; qi < s->queue.size() && qi <= kBatchWindow && (int)extra.size() + 1 < lim; ++qi) {
+              srv_request *c = s->queue[qi];
+              if (c->req.n == req.n && c->req.reuse_key == 0) {
+                extra.push_back(c);
+                extra_req.push_back(c->req);
+              }
+            }
+        }
       }
       if (!next && !progress) {
         if (s->inflight.empty())
@@ -399,7 +463,7 @@ void worker_main(bm_server *s) {
     }
     if (!next) continue;
     srv_handle *h = nullptr;
-    int rc = acquire(s, req, lane, &h);
+    int rc = acquire(s, req, lane, 0, &h);
     if (rc == BM_OK && !h) {
       if (!s->inflight.empty()) {  // no room until a request completes
         std::this_thread::sleep_for(std::chrono::microseconds(50));
@@ -407,11 +471,39 @@ void worker_main(bm_server *s) {
       }
       rc = BM_E_BUDGET;  // not reached: the submission check guarantees that one handle fits
     }
+    // the other members' handles (slots 1, 2, ...): the batch ends at the first
+    // that cannot be had now; each handle is held (pending) once acquired, so that
+    // a later acquisition does not evict it
+    std::vector<srv_handle *> extra_h;
+    if (!rc) {
+      ++h->pending;
+      for (size_t k = 0; k < extra.size(); ++k) {
+        srv_handle *hk = nullptr;
+        if (acquire(s, extra_req[k], lane, (int)k + 1, &hk) != BM_OK || !hk) break;
+        ++hk->pending;
+        extra_h.push_back(hk);
+      }
+      for (size_t k = extra_h.size(); k < extra.size(); ++k) extra[k] = nullptr;
+    }
     {
       std::lock_guard<std::mutex> g(s->mu);
-      if (s->queue.empty() || s->queue.front() != next) continue;  // canceled meanwhile
+      if (s->queue.empty() || s->queue.front() != next) {  // canceled meanwhile
+        if (!rc) --h->pending;
+        for (srv_handle *hk : extra_h) --hk->pending;
+        continue;
+      }
       s->queue.pop_front();
       next->state = RQ_RUNNING;  // from here on only the worker touches it until it is done
+      for (size_t k = 0; k < extra_h.size(); ++k) {
+        auto it = std::find(s->queue.begin(), s->queue.end(), extra[k]);
+        if (it == s->queue.end()) {  // canceled meanwhile: its handle stays idle
+          --extra_h[k]->pending;
+          extra[k] = nullptr;
+          continue;
+        }
+        s->queue.erase(it);
+        extra[k]->state = RQ_RUNNING;
+      }
     }
     next->res.t_start = now_s();
     next->lane = lane;
@@ -419,22 +511,31 @@ void worker_main(bm_server *s) {
       finish(s, next, rc);
       continue;
     }
+    std::vector<srv_request *> group{next};
     next->h = h;
-    ++h->pending;
-    h->last_use = ++s->use_clock;
-    next->slot = s->free_slots.back();
-    s->free_slots.pop_back();
-    ++s->lanes[lane].inflight;
-    rc = enqueue(s, next);
+    for (size_t k = 0; k < extra_h.size(); ++k)
+      if (extra[k]) {
+        extra[k]->h = extra_h[k];
+        extra[k]->res.t_start = next->res.t_start;
+        extra[k]->lane = lane;
+        group.push_back(extra[k]);
+      }
+    for (srv_request *rq : group) {
+      rq->h->last_use = ++s->use_clock;
+      rq->slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      ++s->lanes[lane].inflight;
+    }
+    rc = (group.size() == 1) ? enqueue(s, next) : enqueue_batch(s, group);
     if (rc) {
-      h->factored = false;
-      // the lane may hold part of the request's work: let everything drain
+      for (srv_request *rq : group) rq->h->factored = false;
+      // the lane may hold part of the requests' work: let everything drain
       (void)hipDeviceSynchronize();
       (void)poll(s);
-      finish(s, next, rc);
+      for (srv_request *rq : group) finish(s, rq, rc);
       continue;
     }
-    s->inflight.push_back(next);
+    for (srv_request *rq : group) s->inflight.push_back(rq);
   }
 }
 
@@ -477,6 +578,8 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
   s->max_inflight = c.max_inflight > 0 ? c.max_inflight : 4;
   s->graph_max_n = c.graph_max_n;
   s->concurrent_max_n = cmax;
+  s->ncu = ncu;
+  s->batch_max = (c.batch_max < 1) ? 1 : ((c.batch_max > BM_LU_BATCH_MAX) ? BM_LU_BATCH_MAX : c.batch_max);
   s->quad = c.quadrature;
   s->prec = c.precision;
   s->refine_steps = c.refine_steps > 0 ? c.refine_steps : 2;
@@ -491,7 +594,7 @@ int bm_server_create(const bm_server_config *cfg, bm_server **out) {
     ok = ok && hipEventCreateWithFlags(&L.fence, hipEventDisableTiming) == hipSuccess;
   }
   ok = ok && hipEventCreateWithFlags(&s->big_fence, hipEventDisableTiming) == hipSuccess;
-  const int nslot = s->max_inflight * lanes;
+  const int nslot = (s->max_inflight + s->batch_max - 1) * lanes;  // (a batch may go past max_inflight)
   s->ev_start.assign(nslot, nullptr);
   s->ev_done.assign(nslot, nullptr);
   for (int i = 0; ok && i < nslot; ++i) {
@@ -528,6 +631,7 @@ int bm_server_submit(bm_server *s, const bm_request *r, uint64_t *ticket) {
   rq->ticket = s->next_ticket++;
   rq->req = *r;
   rq->res.n = r->n;
+  rq->res.batched = 1;
   rq->res.t_submit = now_s();
   s->queue.push_back(rq);
   s->by_ticket[rq->ticket] = rq;

@@ -75,11 +75,15 @@ def contour_mix():
     return [reqs[i] for i in order]
 
 
-@pytest.mark.parametrize("graph_max_n,lanes,concurrent_max_n", [(0, 1, 1024), (256, 4, 1024), (0, 4, 1024),
-                                                                 (256, 3, 128)])
-def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n):
+@pytest.mark.parametrize("graph_max_n,lanes,concurrent_max_n,batch_max",
+                         [(0, 1, 1024, 1), (256, 4, 1024, 1), (0, 4, 1024, 1), (256, 3, 128, 1), (0, 2, 512, 4),
+                          (128, 3, 512, 2)])
+def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n, batch_max):
     """lanes > 1: requests with N <= concurrent_max_n run concurrently, larger
-    ones (N = 192, 256 when concurrent_max_n = 128) are fenced to run alone."""
+    ones (N = 192, 256 when concurrent_max_n = 128) are fenced to run alone.  With
+    batch_max > 1, queued requests of one N are factored together (up to four at
+    N = 128, two at N = 192 and 256 with a lane share of eight panel workgroups);
+    every result is still bitwise the direct one."""
     reqs = contour_mix()
     ref = [direct(r) for r in reqs]
     alone = []
@@ -89,7 +93,8 @@ def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n):
         assert res["status"] == 0
         alone.append(X)
         s.close()
-    s = B.Server(max_inflight=3, graph_max_n=graph_max_n, lanes=lanes, concurrent_max_n=concurrent_max_n)
+    s = B.Server(max_inflight=3, graph_max_n=graph_max_n, lanes=lanes, concurrent_max_n=concurrent_max_n,
+                 batch_max=batch_max)
     mix = serve(s, reqs)
     st = s.stats()
     s.close()
@@ -98,10 +103,15 @@ def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n):
         assert res["t_submit"] <= res["t_start"] <= res["t_done"] and res["device_ms"] > 0
         assert torch.equal(Xa, Xr), "alone != direct"
         assert torch.equal(Xm, Xr), "in the mix != direct"
-        assert res["graph"] == (1 if r.n <= graph_max_n else 0)
+        if res["batched"] == 1:
+            assert res["graph"] == (1 if r.n <= graph_max_n else 0)
+        else:
+            assert res["graph"] == 0 and 2 <= res["batched"] <= batch_max
     assert st["completed"] == len(reqs) and st["failed"] == 0
-    assert 3 <= st["handles_created"] <= 3 * lanes and (lanes > 1 or st["handles_created"] == 3)
-    assert st["graph_launches"] == sum(r.n <= graph_max_n for r in reqs)
+    batched = sum(res["batched"] > 1 for res, _ in mix)
+    assert st["batched"] == batched and (batch_max == 1) == (batched == 0)
+    assert 3 <= st["handles_created"] <= 3 * lanes * batch_max and (lanes > 1 or st["handles_created"] == 3)
+    assert st["graph_launches"] == sum(r.n <= graph_max_n and res["batched"] == 1 for r, (res, _) in zip(reqs, mix))
 
 
 def test_served_solutions_vs_oracle():
