@@ -351,11 +351,12 @@ def serving_section(rate, graph_max_n, max_inflight, lanes, concurrent_max_n, ba
     out["server_stats"] = srv.stats()
     srv.close()
     # the same sweep in mixed precision (split-FP16 Schur complement, complex64 LU,
-    # refinement decided on the device: 2 passes, target 1e-10; one request at a
-    # time per lane), against the FP64 served solutions
+    # refinement decided on the device: 2 passes, target 1e-10; same-N requests
+    # factored together as above), against the FP64 served solutions
     fp64 = [x.clone() for x in Xs]
     srv = B.Server(max_inflight=max_inflight, graph_max_n=graph_max_n, lanes=lanes,
-                   concurrent_max_n=concurrent_max_n, precision="mixed", refine_steps=2, refine_tol=1e-10)
+                   concurrent_max_n=concurrent_max_n, precision="mixed", refine_steps=2, refine_tol=1e-10,
+                   batch_max=batch_max)
     warm(srv, lanes)
     tickets = []
     for r in sw.requests:

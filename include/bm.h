@@ -179,16 +179,17 @@ int bm_assemble_create(const bm_assemble_args *a, void *hip_stream, bm_problem *
 int bm_block_lu(bm_problem *p, int32_t *info);
 
 /* The same factorisation for `count` (1..BM_LU_BATCH_MAX) problems of one order N
- * (mixed formulation, FP64, assembled, the same device and stream), factored
+ * (mixed formulation, one precision, assembled, the same device and stream), factored
  * together: each Schur complement as in bm_block_lu (U33 formed in full before its
  * LU), then one LU in which every panel, interchange and update launch covers all
  * of the problems, so that the CUs one problem's panel chain leaves idle serve the
  * others (the panels of the batch together need count * ceil(N / 64) workgroups
  * resident, at most the CU count).  Each problem gets bitwise the factors that
- * bm_block_lu without the segmented product gives it.  info: NULL (asynchronous)
- * or a host array of count entries, filled as bm_block_lu's (then it waits).
- * Errors: BM_E_ARG (count, differing N, device or stream, a repeated or ordinary or
- * mixed-precision problem, too many panel workgroups), BM_E_STATE. */
+ * bm_block_lu without the segmented product gives it (in mixed precision, the
+ * complex64 factors of its FP32 factorisation).  info: NULL (asynchronous) or a host
+ * array of count entries, filled as bm_block_lu's (then it waits).
+ * Errors: BM_E_ARG (count, differing N, precision, device or stream, a repeated or
+ * ordinary problem, too many panel workgroups), BM_E_STATE. */
 #define BM_LU_BATCH_MAX 4
 int bm_block_lu_batch(bm_problem *const *ps, int32_t count, int32_t *info);
 
@@ -414,7 +415,7 @@ typedef struct {
                                 BM_E_NOCONV)                                        */
   int32_t refine_steps;      /* correction passes of BM_PREC_MIXED_DEVICE; <= 0: 2   */
   double refine_tol;         /* relative residual target; <= 0: 1e-12               */
-  int32_t batch_max;         /* FP64: up to this many queued requests of one N
+  int32_t batch_max;         /* up to this many queued requests of one N
                                 (<= BM_LU_BATCH_MAX, no reuse key) are factored
                                 together on one lane (bm_block_lu_batch), as many
                                 as their panels fit a lane's share of the panel

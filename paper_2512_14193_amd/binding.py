@@ -447,7 +447,7 @@ class Server:
                  refine_steps: int = 2, refine_tol: float = 1e-12, batch_max: int = 1):
         """precision "fp64" or "mixed" (split-FP16 Schur complement, refinement decided
         on the device: refine_steps passes, target refine_tol).  batch_max: queued
-        requests of one N factored together (FP64; see bm_server_config)."""
+        requests of one N factored together (see bm_server_config)."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs on the GPU only")
         prec = {"fp64": BM_PREC_FP64, "mixed": BM_PREC_MIXED_DEVICE}[precision]

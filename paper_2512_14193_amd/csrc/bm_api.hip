@@ -294,6 +294,26 @@ static int read_dev_err(bm_problem *p, int32_t *info) {
   return h[3] ? BM_E_NOCONV : BM_OK;  // [3]: a device-decided refinement missed its target
 }
 
+// Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23], in full, on
+// the problem's stream.  Mixed precision: into a complex64 U33 that takes the first
+// half of the factor storage, on the FP16 matrix cores with split operands where
+// their packed planes fit in the half it leaves free, else on the FP32 ones
+// (bm_solve refines against the FP64 blocks).
+static int schur_product(bm_problem *p) {
+  const int n = p->n;
+  if (p->prec != BM_PREC_FP64) {
+    const size_t half = (size_t)n * n * sizeof(cplx32);
+    char *ws = (char *)p->lu + (half + 255) / 256 * 256;
+    const size_t wsb = 2 * half - (size_t)(ws - (char *)p->lu);
+    if (n >= BM_F16X3_MIN_N && wsb >= bm_zgemm16_ws_bytes(n, n, 16))
+      return bm_launch_zgemm16(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, (cplx32 *)p->lu, n,
+                               ws, wsb, nullptr);
+    return bm_launch_zgemm32_c(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0),
+                               (cplx32 *)p->lu, n);
+  }
+  return bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu, n);
+}
+
 int bm_block_lu(bm_problem *p, int32_t *info) {
   if (!p) return BM_E_ARG;
   if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
@@ -330,23 +350,7 @@ int bm_block_lu(bm_problem *p, int32_t *info) {
   if (p->form == BM_MIXED) {
     // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
     phase_begin(p, BM_PH_SCHUR);
-    // (mixed precision: on the FP32 matrix cores, into a complex64 U33 that takes
-    // the first half of the factor storage; bm_solve refines against the FP64 blocks)
-    if (p->prec != BM_PREC_FP64) {
-      // the split-FP16 product where its packed operands fit in the half of the
-      // factor storage the complex64 U33 leaves free, else the FP32 one
-      const size_t half = (size_t)n * n * sizeof(cplx32);
-      char *ws = (char *)p->lu + (half + 255) / 256 * 256;
-      const size_t wsb = 2 * half - (size_t)(ws - (char *)p->lu);
-      if (n >= BM_F16X3_MIN_N && wsb >= bm_zgemm16_ws_bytes(n, n, 16))
-        rc = bm_launch_zgemm16(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, (cplx32 *)p->lu, n,
-                               ws, wsb, nullptr);
-      else
-        rc = bm_launch_zgemm32_c(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0),
-                                 (cplx32 *)p->lu, n);
-    } else
-      rc = bm_launch_zgemm(p->stream, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu,
-                           n);
+    rc = schur_product(p);
     phase_end(p, BM_PH_SCHUR);
     if (rc) return rc;
     if (p->after_schur) BM_HIP_TRY(hipEventRecord(p->after_schur, p->stream));
@@ -378,8 +382,9 @@ int bm_block_lu_batch(bm_problem *const *ps, int32_t count, int32_t *info) {
   if (!ps || count < 1 || count > BM_LU_BATCH_MAX) return BM_E_ARG;
   for (int b = 0; b < count; ++b) {
     bm_problem *p = ps[b];
-    if (!p || p->form != BM_MIXED || p->prec != BM_PREC_FP64) return BM_E_ARG;
-    if (p->n != ps[0]->n || p->device != ps[0]->device || p->stream != ps[0]->stream) return BM_E_ARG;
+    if (!p || p->form != BM_MIXED) return BM_E_ARG;
+    if (p->n != ps[0]->n || p->device != ps[0]->device || p->stream != ps[0]->stream || p->prec != ps[0]->prec)
+      return BM_E_ARG;
     for (int c = 0; c < b; ++c)
       if (ps[c] == p) return BM_E_ARG;
     if (p->state < BM_ST_ASSEMBLED) return BM_E_STATE;
@@ -388,30 +393,34 @@ int bm_block_lu_batch(bm_problem *const *ps, int32_t count, int32_t *info) {
   if (hipSetDevice(p0->device) != hipSuccess) return BM_E_HIP;
   const int n = p0->n;
   const hipStream_t st = p0->stream;
+  const bool c64 = (p0->prec != BM_PREC_FP64);  // the FP32 factorisation of each (complex64 U33)
   cplx *A[BM_LU_BATCH_MAX];
+  cplx32 *A32[BM_LU_BATCH_MAX];
   int32_t *ipiv[BM_LU_BATCH_MAX], *err[BM_LU_BATCH_MAX];
   bm_getrf_ws *ws[BM_LU_BATCH_MAX];
   for (int b = 0; b < count; ++b) {
     bm_problem *p = ps[b];
     if (int rc0 = bm_launch_ir_reset(st, p->ir_norm + 2 * BM_MAX_NRHS, p->dev_err + 3, 0)) return rc0;
-    // Theorem thm:LU: U33 = -M31 M13 - M32 M23 = -[M31 M32] [M13; M23]
-    if (int rc0 = bm_launch_zgemm(st, n, n, 2 * n, cmk(-1.0, 0.0), p->bot, n, p->top, 2 * n, cmk(0.0, 0.0), p->lu,
-                                  n))
-      return rc0;
+    if (int rc0 = schur_product(p)) return rc0;
     if (p->after_schur) BM_HIP_TRY(hipEventRecord(p->after_schur, st));
     p->lu_segments = 0;
     A[b] = p->lu;
+    A32[b] = (cplx32 *)p->lu;
     ipiv[b] = p->ipiv;
     err[b] = p->dev_err;
     ws[b] = p->gws;
   }
-  if (int rc0 = bm_getrf_run_batch(st, n, count, A, n, ipiv, err, ws)) return rc0;
+  if (int rc0 = c64 ? bm_getrf_run_batch_c64(st, n, count, A32, n, ipiv, err, ws)
+                    : bm_getrf_run_batch(st, n, count, A, n, ipiv, err, ws))
+    return rc0;
   for (int b = 0; b < count; ++b) {
     bm_problem *p = ps[b];
-    if (int rc0 = bm_launch_diag_inverses(st, n, p->lu, n, p->dinv)) return rc0;
+    if (int rc0 = c64 ? bm_launch_diag_inverses_c64(st, n, A32[b], n, p->dinv)
+                      : bm_launch_diag_inverses(st, n, p->lu, n, p->dinv))
+      return rc0;
     if (int rc0 = bm_launch_perm(st, p->gws, n, p->perm)) return rc0;
     p->state = BM_ST_FACTORED;
-    p->factored_prec = BM_PREC_FP64;
+    p->factored_prec = p->prec;
   }
   if (!info) return BM_OK;
   int status = BM_OK;

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(SNT) void panel_kernel(int N, T *A, long lda, int j
                                                     int next_jb, int32_t *swp, int j0, const int32_t *swp0,
                                                     bm_lu_batch bb) {
   if constexpr (BAT) {
-    static_assert(!FUSE && sizeof(T) == sizeof(cplx), "batched panels: FP64 storage, no fused update");
+    static_assert(!FUSE, "batched panels: no fused update");
     const int b = blockIdx.y;
     A = (T *)bb.A[b];
     ipiv = bb.ipiv[b];
@@ -984,6 +984,10 @@ static const panel_fn<cplx> panel_fns[3] = {panel_kernel<1, false, cplx>, panel_
                                             panel_kernel<1, true, cplx>};
 static const panel_fn<cplx32> panel_fns_c64[2] = {panel_kernel<1, false, cplx32>, panel_kernel<2, false, cplx32>};
 static const panel_fn<cplx> panel_fns_bat[2] = {panel_kernel<1, false, cplx, true>, panel_kernel<2, false, cplx, true>};
+static const panel_fn<cplx32> panel_fns_bat_c64[2] = {panel_kernel<1, false, cplx32, true>,
+                                                      panel_kernel<2, false, cplx32, true>};
+static const void *panel_bat_of(const cplx *, int k) { return (const void *)panel_fns_bat[k]; }
+static const void *panel_bat_of(const cplx32 *, int k) { return (const void *)panel_fns_bat_c64[k]; }
 static const void *panel_fn_of(const cplx *, int k) { return (const void *)panel_fns[k]; }
 static const void *panel_fn_of(const cplx32 *, int k) { return (k < 2) ? (const void *)panel_fns_c64[k] : nullptr; }
 
@@ -1033,16 +1037,19 @@ int bm_getrf_prepare() {
     const void *big[] = {(const void *)panel_fns[0],     (const void *)panel_fns[1],
                          (const void *)panel_fns[2],     (const void *)panel_fns_c64[0],
                          (const void *)panel_fns_c64[1], (const void *)panel_fns_bat[0],
-                         (const void *)panel_fns_bat[1]};
+                         (const void *)panel_fns_bat[1], (const void *)panel_fns_bat_c64[0],
+                         (const void *)panel_fns_bat_c64[1]};
     for (const void *f : big)
       BM_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PANEL_LDS_ALLOC));
     const void *st_next[] = {(const void *)swap_trsm_kernel<ST_CW_NEXT, cplx>,
                              (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx32>,
-                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx, true>};
+                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx, true>,
+                             (const void *)swap_trsm_kernel<ST_CW_NEXT, cplx32, true>};
     const void *st_rest[] = {(const void *)swap_trsm_kernel<ST_CW_REST, cplx>,
                              (const void *)swap_trsm_kernel<ST_CW_REST, cplx32>,
-                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx, true>};
-    for (int t = 0; t < 3; ++t) {
+                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx, true>,
+                             (const void *)swap_trsm_kernel<ST_CW_REST, cplx32, true>};
+    for (int t = 0; t < 4; ++t) {
       BM_HIP_TRY(hipFuncSetAttribute(st_next[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_NEXT)));
       BM_HIP_TRY(hipFuncSetAttribute(st_rest[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ST_LDS(ST_CW_REST)));
     }
@@ -1217,6 +1224,17 @@ int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv
 // panel chain leaves idle work on the others.  Every problem sees the kernels and
 // the arithmetic of its own factorisation (bitwise the same factors).
 // ---------------------------------------------------------------------------
+static int lu_gemm_batch(const cplx *, hipStream_t st, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                         long lda, long ob, long oc, bool) {
+  return bm_launch_zgemm_lu_batch(st, count, bb, m, n, k, oa, lda, ob, lda, oc, lda);
+}
+static int lu_gemm_batch(const cplx32 *, hipStream_t st, int count, const bm_lu_batch &bb, int m, int n, int k,
+                         long oa, long lda, long ob, long oc, bool next) {
+  return (next ? bm_launch_zgemm_shallow_lu_batch_c64 : bm_launch_zgemm32_lu_batch)(st, count, bb, m, n, k, oa, lda, ob,
+                                                                                    lda, oc, lda);
+}
+
+template <class T>
 static int lu_update_batch(hipStream_t st, int count, const bm_lu_batch &bb, long lda, int n, int j, int jb,
                            int lcols, int c0, int c1, bool next) {
   const int cw = next ? ST_CW_NEXT : ST_CW_REST;
@@ -1224,22 +1242,23 @@ static int lu_update_batch(hipStream_t st, int count, const bm_lu_batch &bb, lon
   if (nleft + nright > 0) {
     const dim3 grid(nleft + nright, count);
     if (next)
-      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_NEXT, cplx, true>), grid, dim3(256), ST_LDS(ST_CW_NEXT), st,
-                         (cplx *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_NEXT, T, true>), grid, dim3(256), ST_LDS(ST_CW_NEXT), st,
+                         (T *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
     else
-      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_REST, cplx, true>), grid, dim3(256), ST_LDS(ST_CW_REST), st,
-                         (cplx *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
+      hipLaunchKernelGGL((swap_trsm_kernel<ST_CW_REST, T, true>), grid, dim3(256), ST_LDS(ST_CW_REST), st,
+                         (T *)nullptr, lda, j, jb, lcols, c0, c1, (const int32_t *)nullptr, nleft, bb);
     BM_HIP_TRY(hipGetLastError());
   }
   const int nr = n - j - jb, jn = j + jb;
   if (nr > 0 && c1 > c0)
-    return bm_launch_zgemm_lu_batch(st, count, bb, nr, c1 - c0, jb, jn + (long)j * lda, lda, j + (long)c0 * lda, lda,
-                                    jn + (long)c0 * lda, lda);
+    return lu_gemm_batch((const T *)nullptr, st, count, bb, nr, c1 - c0, jb, jn + (long)j * lda, lda,
+                         j + (long)c0 * lda, jn + (long)c0 * lda, next);
   return BM_OK;
 }
 
-int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t lda, int32_t *const *ipiv,
-                       int32_t *const *dev_err, bm_getrf_ws *const *ws) {
+template <class T>
+static int getrf_run_batch(hipStream_t s, int n, int count, T *const *A, int64_t lda, int32_t *const *ipiv,
+                           int32_t *const *dev_err, bm_getrf_ws *const *ws) {
   if (count < 1 || count > BM_LU_BATCH_MAX || n < 1 || lda < n) return BM_E_ARG;
   for (int b = 0; b < count; ++b)
     if (!ws[b] || ws[b]->n < n || !A[b] || !ipiv[b] || !dev_err[b]) return BM_E_ARG;
@@ -1253,7 +1272,7 @@ int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t 
   const bool la = w->aux != nullptr;
   bm_lu_batch bb{};
   for (int b = 0; b < count; ++b) {
-    bb.A[b] = A[b];
+    bb.A[b] = (cplx *)A[b];  // (complex64 storage read back as such by the T kernels)
     bb.ipiv[b] = ipiv[b];
     bb.err[b] = dev_err[b];
   }
@@ -1273,27 +1292,38 @@ int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t 
     }
     {
       int nn = n, jj = j, jbb = jb, j0 = 0;
-      cplx *a0 = nullptr, *c0p = nullptr, *c1p = nullptr;
+      T *a0 = nullptr;
+      cplx *c0p = nullptr, *c1p = nullptr;
       int32_t *p0 = nullptr, *e0 = nullptr, *s0 = nullptr;
       const int32_t *sw0 = nullptr;
       void *args[] = {&nn, &a0, (void *)&ldal, &jj, &jbb, &P, &p0, &e0, &c0p, &c1p, &next_P, &next_jb, &s0, &j0,
                       &sw0, &bb};
-      BM_HIP_TRY(hipLaunchKernel((const void *)panel_fns_bat[shape[3 * pi] - 1], dim3(P, count), dim3(SNT), args,
+      BM_HIP_TRY(hipLaunchKernel(panel_bat_of((const T *)nullptr, shape[3 * pi] - 1), dim3(P, count), dim3(SNT), args,
                                  PANEL_LDS_ALLOC, s));
     }
     const int nr = n - j - jb;
     const int jn = j + jb, jbn = (nr < LU_NB) ? nr : LU_NB;
     if (la && pi > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
-    if (int rc = lu_update_batch(s, count, bb, ldal, n, j, jb, 0, jn, jn + jbn, true)) return rc;
+    if (int rc = lu_update_batch<T>(s, count, bb, ldal, n, j, jb, 0, jn, jn + jbn, true)) return rc;
     if (la) {
       BM_HIP_TRY(hipEventRecord(w->e_next, s));
       BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
     }
-    if (int rc = lu_update_batch(la ? w->aux : s, count, bb, ldal, n, j, jb, j, jn + jbn, n, false)) return rc;
+    if (int rc = lu_update_batch<T>(la ? w->aux : s, count, bb, ldal, n, j, jb, j, jn + jbn, n, false)) return rc;
     if (la) BM_HIP_TRY(hipEventRecord(w->e_rest, w->aux));
   }
   if (la && npanel > 0) BM_HIP_TRY(hipStreamWaitEvent(s, w->e_rest, 0));
   return BM_OK;
+}
+
+int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t lda, int32_t *const *ipiv,
+                       int32_t *const *dev_err, bm_getrf_ws *const *ws) {
+  return getrf_run_batch(s, n, count, A, lda, ipiv, dev_err, ws);
+}
+
+int bm_getrf_run_batch_c64(hipStream_t s, int n, int count, cplx32 *const *A, int64_t lda, int32_t *const *ipiv,
+                           int32_t *const *dev_err, bm_getrf_ws *const *ws) {
+  return getrf_run_batch(s, n, count, A, lda, ipiv, dev_err, ws);
 }
 
 // ---------------------------------------------------------------------------

@@ -265,6 +265,12 @@ struct bm_lu_batch {  // (BM_LU_BATCH_MAX: include/bm.h)
 // oc of that problem's matrix (the kernels and tiling of bm_launch_zgemm)
 int bm_launch_zgemm_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
                              long lda, long ob, long ldb, long oc, long ldc);
+// the same for complex64 matrices (A[] holding complex64 storage): the FP64
+// shallow kernel for the next panel's update, the FP32 matrix cores for the rest
+int bm_launch_zgemm_shallow_lu_batch_c64(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                                        long lda, long ob, long ldb, long oc, long ldc);
+int bm_launch_zgemm32_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                               long lda, long ob, long ldb, long oc, long ldc);
 // The split-FP16 product into complex64 C (bm_zgemm16.hip): workspace bytes for
 // k chunks of kc, and the launcher (chunks_out: the number of k-chunks taken)
 // (the mixed-precision Schur complement takes it from this N on)
@@ -352,6 +358,9 @@ int bm_getrf_run_c64(hipStream_t s, int n, cplx32 *A, int64_t lda, int32_t *ipiv
 // ws[0]'s second stream and events order the lookahead
 int bm_getrf_run_batch(hipStream_t s, int n, int count, cplx *const *A, int64_t lda, int32_t *const *ipiv,
                        int32_t *const *dev_err, bm_getrf_ws *const *ws);
+// the same for complex64 storage (the FP32 factorisation of each problem)
+int bm_getrf_run_batch_c64(hipStream_t s, int n, int count, cplx32 *const *A, int64_t lda, int32_t *const *ipiv,
+                           int32_t *const *dev_err, bm_getrf_ws *const *ws);
 // Per 64-row block b, BM_DINV_TILES column-major 64 x 64 tiles at dinv + b * BM_DINV_TILES * 4096:
 //   Linv_b, Uinv_b, WL_b = Linv_b L(b, b - 1) (b > 0), WU_b = Uinv_b U(b, b + 1) (b < last)
 #define BM_DINV_TILES 4

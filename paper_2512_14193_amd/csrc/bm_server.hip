@@ -146,7 +146,7 @@ int panel_p(int n) { return (n <= 64 * 32) ? (n + 63) / 64 : (n + 127) / 128; }
 // requests of N nodes that may be factored together: their panels within one
 // lane's share of the panel workgroups all lanes may hold, half the CUs
 int batch_limit(const bm_server *s, int n) {
-  if (s->batch_max < 2 || s->prec != BM_PREC_FP64 || !is_small(s, n)) return 1;
+  if (s->batch_max < 2 || !is_small(s, n)) return 1;
   const int fit = (s->ncu / 2 / (int)s->lanes.size()) / panel_p(n);
   const int b = (s->batch_max < fit) ? s->batch_max : fit;
   return (b < BM_LU_BATCH_MAX) ? (b > 1 ? b : 1) : BM_LU_BATCH_MAX;

@@ -397,12 +397,13 @@ __global__ __launch_bounds__(256) void zgemm_shallow_kernel(int m, int n, int k,
 // The LU's k <= 64 updates C -= A B for a batch of problems (blockIdx.y), each
 // operand at an element offset into that problem's matrix: the same tiles as the
 // single-problem kernels
+template <class T>
 __global__ __launch_bounds__(256) void zgemm_shallow_batch_kernel(bm_lu_batch bb, int m, int n, int k, long oa,
                                                                   long lda, long ob, long ldb, long oc, long ldc,
                                                                   int tiles_m) {
-  cplx *M = bb.A[blockIdx.y];
-  shallow_tile<cplx>(blockIdx.x, m, n, k, cmk(-1.0, 0.0), M + oa, lda, M + ob, ldb, cmk(1.0, 0.0), M + oc, ldc,
-                     tiles_m);
+  T *M = (T *)bb.A[blockIdx.y];
+  shallow_tile<T>(blockIdx.x, m, n, k, cmk(-1.0, 0.0), M + oa, lda, M + ob, ldb, cmk(1.0, 0.0), M + oc, ldc,
+                  tiles_m);
 }
 __global__ __launch_bounds__(256, GM_OCC) void zgemm_update_batch_kernel(bm_lu_batch bb, int m, int n, int k, long oa,
                                                                          long lda, long ob, long ldb, long oc, long ldc,
@@ -418,8 +419,8 @@ int bm_launch_zgemm_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, in
   if (count < 1 || count > BM_LU_BATCH_MAX || k > GM_3M_MIN_K - 1) return BM_E_ARG;
   if (k <= GS_K && n <= 64) {
     const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
-    hipLaunchKernelGGL(zgemm_shallow_batch_kernel, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n, k, oa,
-                       lda, ob, ldb, oc, ldc, tm);
+    hipLaunchKernelGGL(zgemm_shallow_batch_kernel<cplx>, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n,
+                       k, oa, lda, ob, ldb, oc, ldc, tm);
   } else {
     const int tm = (m + GM_BM - 1) / GM_BM, tn = (n + GM_BN - 1) / GM_BN;
     hipLaunchKernelGGL(zgemm_update_batch_kernel, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n, k, oa,
@@ -471,6 +472,17 @@ int bm_launch_zgemm_shallow_c64(hipStream_t s, int m, int n, int k, cplx alpha, 
   if (tiles > 0x7fffffffL) return BM_E_ARG;
   hipLaunchKernelGGL(zgemm_shallow_kernel<cplx32>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, alpha, A,
                      (long)lda, B, (long)ldb, beta, C, (long)ldc, tm);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
+int bm_launch_zgemm_shallow_lu_batch_c64(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                                        long lda, long ob, long ldb, long oc, long ldc) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  if (count < 1 || count > BM_LU_BATCH_MAX || k > GS_K || n > 64) return BM_E_ARG;
+  const int tm = (m + GS_T - 1) / GS_T, tn = (n + GS_T - 1) / GS_T;
+  hipLaunchKernelGGL(zgemm_shallow_batch_kernel<cplx32>, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n,
+                     k, oa, lda, ob, ldb, oc, ldc, tm);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
 }

@@ -46,18 +46,18 @@ __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// One 128 x 128 tile (index `tile`) of the product: the body of the plain and the
+// batched kernels
 template <bool BETA0, class TA, class TB, class TC>
-__global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int k, cplx alpha,
-                                                           const TA *__restrict__ A, long lda,
-                                                           const TB *__restrict__ B, long ldb, cplx beta,
-                                                           TC *__restrict__ C, long ldc, int tiles_m) {
+__device__ __forceinline__ void zgemm32_tile(int tile, int m, int n, int k, cplx alpha, const TA *__restrict__ A,
+                                             long lda, const TB *__restrict__ B, long ldb, cplx beta,
+                                             TC *__restrict__ C, long ldc, int tiles_m) {
   __shared__ float As[2][G2_LP][G2_BK][G2_BM];
   __shared__ float Bs[2][G2_LP][G2_BK][G2_BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int tile = blockIdx.x;
   const int row0 = (tile % tiles_m) * G2_BM, col0 = (tile / tiles_m) * G2_BN;
 
   // global -> LDS assignment (G2_LPT complex values per thread and operand)
@@ -175,6 +175,35 @@ __global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int 
         }
       }
       }
+}
+
+template <bool BETA0, class TA, class TB, class TC>
+__global__ __launch_bounds__(256, G2_OCC) void zgemm32_kernel(int m, int n, int k, cplx alpha,
+                                                           const TA *__restrict__ A, long lda,
+                                                           const TB *__restrict__ B, long ldb, cplx beta,
+                                                           TC *__restrict__ C, long ldc, int tiles_m) {
+  zgemm32_tile<BETA0, TA, TB, TC>(blockIdx.x, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
+}
+
+// The complex64 LU's trailing update C -= A B for a batch of problems (blockIdx.y),
+// each operand at an element offset into that problem's complex64 matrix
+__global__ __launch_bounds__(256, G2_OCC) void zgemm32_update_batch_kernel(bm_lu_batch bb, int m, int n, int k,
+                                                                        long oa, long lda, long ob, long ldb,
+                                                                        long oc, long ldc, int tiles_m) {
+  cplx32 *M = (cplx32 *)bb.A[blockIdx.y];
+  zgemm32_tile<false, cplx32, cplx32, cplx32>(blockIdx.x, m, n, k, cmk(-1.0, 0.0), M + oa, lda, M + ob, ldb,
+                                              cmk(1.0, 0.0), M + oc, ldc, tiles_m);
+}
+
+int bm_launch_zgemm32_lu_batch(hipStream_t s, int count, const bm_lu_batch &bb, int m, int n, int k, long oa,
+                               long lda, long ob, long ldb, long oc, long ldc) {
+  if (m <= 0 || n <= 0) return BM_OK;
+  if (count < 1 || count > BM_LU_BATCH_MAX) return BM_E_ARG;
+  const int tm = (m + G2_BM - 1) / G2_BM, tn = (n + G2_BN - 1) / G2_BN;
+  hipLaunchKernelGGL(zgemm32_update_batch_kernel, dim3((unsigned)(tm * tn), count), dim3(256), 0, s, bb, m, n, k, oa,
+                     lda, ob, ldb, oc, ldc, tm);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
 }
 
 template <class TA, class TB, class TC>

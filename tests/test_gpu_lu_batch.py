@@ -51,6 +51,35 @@ def test_batch_equals_single(n, count):
         P.close()
 
 
+@pytest.mark.parametrize("n", [256, 640])
+def test_batch_mixed_precision_equals_single(n):
+    """Mixed precision: each problem's split-FP16 Schur complement, then the complex64
+    LUs in shared launches: bitwise the single mixed-precision factors and refined
+    solutions."""
+    print(f"[lu_batch] mixed n={n}", flush=True)
+    rhs = B.fortran(torch.as_tensor(I.probing_rhs(3 * n, 3, 4)).cuda())
+    probs = []
+    for b in range(3):
+        P, bnd, ph = make(n, b)
+        P.set_precision("mixed", tol=1e-12, max_iter=6)
+        P.assemble(bnd, ph)
+        probs.append((P, bnd, ph))
+    assert B.block_lu_batch([p for p, _, _ in probs]) == [0, 0, 0]
+    for P, bnd, ph in probs:
+        X = P.solve(rhs)
+        lu, piv = P.copy_factors()
+        R = B.Problem(n, "mixed")
+        R.set_precision("mixed", tol=1e-12, max_iter=6)
+        R.assemble(bnd, ph)
+        assert R.block_lu() == 0
+        torch.cuda.synchronize()
+        lu_r, piv_r = R.copy_factors()
+        assert torch.equal(lu, lu_r) and torch.equal(piv, piv_r)
+        assert torch.equal(X, R.solve(rhs))
+        R.close()
+        P.close()
+
+
 def test_batch_errors():
     a, _, _ = make(128, 0)
     b, _, _ = make(128, 1)
@@ -73,7 +102,7 @@ def test_batch_errors():
     m.set_precision("mixed")
     m.assemble(I.star(128), I.Physics.from_wavenumbers(2.0, 3.0))
     with pytest.raises(B.BMError) as e:
-        B.block_lu_batch([a, m])  # mixed precision
+        B.block_lu_batch([a, m])  # different precisions
     assert e.value.code == B.BM_E_ARG
     fresh = B.Problem(128, "mixed")
     with pytest.raises(B.BMError) as e:

@@ -142,10 +142,11 @@ def test_served_request_in_sweep_range_vs_oracle():
 
 @pytest.mark.parametrize("graph_max_n", [0, 256])
 def test_served_mixed_precision(graph_max_n):
-    """precision "mixed": the FP32 Schur complement with the refinement decided on
-    the device (inside the captured graph for graph_max_n = 256): against the
-    oracle to 1e-10, the same request alone and in the mix bitwise equal, and a
-    target out of reach ends the request with BM_E_NOCONV."""
+    """precision "mixed": the split-FP16 Schur complement and complex64 LU with the
+    refinement decided on the device (inside the captured graph for graph_max_n =
+    256): against the oracle to 1e-10, the same request alone, in the mix and in a
+    batched factorisation bitwise equal, and a target out of reach ends the request
+    with BM_E_NOCONV."""
     reqs = contour_mix()[:6]
     print(f"[serving] mixed precision, graph_max_n {graph_max_n}", flush=True)
 
@@ -162,9 +163,18 @@ def test_served_mixed_precision(graph_max_n):
     s = mk(3)
     mix = serve(s, reqs)
     s.close()
-    for r, Xa, (res, Xm) in zip(reqs, alone, mix):
+    # factored in batches of same-N requests (concurrent_max_n 512: a lane's share
+    # holds two to four of these sizes): still bitwise the requests alone
+    s = B.Server(max_inflight=2, graph_max_n=graph_max_n, lanes=2, concurrent_max_n=512, precision="mixed",
+                 refine_steps=3, batch_max=4)
+    bat = serve(s, reqs)
+    st = s.stats()
+    s.close()
+    assert st["batched"] == sum(res["batched"] > 1 for res, _ in bat) > 0
+    for r, Xa, (res, Xm), (rb, Xb) in zip(reqs, alone, mix, bat):
         assert res["status"] == 0 and res["graph"] == (1 if r.n <= graph_max_n else 0)
-        assert torch.equal(Xa, Xm)
+        assert rb["status"] == 0
+        assert torch.equal(Xa, Xm) and torch.equal(Xa, Xb)
         Xo = O.zgesv(O.build_mixed(r.bnd, r.ph), r.Bh)
         assert rel_cols(Xm.cpu().numpy(), Xo) < 1e-10
     s = B.Server(lanes=1, graph_max_n=graph_max_n, precision="mixed", refine_steps=1, refine_tol=1e-30)
