@@ -216,6 +216,17 @@ def test_budget_eviction_and_rejection():
         assert torch.equal(X, Xr)
     assert st["evictions"] > 0 and st["bytes_peak"] <= budget and st["budget"] == budget
     s.close()
+    # batched factorisations under the same budget: a batch takes only the handles
+    # that fit beside the ones in use (else it shrinks), and results stay bitwise
+    for budget_b in (budget, b[256] + b[192] + 2 * b[128] + 1):
+        s = B.Server(hbm_budget_bytes=budget_b, max_inflight=2, lanes=2, concurrent_max_n=256, batch_max=4)
+        out = serve(s, reqs)
+        st = s.stats()
+        s.close()
+        for Xr, (res, X) in zip(ref, out):
+            assert res["status"] == 0
+            assert torch.equal(X, Xr)
+        assert st["bytes_peak"] <= budget_b and st["completed"] == len(reqs)
     # a handle of the request's size alone exceeds the budget: rejected at submission
     s = B.Server(hbm_budget_bytes=b[128] - 1)
     r = Req(128, 4.0, 2, 5)
