@@ -28,29 +28,41 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_zgemm_star2048_traffic.json")
-ZGEMM_SRC = os.path.join(ROOT, "paper_2512_14193_amd", "csrc", "bm_zgemm.hip")
+CSRC = os.path.join(ROOT, "paper_2512_14193_amd", "csrc")
+# rocprofv3 FETCH_SIZE / WRITE_SIZE records (profiles/*.json): the file, the
+# sources whose hash it carries, and the factorisation mode it was taken in
+TRAFFIC = {
+    "schur_gemm": ("schur_zgemm_star2048_traffic.json", ("bm_zgemm.hip",), False),
+    "panel": ("panel_star2048_traffic.json", ("bm_getrf.hip", "bm_internal.h"), True),
+}
 
 
-def kernel_hash(path=ZGEMM_SRC):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(sources):
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_record():
-    """HBM bytes per Schur-GEMM launch from rocprofv3 counters, if they were taken
-    on the current kernel source; else None."""
+def traffic_record(which, workload, lu_overlap):
+    """HBM bytes per launch of a kernel from rocprofv3 counters, if they were taken
+    on the current kernel sources, this workload and this factorisation mode; else
+    None."""
+    fname, sources, overlap = TRAFFIC[which]
+    if overlap != lu_overlap:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != kernel_hash():
+    if rec.get("kernel_source_sha256_16") != kernel_hash(sources) or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 
 
-def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12):
+def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12, lu_overlap=True):
     import torch
     from paper_2512_14193_amd import binding as B
 
@@ -64,6 +76,8 @@ def run_formulation(form, w, steps, warmup, precision="fp64", tol=1e-12):
     P = B.Problem(N, form)
     if precision != "fp64":
         P.set_precision(precision, tol=tol, max_iter=10)
+    if form == "mixed" and not lu_overlap:
+        P.set_lu_overlap(False)  # the whole Schur product first, then the LU
     Bm = B.fortran_empty(P.rows, R)
     X = B.fortran_empty(P.rows, R)
     F = B.fortran_empty(len(w.theta_obs), R)
@@ -433,6 +447,8 @@ def main():
     ap.add_argument("--workload", default="star2048")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-lu-overlap", action="store_true",
+                    help="form the whole Schur complement before the LU (no segments beside the panels)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64 vs mixed-precision comparison")
     ap.add_argument("--mixed-workload", default="star8192")
     ap.add_argument("--mixed-steps", type=int, default=3)
@@ -470,7 +486,7 @@ def main():
     w = I.workload(args.workload)
     N = w.boundary.n_nodes
     R = len(w.theta_inc)
-    mixed = run_formulation("mixed", w, args.steps, args.warmup)
+    mixed = run_formulation("mixed", w, args.steps, args.warmup, lu_overlap=not args.no_lu_overlap)
     sec = mixed["seconds"]
     value = args.steps / sec
     ph = mixed["phase_ms"]
@@ -487,7 +503,7 @@ def main():
     t_factor = ph["factor"] * 1e-3
     factor_tflops = (flops_schur + flops_lu) / t_factor / 1e12
     overlap = mixed["lu_overlap"]["segments"] > 0
-    traffic = traffic_record()
+    traffic = {k: traffic_record(k, w.name, overlap) for k in TRAFFIC}
     # The panel factorisation kernel: mean algorithmic flops of the step's panels
     # (LU of an R x 64 panel: sum_c 8 (R - c - 1)(63 - c) for the rank-1 updates and
     # 6 (R - c - 1) for the scaling, R = N - 64 i) over its mean launch duration.
@@ -505,7 +521,8 @@ def main():
                             "previous panel's update to its columns)",
                   "bound": "alu", "achieved": panel_flops_mean / t_panel / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
                   "unit": "TFLOP/s", "frac": panel_flops_mean / t_panel / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
-                  "traffic": None, "avg_launch_ms": ph["panel_kernel_avg"], "launches_per_step": len(panel_rows),
+                  "traffic": traffic["panel"], "avg_launch_ms": ph["panel_kernel_avg"],
+                  "launches_per_step": len(panel_rows),
                   "ms_per_step": panel_step_ms, "flops_per_launch_mean": panel_flops_mean,
                   "launches_timed": mixed["panel_launches_timed"]},
         "schur_gemm": {"kernel": ("zgemm_persist_kernel segments beside the LU (Schur complement, m=n=N, k=2N; "
@@ -513,7 +530,7 @@ def main():
                        if overlap else
                        "zgemm_kernel<true,true> (Schur complement, m=n=N, k=2N; 16 N^3 algorithmic flops)",
                        "bound": "mfma", "achieved": schur_tflops, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": None if overlap else traffic,
+                       "frac": schur_tflops / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic["schur_gemm"],
                        "avg_launch_ms": ph["schur_gemm"],
                        "launches_per_step": mixed["lu_overlap"]["segments"] if overlap else 1,
                        "ms_per_step": ph["schur_gemm"], "overlapped_with_lu": overlap},

@@ -194,11 +194,27 @@ if constexpr (M3) {
       }
 }
 
+// Output tile of workgroup b in a grid of tm x tn tiles.  Workgroups are dealt to
+// the eight XCDs in turn (XCD b % 8); XCD x takes the x-th consecutive range of a
+// tile order that walks groups of eight tile rows column by column, so that the
+// workgroups one XCD runs together (64 at two per CU) form about an 8 x 8 block of
+// C and share its eight A row panels and eight B column panels in that XCD's L2.
+// A bijection of [0, tm tn) for any tile count (the first T % 8 XCDs take one
+// tile more); the tiles' arithmetic does not depend on it.
+__device__ inline int gm_tile_of(int b, int tm, int tn) {
+  const int T = tm * tn, q = T / 8, r = T % 8, x = b % 8;
+  const int t = x * q + (x < r ? x : r) + b / 8;
+  const int gsz = 8 * tn, grp = t / gsz, gi = t % gsz;
+  const int grows = (tm - grp * 8 < 8) ? tm - grp * 8 : 8;
+  return grp * 8 + gi % grows + (gi / grows) * tm;
+}
+
 template <bool BETA0, bool M3>
 __global__ __launch_bounds__(256, GM_OCC) void zgemm_kernel(int m, int n, int k, cplx alpha, const cplx *__restrict__ A,
                                                     long lda, const cplx *__restrict__ B, long ldb, cplx beta,
                                                     cplx *__restrict__ C, long ldc, int tiles_m) {
-  zgemm_tile<BETA0, M3>(blockIdx.x, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
+  const int tile = gm_tile_of(blockIdx.x, tiles_m, (n + GM_BN - 1) / GM_BN);
+  zgemm_tile<BETA0, M3>(tile, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m);
 }
 
 // Persistent form of the deep product (beta = 0), for the Schur complement
@@ -219,7 +235,9 @@ __global__ __launch_bounds__(256, GM_OCC) void zgemm_persist_kernel(int m, int n
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int tile = item % ntiles, sl = item / ntiles;
     if (ksplit == 1) {
-      zgemm_tile<true, M3>(tile, m, n, k, alpha, A, lda, B, ldb, zero, C, ldc, tiles_m);
+      // item % 8 is the XCD when the grid is a multiple of 8 or covers every item
+      zgemm_tile<true, M3>(gm_tile_of(item, tiles_m, ntiles / tiles_m), m, n, k, alpha, A, lda, B, ldb, zero, C, ldc,
+                           tiles_m);
     } else {
       const int k0 = sl * kc, kk = (k - k0 < kc) ? k - k0 : kc;
       zgemm_tile<true, M3>(tile, m, n, kk, one, A + (long)k0 * lda, lda, B + k0, ldb, zero, W + (long)sl * m * n, m,
