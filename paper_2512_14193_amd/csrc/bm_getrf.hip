@@ -1333,9 +1333,10 @@ int bm_getrf_run_batch_c64(hipStream_t s, int n, int count, cplx32 *const *A, in
 // The product is formed in column segments of whole 64-column blocks.  Block 0
 // goes first on the whole device (k split into slices summed afterwards, so that
 // its few tiles fill the CUs); the other segments follow on a third stream g as a
-// bounded persistent grid of one workgroup per CU, which leaves as many CUs free
-// as the largest panel has workgroups, while the panels factor the columns that
-// are already there.  A segment whose first panel is f is brought up to date by a
+// bounded persistent grid of one workgroup per CU that claims each of its CUs
+// whole, leaving free as many CUs as the largest panel has workgroups plus
+// SP_FREE_CUS for the updates, while the panels factor the columns that are
+// already there.  A segment whose first panel is f is brought up to date by a
 // fourth stream c: the interchanges, U12 rows and trailing updates of panels
 // 0 .. f - 2 on its columns, in panel order, each as soon as its panel is done;
 // from panel f - 1 on the segment belongs to the ordinary lookahead (s for the
@@ -1351,6 +1352,7 @@ int bm_getrf_run_batch_c64(hipStream_t s, int n, int count, cplx32 *const *A, in
 // ---------------------------------------------------------------------------
 #define SP_MAXB (BM_PIPE_MAX_N / LU_NB)
 #define SP_MAXSEG 24
+#define SP_FREE_CUS 32
 
 struct bm_lu_pipe {
   hipStream_t g, c;
@@ -1487,7 +1489,11 @@ int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_
   const int B = (n + LU_NB - 1) / LU_NB;
   int pmax = 0;
   for (int pi = 0; pi < B; ++pi) pmax = (shape[3 * pi + 1] > pmax) ? shape[3 * pi + 1] : pmax;
-  const int gs = ncu - pmax;  // the product's workgroups: one per CU, the panel's CUs left free
+  // the product's workgroups: one per CU, leaving free the largest panel's CUs and
+  // SP_FREE_CUS more for the trailing updates and catch-ups (which share no CU
+  // with the product)
+  int gs = ncu - pmax - SP_FREE_CUS;
+  if (gs < (ncu - pmax) / 2) gs = ncu - pmax;
   if (gs < 1) return BM_E_ARG;
   sp_seg seg[SP_MAXSEG];
   int nseg = 0;

@@ -246,7 +246,12 @@ __global__ __launch_bounds__(256, GM_OCC) void zgemm_persist_kernel(int m, int n
   }
 }
 
-#define GM_PERSIST_PAD (16 << 10)  // 66 KB static + 16 KB: a second workgroup does not fit in 160 KB
+// Dynamic LDS of a one-per-CU launch: with the kernel's static 64.5 KB it claims a
+// CU's whole 160 KB, so that no other workgroup that uses LDS (a panel, a trailing
+// update, another product) shares a CU with it.  Sharing cost more than it gave:
+// the short kernels beside the product ran several times slower on CUs whose
+// matrix cores it kept busy.
+#define GM_PERSIST_PAD ((160 << 10) - 2 * GM_BK3 * (GM_BM + GM_BN + 1) * (int)sizeof(cplx))
 
 // C = alpha sum_s W_s, the k-slices summed in order (deterministic)
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce(int m, int n, int ksplit, cplx alpha,
