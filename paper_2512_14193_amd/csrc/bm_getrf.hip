@@ -1590,11 +1590,15 @@ int bm_getrf_schur_run(hipStream_t s, int n, cplx alpha, const cplx *bot, int64_
         hi = c1;
         if (i > 0 && seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(s, q->ec[i], 0));  // joins now
       }
-    // (a fused next panel applies this update to its own columns)
-    if (!(pi + 1 < B && lu_fused(true, shape, pi + 1)))
+    // (a fused next panel applies this update to its own columns; then nothing runs
+    // on s after the panel, and the other stream starts from the panel's own event)
+    if (!(pi + 1 < B && lu_fused(true, shape, pi + 1))) {
       if (int rc = lu_update(s, A, ldal, n, j, jb, swp, 0, jn, jn + jbn, true, 0)) return rc;
-    BM_HIP_TRY(hipEventRecord(w->e_next, s));
-    BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+      BM_HIP_TRY(hipEventRecord(w->e_next, s));
+      BM_HIP_TRY(hipStreamWaitEvent(w->aux, w->e_next, 0));
+    } else {
+      BM_HIP_TRY(hipStreamWaitEvent(w->aux, q->ep[pi], 0));
+    }
     for (int i = 1; i < nseg; ++i)
       if (seg[i].b0 == pi + 1) BM_HIP_TRY(hipStreamWaitEvent(w->aux, q->ec[i], 0));
     if (int rc = lu_update(w->aux, A, ldal, n, j, jb, swp, 0, jn + jbn, hi, false, 0)) return rc;
