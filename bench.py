@@ -30,18 +30,26 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_HBM_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2512_14193_amd", "csrc")
 # rocprofv3 FETCH_SIZE / WRITE_SIZE records (profiles/*.json): the file, the
-# sources whose hash it carries, and the factorisation mode it was taken in
+# source text of the kernel it was measured on (file, first line starting with the
+# start marker up to the end marker; None: the whole file), and the factorisation
+# mode it was taken in
 TRAFFIC = {
-    "schur_gemm": ("schur_zgemm_star2048_traffic.json", ("bm_zgemm.hip",), False),
-    "panel": ("panel_star2048_traffic.json", ("bm_getrf.hip", "bm_internal.h"), True),
+    "schur_gemm": ("schur_zgemm_star2048_traffic.json",
+                   (("bm_zgemm.hip", None, "// Persistent form of the deep product"),), False),
+    "panel": ("panel_star2048_traffic.json",
+              (("bm_getrf.hip", "// 1. panel factorisation", "// 2. row interchanges outside the panel"),
+               ("bm_internal.h", None, None)), True),
 }
 
 
 def kernel_hash(sources):
     h = hashlib.sha256()
-    for name in sources:
+    for name, start, end in sources:
         with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        a = text.index(start.encode()) if start else 0
+        b = text.index(end.encode(), a) if end else len(text)
+        h.update(text[a:b])
     return h.hexdigest()[:16]
 
 
