@@ -365,87 +365,169 @@ int bm_fds_cpqr_scatter(hipStream_t s, int nprob, const bm_qr_prob *pr, bm_qr_st
 // ---------------------------------------------------------------------------
 // Explicit inverse of small dense matrices by Gauss-Jordan elimination with
 // partial pivoting (largest |Re| + |Im| in the column, first row on ties), one
-// workgroup per matrix, in place (n x n at a + off, ld).  Row swaps are recorded and
-// undone on the columns at the end.  Returns info (1-based column of an exactly
-// zero pivot) in info[b].
+// workgroup per matrix, in place (n x n at A, ld).  Returns info (1-based column of
+// an exactly zero pivot) in info[b].
+//
+// Blocked: GJ_BS pivots at a time.  The block's GJ_BS columns (the panel) are held
+// in LDS and eliminated there one pivot after the other: pivot search, interchange
+// of rows j and p, scaling of row j, elimination of column j from every other row,
+// column j then storing the transformation's column (the in-place form).  The
+// transformation of the block is G = I + (P - E_R) E_R^T, R = the block's pivot rows,
+// P = the eliminated panel; every other column x receives it at once after the
+// block's row interchanges, x <- x - E_R x_R + P x_R.  So the matrix is read and
+// written once per GJ_BS pivots instead of once per pivot.  Row interchanges are
+// recorded and undone on the columns at the end.  Orders up to GJ_RPT * GJ_NT.
 // ---------------------------------------------------------------------------
 #define GJ_NT 256
+#define GJ_BS 16   // pivots per block
+#define GJ_CH 64   // columns per chunk of the block's update
+#define GJ_RPT 2   // rows per thread
 __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d, int *info) {
   const bm_inv_desc D = d[blockIdx.x];
   const int n = D.n;
   const long ld = D.ld;
   cplx *A = D.A;
   extern __shared__ char smem[];
-  cplx *rowj = (cplx *)smem;                   // pivot row (n)
-  int *piv = (int *)(rowj + n);                // row swaps (n)
-  __shared__ double rv[GJ_NT];
-  __shared__ int ri[GJ_NT];
+  cplx *pan = (cplx *)smem;                     // panel: column c at pan + c n
+  int *piv = (int *)(pan + (size_t)GJ_BS * n);  // row interchanges (n)
+  __shared__ cplx Tc[GJ_BS][GJ_CH];             // the block's pivot rows of a column chunk
+  __shared__ cplx rowj[GJ_BS];                  // scaled pivot row (panel columns)
   __shared__ cplx s_ip;
-  const int tid = threadIdx.x;
-  if (tid == 0) info[blockIdx.x] = 0;
-  for (int j = 0; j < n; ++j) {
-    // pivot search in column j, rows j..n-1
-    double bvv = -1.0;
-    int bi = n;
-    for (int i = j + tid; i < n; i += GJ_NT) {
-      const cplx v = A[i + (long)j * ld];
-      const double a = fabs(v.x) + fabs(v.y);
-      if (a > bvv) {
-        bvv = a;
-        bi = i;
-      }
+  __shared__ double wv[GJ_NT / 64];
+  __shared__ int wi[GJ_NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int zinfo = 0;
+  for (int kb = 0; kb < n; kb += GJ_BS) {
+    const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS;
+    for (int idx = tid; idx < bw * n; idx += GJ_NT) {
+      const int c = idx / n, i = idx - c * n;
+      pan[c * n + i] = A[i + (long)(kb + c) * ld];
     }
-    rv[tid] = bvv;
-    ri[tid] = bi;
     __syncthreads();
-    for (int st = GJ_NT / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        if (rv[tid + st] > rv[tid] || (rv[tid + st] == rv[tid] && ri[tid + st] < ri[tid])) {
-          rv[tid] = rv[tid + st];
-          ri[tid] = ri[tid + st];
+    for (int jj = 0; jj < bw; ++jj) {
+      const int j = kb + jj;
+      // pivot: largest |Re| + |Im| among rows j .. n - 1 of panel column jj (NaNs
+      // never win), the smallest row on ties
+      double bv = -1.0;
+      int bi = n;
+#pragma unroll
+      for (int u = 0; u < GJ_RPT; ++u) {
+        const int i = tid + GJ_NT * u;
+        if (i >= j && i < n) {
+          const cplx v = pan[jj * n + i];
+          const double a = fabs(v.x) + fabs(v.y);
+          if (a > bv) {
+            bv = a;
+            bi = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        wv[wave] = bv;
+        wi[wave] = bi;
+      }
+      __syncthreads();
+      double pv = wv[0];
+      int p = wi[0];
+#pragma unroll
+      for (int w = 1; w < GJ_NT / 64; ++w)
+        if (wv[w] > pv || (wv[w] == pv && wi[w] < p)) {
+          pv = wv[w];
+          p = wi[w];
+        }
+      const bool zero = !(pv > 0.0);
+      if (p >= n) p = j;  // a column of NaNs: no interchange
+      if (tid == 0) {
+        piv[j] = p;
+        if (zero && zinfo == 0) zinfo = j + 1;
+      }
+      if (p != j && tid < bw) {
+        const cplx t = pan[tid * n + j];
+        pan[tid * n + j] = pan[tid * n + p];
+        pan[tid * n + p] = t;
+      }
+      __syncthreads();
+      if (tid == 0) s_ip = zero ? cmk(0, 0) : crecip(pan[jj * n + j]);
+      __syncthreads();
+      if (tid < bw) {
+        cplx v = (tid == jj) ? cmk(1.0, 0.0) : pan[tid * n + j];
+        v = cmul(v, s_ip);
+        rowj[tid] = v;
+        pan[tid * n + j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < GJ_RPT; ++u) {
+        const int i = tid + GJ_NT * u;
+        if (i < n && i != j) {
+          const cplx f = pan[jj * n + i];
+          pan[jj * n + i] = cmk(0, 0);
+          for (int c = 0; c < bw; ++c) pan[c * n + i] = cfms(pan[c * n + i], f, rowj[c]);
         }
       }
       __syncthreads();
     }
-    const int p = ri[0];
-    const bool zero = !(rv[0] > 0.0);
-    if (tid == 0) {
-      piv[j] = p;
-      if (zero && info[blockIdx.x] == 0) info[blockIdx.x] = j + 1;
-    }
-    __syncthreads();
-    // swap rows j and p
-    if (p != j && p < n)
-      for (int c = tid; c < n; c += GJ_NT) {
-        const cplx t = A[j + (long)c * ld];
-        A[j + (long)c * ld] = A[p + (long)c * ld];
-        A[p + (long)c * ld] = t;
-      }
-    __syncthreads();
-    // scale the pivot row: a_jj <- 1, row j <- row j / pivot (the reciprocal is taken
-    // by one thread and shared: the row's own update overwrites a_jj)
-    if (tid == 0) s_ip = zero ? cmk(0, 0) : crecip(A[j + (long)j * ld]);
-    __syncthreads();
-    const cplx ip = s_ip;
+    // the block's interchanges on the other columns, in order (each thread owns its
+    // columns, so the order within a column is kept without barriers)
     for (int c = tid; c < n; c += GJ_NT) {
-      cplx v = (c == j) ? cmk(1.0, 0.0) : A[j + (long)c * ld];
-      v = cmul(v, ip);
-      rowj[c] = v;
-      A[j + (long)c * ld] = v;
+      if (c >= kb && c < kb + bw) continue;
+      for (int jj = 0; jj < bw; ++jj) {
+        const int j = kb + jj, p = piv[j];
+        if (p != j) {
+          const cplx t = A[j + (long)c * ld];
+          A[j + (long)c * ld] = A[p + (long)c * ld];
+          A[p + (long)c * ld] = t;
+        }
+      }
+    }
+    // this thread's rows of -P in registers (x + P t as x - (-P) t: exact negation)
+    cplx pn[GJ_RPT][GJ_BS];
+#pragma unroll
+    for (int u = 0; u < GJ_RPT; ++u) {
+      const int i = tid + GJ_NT * u;
+#pragma unroll
+      for (int t = 0; t < GJ_BS; ++t) pn[u][t] = (i < n && t < bw) ? cneg(pan[t * n + i]) : cmk(0, 0);
     }
     __syncthreads();
-    // eliminate column j from every other row: row i <- row i - a_ij row j (a_ij -> 0 first)
-    for (int i = tid; i < n; i += GJ_NT) {
-      if (i == j) continue;
-      const cplx f = A[i + (long)j * ld];
-      A[i + (long)j * ld] = cmk(0, 0);
-      for (int c = 0; c < n; ++c) {
-        const cplx a = A[i + (long)c * ld];
-        A[i + (long)c * ld] = cfms(a, f, rowj[c]);
+    for (int c0 = 0; c0 < n; c0 += GJ_CH) {
+      for (int idx = tid; idx < GJ_BS * GJ_CH; idx += GJ_NT) {
+        const int t = idx % GJ_BS, cc = idx / GJ_BS, c = c0 + cc;
+        Tc[t][cc] = (t < bw && c < n) ? A[kb + t + (long)c * ld] : cmk(0, 0);
       }
+      __syncthreads();
+      const int cend = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
+      for (int cc = 0; cc < cend; ++cc) {
+        const int c = c0 + cc;
+        if (c >= kb && c < kb + bw) continue;
+#pragma unroll
+        for (int u = 0; u < GJ_RPT; ++u) {
+          const int i = tid + GJ_NT * u;
+          if (i < n) {
+            cplx acc = (i >= kb && i < kb + bw) ? cmk(0, 0) : A[i + (long)c * ld];
+#pragma unroll
+            for (int t = 0; t < GJ_BS; ++t) acc = cfms(acc, pn[u][t], Tc[t][cc]);
+            A[i + (long)c * ld] = acc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < bw * n; idx += GJ_NT) {
+      const int c = idx / n, i = idx - c * n;
+      A[i + (long)(kb + c) * ld] = pan[c * n + i];
     }
     __syncthreads();
   }
+  if (tid == 0) info[blockIdx.x] = zinfo;
   // undo the row interchanges on the columns, last first
   for (int j = n - 1; j >= 0; --j) {
     const int p = piv[j];
@@ -461,7 +543,10 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
 
 int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev) {
   if (count <= 0) return BM_OK;
-  const size_t lds = (sizeof(cplx) + sizeof(int)) * (size_t)max_n;
+  if (max_n < 1 || max_n > GJ_RPT * GJ_NT) return BM_E_ARG;
+  const size_t lds = (sizeof(cplx) * GJ_BS + sizeof(int)) * (size_t)max_n;
+  BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((sizeof(cplx) * GJ_BS + sizeof(int)) * GJ_RPT * GJ_NT)));
   hipLaunchKernelGGL(gj_inverse_kernel, dim3(count), dim3(GJ_NT), lds, s, d_dev, info_dev);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
