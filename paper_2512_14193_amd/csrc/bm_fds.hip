@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -62,7 +63,8 @@ struct bm_fds {
   double *geo = nullptr, *wts = nullptr;
   std::vector<double> hx, hdx;
   std::vector<std::vector<fds_cell>> lv;  // lv[l]: cells of level l (0 = root)
-  std::vector<void *> mem;                // device allocations of the factorisation
+  std::vector<std::pair<void *, size_t>> mem;  // device allocations of the factorisation (address, bytes)
+  std::multimap<size_t, void *> spare;         // the previous factorisation's, reused by size
   std::vector<void *> mem_fixed;
   size_t bytes = 0, bytes_fixed = 0;
   bool factored = false;
@@ -99,23 +101,47 @@ bool verbose() {
     if (verbose()) fprintf(stderr, "[bm_fds] %s failed: %d\n", what, (int)(rc)); \
   } while (0)
 
+// Allocations of a factorisation are kept when the next one starts and handed out
+// again to requests of the same size (a repeated factorisation of one configuration
+// asks for the same sizes in the same order); what the new one has not taken by its
+// end is freed.  hipFree and hipMalloc of gigabytes each cost tens of milliseconds
+// and wait for the device.
 template <typename T>
 int dmalloc(bm_fds *f, T **p, size_t count, bool fixed = false) {
   *p = nullptr;
   if (count == 0) return BM_OK;
-  if (hipMalloc((void **)p, sizeof(T) * count) != hipSuccess) return BM_E_NOMEM;
-  (fixed ? f->mem_fixed : f->mem).push_back(*p);
-  f->bytes += sizeof(T) * count;
-  if (fixed) f->bytes_fixed += sizeof(T) * count;
+  const size_t bytes = sizeof(T) * count;
+  if (fixed) {
+    if (hipMalloc((void **)p, bytes) != hipSuccess) return BM_E_NOMEM;
+    f->mem_fixed.push_back(*p);
+    f->bytes_fixed += bytes;
+  } else {
+    auto it = f->spare.find(bytes);
+    if (it != f->spare.end()) {
+      *p = (T *)it->second;
+      f->spare.erase(it);
+    } else if (hipMalloc((void **)p, bytes) != hipSuccess) {
+      return BM_E_NOMEM;
+    }
+    f->mem.push_back({(void *)*p, bytes});
+  }
+  f->bytes += bytes;
   return BM_OK;
 }
 
+// The factorisation's allocations become spares (the caller has synchronised the
+// stream that used them).
 void free_factor_memory(bm_fds *f) {
-  for (void *p : f->mem) (void)hipFree(p);
+  for (const auto &m : f->mem) f->spare.emplace(m.second, m.first);
   f->mem.clear();
   f->lv.clear();
   f->factored = false;
   f->bytes = f->bytes_fixed;
+}
+
+void release_spare(bm_fds *f) {
+  for (const auto &m : f->spare) (void)hipFree(m.second);
+  f->spare.clear();
 }
 
 // Upload a host vector to a fresh device buffer (synchronous copy; setup path).
@@ -1114,6 +1140,7 @@ void bm_fds_destroy(bm_fds *f) {
   if (!f) return;
   (void)hipStreamSynchronize(f->stream);
   free_factor_memory(f);
+  release_spare(f);
   for (void *p : f->mem_fixed) (void)hipFree(p);
   if (f->dg) (void)hipFree(f->dg);
   if (f->dc) (void)hipFree(f->dc);
@@ -1126,6 +1153,7 @@ int bm_fds_factor(bm_fds *f, const bm_geometry *g, const bm_params *prm) {
   // the proxy interactions use the Hankel functions of the sector |Im k| <= Re k / 2
   if (prm->k0_im < -0.5 * prm->k0_re || prm->k1_im < -0.5 * prm->k1_re) return BM_E_ARG;
   if (hipSetDevice(f->device) != hipSuccess) return BM_E_HIP;
+  BM_HIP_TRY(hipStreamSynchronize(f->stream));  // the previous factors' last readers
   free_factor_memory(f);
   const int n = f->n;
   f->shell.phys.k0 = cmk(prm->k0_re, prm->k0_im);
@@ -1148,10 +1176,13 @@ int bm_fds_factor(bm_fds *f, const bm_geometry *g, const bm_params *prm) {
   int rc = factor_all(f);
   if (!rc) rc = alloc_solve_buffers(f);
   if (rc) {
+    (void)hipStreamSynchronize(f->stream);
     free_factor_memory(f);
+    release_spare(f);
     return rc;
   }
   BM_HIP_TRY(hipStreamSynchronize(f->stream));
+  release_spare(f);
   f->factored = true;
   return BM_OK;
 }
