@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <new>
 #include <vector>
@@ -64,7 +65,9 @@ struct bm_fds {
   std::vector<double> hx, hdx;
   std::vector<std::vector<fds_cell>> lv;  // lv[l]: cells of level l (0 = root)
   std::vector<std::pair<void *, size_t>> mem;  // device allocations of the factorisation (address, bytes)
-  std::multimap<size_t, void *> spare;         // the previous factorisation's, reused by size
+  // idle device buffers by size: (address, generation: the factorisation that last used it)
+  std::multimap<size_t, std::pair<void *, long>> spare;
+  long gen = 0;  // factorisations started
   std::vector<void *> mem_fixed;
   size_t bytes = 0, bytes_fixed = 0;
   bool factored = false;
@@ -101,11 +104,21 @@ bool verbose() {
     if (verbose()) fprintf(stderr, "[bm_fds] %s failed: %d\n", what, (int)(rc)); \
   } while (0)
 
-// Allocations of a factorisation are kept when the next one starts and handed out
-// again to requests of the same size (a repeated factorisation of one configuration
-// asks for the same sizes in the same order); what the new one has not taken by its
-// end is freed.  hipFree and hipMalloc of gigabytes each cost tens of milliseconds
-// and wait for the device.
+// Device buffers are not freed between factorisations: a factorisation's
+// allocations, and the temporary buffers of its steps, become spares that later
+// requests of the same size take again (a repeated factorisation of one configuration
+// asks for the same sizes).  At the end of a factorisation the spares it found and did
+// not take are freed; its own temporaries stay for the next one.  hipFree and
+// hipMalloc of gigabytes each cost tens of milliseconds and wait for the device.
+// A buffer becomes a spare only once the stream that used it has been synchronised.
+void *spare_take(bm_fds *f, size_t bytes) {
+  auto it = f->spare.find(bytes);
+  if (it == f->spare.end()) return nullptr;
+  void *p = it->second.first;
+  f->spare.erase(it);
+  return p;
+}
+
 template <typename T>
 int dmalloc(bm_fds *f, T **p, size_t count, bool fixed = false) {
   *p = nullptr;
@@ -116,32 +129,54 @@ int dmalloc(bm_fds *f, T **p, size_t count, bool fixed = false) {
     f->mem_fixed.push_back(*p);
     f->bytes_fixed += bytes;
   } else {
-    auto it = f->spare.find(bytes);
-    if (it != f->spare.end()) {
-      *p = (T *)it->second;
-      f->spare.erase(it);
-    } else if (hipMalloc((void **)p, bytes) != hipSuccess) {
-      return BM_E_NOMEM;
-    }
+    *p = (T *)spare_take(f, bytes);
+    if (!*p && hipMalloc((void **)p, bytes) != hipSuccess) return BM_E_NOMEM;
     f->mem.push_back({(void *)*p, bytes});
   }
   f->bytes += bytes;
   return BM_OK;
 }
 
+// Temporary buffers of a factorisation step: tmp_get (a spare, else hipMalloc),
+// tmp_put_all after the step's stream has been synchronised.
+struct tmp_list {
+  std::vector<std::pair<void *, size_t>> v;
+};
+bool tmp_get(bm_fds *f, tmp_list &t, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  *p = spare_take(f, bytes);
+  if (!*p && hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return false;
+  }
+  t.v.push_back({*p, bytes});
+  return true;
+}
+void tmp_put_all(bm_fds *f, tmp_list &t) {
+  for (const auto &m : t.v) f->spare.emplace(m.second, std::make_pair(m.first, f->gen));
+  t.v.clear();
+}
+
 // The factorisation's allocations become spares (the caller has synchronised the
 // stream that used them).
 void free_factor_memory(bm_fds *f) {
-  for (const auto &m : f->mem) f->spare.emplace(m.second, m.first);
+  for (const auto &m : f->mem) f->spare.emplace(m.second, std::make_pair(m.first, f->gen));
   f->mem.clear();
   f->lv.clear();
   f->factored = false;
   f->bytes = f->bytes_fixed;
 }
 
-void release_spare(bm_fds *f) {
-  for (const auto &m : f->spare) (void)hipFree(m.second);
-  f->spare.clear();
+// Frees the spares last used before generation g (all: g = LONG_MAX).
+void release_spare(bm_fds *f, long g) {
+  for (auto it = f->spare.begin(); it != f->spare.end();) {
+    if (it->second.second < g) {
+      (void)hipFree(it->second.first);
+      it = f->spare.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 // Upload a host vector to a fresh device buffer (synchronous copy; setup path).
@@ -278,8 +313,9 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
   if (!small.empty()) {
     bm_inv_desc *dd = nullptr;
     int *info = nullptr;
-    bool ok = hipMalloc(&dd, sizeof(bm_inv_desc) * small.size()) == hipSuccess &&
-              hipMalloc(&info, sizeof(int) * small.size()) == hipSuccess;
+    tmp_list tl;
+    bool ok = tmp_get(f, tl, (void **)&dd, sizeof(bm_inv_desc) * small.size()) &&
+              tmp_get(f, tl, (void **)&info, sizeof(int) * small.size());
     int rc = ok ? BM_OK : BM_E_NOMEM;
     if (ok && hipMemcpy(dd, small.data(), sizeof(bm_inv_desc) * small.size(), hipMemcpyHostToDevice) != hipSuccess)
       rc = BM_E_HIP;
@@ -288,8 +324,8 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
     if (!rc && (hipStreamSynchronize(s) != hipSuccess ||
                 hipMemcpy(hi.data(), info, sizeof(int) * small.size(), hipMemcpyDeviceToHost) != hipSuccess))
       rc = BM_E_HIP;
-    (void)hipFree(dd);
-    (void)hipFree(info);
+    (void)hipStreamSynchronize(s);
+    tmp_put_all(f, tl);
     if (rc) return rc;
     for (size_t q = 0; q < hi.size(); ++q)
       if (hi[q]) {
@@ -303,10 +339,11 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
     int32_t *ipiv = nullptr, *perm = nullptr;
     cplx *dinv = nullptr, *T = nullptr;
     const int nblk = (nmax_big + 63) / 64;
-    bool ok = w && hipMalloc(&ipiv, sizeof(int32_t) * nmax_big) == hipSuccess &&
-              hipMalloc(&perm, sizeof(int32_t) * nmax_big) == hipSuccess &&
-              hipMalloc(&dinv, sizeof(cplx) * (size_t)nblk * BM_DINV_TILES * 4096) == hipSuccess &&
-              hipMalloc(&T, sizeof(cplx) * 64 * (size_t)nmax_big) == hipSuccess;
+    tmp_list tl;
+    bool ok = w && tmp_get(f, tl, (void **)&ipiv, sizeof(int32_t) * nmax_big) &&
+              tmp_get(f, tl, (void **)&perm, sizeof(int32_t) * nmax_big) &&
+              tmp_get(f, tl, (void **)&dinv, sizeof(cplx) * (size_t)nblk * BM_DINV_TILES * 4096) &&
+              tmp_get(f, tl, (void **)&T, sizeof(cplx) * 64 * (size_t)nmax_big);
     int rc = ok ? BM_OK : BM_E_NOMEM;
     for (const auto &j : jobs) {
       if (rc || j.n <= BM_FDS_GJ_MAX) continue;
@@ -319,10 +356,8 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
     }
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = BM_E_HIP;
     bm_getrf_ws_destroy(w);
-    (void)hipFree(ipiv);
-    (void)hipFree(perm);
-    (void)hipFree(dinv);
-    (void)hipFree(T);
+    (void)hipStreamSynchronize(s);
+    tmp_put_all(f, tl);
     if (rc) return rc;
     int32_t h[2] = {0, 0};
     BM_HIP_TRY(hipMemcpy(h, f->dev_err, sizeof(h), hipMemcpyDeviceToHost));
@@ -354,8 +389,9 @@ int entries(bm_fds *f, cplx *base, const std::vector<entry_job> &jobs) {
   int *dcodes = nullptr;
   fds_tgt *ditems = nullptr;
   int rc = BM_OK;
-  if (hipMalloc(&dcodes, sizeof(int) * std::max<size_t>(codes.size(), 1)) != hipSuccess ||
-      hipMalloc(&ditems, sizeof(fds_tgt) * jobs.size()) != hipSuccess)
+  tmp_list tl;
+  if (!tmp_get(f, tl, (void **)&dcodes, sizeof(int) * std::max<size_t>(codes.size(), 1)) ||
+      !tmp_get(f, tl, (void **)&ditems, sizeof(fds_tgt) * jobs.size()))
     rc = BM_E_NOMEM;
   std::vector<fds_tgt> items;
   long maxe = 0;
@@ -378,8 +414,7 @@ int entries(bm_fds *f, cplx *base, const std::vector<entry_job> &jobs) {
     rc = BM_E_HIP;
   if (!rc) rc = bm_launch_fds_targets(f->stream, &f->shell, (int)items.size(), ditems, maxe, base);
   if (hipStreamSynchronize(f->stream) != hipSuccess && !rc) rc = BM_E_HIP;
-  (void)hipFree(dcodes);
-  (void)hipFree(ditems);
+  tmp_put_all(f, tl);
   return rc;
 }
 
@@ -509,17 +544,11 @@ int compress_level(bm_fds *f, std::vector<fds_cell> &cells) {
     max_e = std::max(max_e, (long)q.M * q.C);
   }
   // device buffers of the level (freed at the end)
-  std::vector<void *> tmp;
-  auto talloc = [&](void **p, size_t bytes) -> bool {
-    *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    if (hipMalloc(p, bytes) != hipSuccess) return false;
-    tmp.push_back(*p);
-    return true;
-  };
+  tmp_list tl;
+  auto talloc = [&](void **p, size_t bytes) -> bool { return tmp_get(f, tl, p, bytes); };
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
-    for (void *p : tmp) (void)hipFree(p);
+    tmp_put_all(f, tl);
   };
   int *dcodes;
   cplx *work;
@@ -733,15 +762,14 @@ int leaf_solve_block_rhs(bm_fds *f, std::vector<fds_cell> &cells) {
   if (int rc = run_gemms(f, g1)) return rc;
   // Z = -U33^{-1} Y: through a scratch block per cell
   std::vector<cplx *> Z(cells.size(), nullptr);
-  std::vector<void *> tmp;
+  tmp_list tl;
   for (size_t i = 0; i < cells.size(); ++i) {
     fds_cell &c = cells[i];
     if (c.ktot == 0) continue;
-    if (hipMalloc(&Z[i], sizeof(cplx) * (size_t)n * c.ktot) != hipSuccess) {
-      for (void *p : tmp) (void)hipFree(p);
+    if (!tmp_get(f, tl, (void **)&Z[i], sizeof(cplx) * (size_t)n * c.ktot)) {
+      tmp_put_all(f, tl);  // (nothing has used them yet)
       return BM_E_NOMEM;
     }
-    tmp.push_back(Z[i]);
     g2.push_back(gemm(n, c.ktot, n, MONE, c.Ainv, n, c.W + 2 * n, 3 * n, ZERO, Z[i], n));
   }
   int rc = run_gemms(f, g2);
@@ -753,7 +781,8 @@ int leaf_solve_block_rhs(bm_fds *f, std::vector<fds_cell> &cells) {
     if (c.ktot) g3.push_back(gemm(2 * n, c.ktot, n, MONE, c.Abar + (long)2 * n * 3 * n, 3 * n, c.W + 2 * n, 3 * n, ONE,
                                   c.W, 3 * n));
   if (!rc) rc = run_gemms(f, g3);
-  for (void *p : tmp) (void)hipFree(p);
+  (void)hipStreamSynchronize(f->stream);
+  tmp_put_all(f, tl);
   return rc;
 }
 
@@ -761,16 +790,18 @@ int leaf_solve_block_rhs(bm_fds *f, std::vector<fds_cell> &cells) {
 int level_lambda(bm_fds *f, std::vector<fds_cell> &cells) {
   std::vector<bm_gemm_desc> g;
   std::vector<inv_job> jobs;
-  std::vector<void *> tmp;
+  tmp_list tl;
   for (auto &c : cells) {
-    if (int rc = dmalloc(f, &c.Lam, (size_t)c.ktot * c.ktot)) return rc;
+    if (int rc = dmalloc(f, &c.Lam, (size_t)c.ktot * c.ktot)) {
+      tmp_put_all(f, tl);  // (nothing has used them yet)
+      return rc;
+    }
     if (c.ktot == 0) continue;
     cplx *RW = nullptr;
-    if (hipMalloc(&RW, sizeof(cplx) * (size_t)c.ktot * c.ktot) != hipSuccess) {
-      for (void *p : tmp) (void)hipFree(p);
+    if (!tmp_get(f, tl, (void **)&RW, sizeof(cplx) * (size_t)c.ktot * c.ktot)) {
+      tmp_put_all(f, tl);
       return BM_E_NOMEM;
     }
-    tmp.push_back(RW);
     g.push_back(gemm(c.ktot, c.ktot, c.m, ONE, c.R, c.ktot, c.W, c.m, ZERO, RW, c.ktot));
     inv_job j;
     j.A = RW;
@@ -780,7 +811,8 @@ int level_lambda(bm_fds *f, std::vector<fds_cell> &cells) {
   }
   int rc = run_gemms(f, g);
   if (!rc) rc = invert(f, jobs);
-  for (void *p : tmp) (void)hipFree(p);
+  (void)hipStreamSynchronize(f->stream);
+  tmp_put_all(f, tl);
   return rc;
 }
 
@@ -1140,7 +1172,7 @@ void bm_fds_destroy(bm_fds *f) {
   if (!f) return;
   (void)hipStreamSynchronize(f->stream);
   free_factor_memory(f);
-  release_spare(f);
+  release_spare(f, LONG_MAX);
   for (void *p : f->mem_fixed) (void)hipFree(p);
   if (f->dg) (void)hipFree(f->dg);
   if (f->dc) (void)hipFree(f->dc);
@@ -1155,6 +1187,7 @@ int bm_fds_factor(bm_fds *f, const bm_geometry *g, const bm_params *prm) {
   if (hipSetDevice(f->device) != hipSuccess) return BM_E_HIP;
   BM_HIP_TRY(hipStreamSynchronize(f->stream));  // the previous factors' last readers
   free_factor_memory(f);
+  const long gen_now = ++f->gen;  // this factorisation's temporaries carry gen_now
   const int n = f->n;
   f->shell.phys.k0 = cmk(prm->k0_re, prm->k0_im);
   f->shell.phys.k1 = cmk(prm->k1_re, prm->k1_im);
@@ -1178,11 +1211,11 @@ int bm_fds_factor(bm_fds *f, const bm_geometry *g, const bm_params *prm) {
   if (rc) {
     (void)hipStreamSynchronize(f->stream);
     free_factor_memory(f);
-    release_spare(f);
+    release_spare(f, LONG_MAX);
     return rc;
   }
   BM_HIP_TRY(hipStreamSynchronize(f->stream));
-  release_spare(f);
+  release_spare(f, gen_now);
   f->factored = true;
   return BM_OK;
 }
