@@ -28,7 +28,8 @@
 
 #include "bm_fds.h"
 
-#define BM_FDS_GJ_MAX 320      // explicit inverses up to this order by one workgroup each
+#define BM_FDS_GJ_MAX 512      // explicit inverses up to this order by one workgroup each
+#define BM_FDS_LEAF_MAX 320    // leaf cells of at most this many nodes
 #define BM_FDS_BACKSUB_MAX 128 // interpolation solves up to this rank per thread
 #define BM_FDS_RCHUNK 32       // right-hand sides per solve pass
 
@@ -1129,7 +1130,7 @@ int bm_fds_create(int32_t n, const bm_fds_config *cfg, void *hip_stream, bm_fds 
   bm_fds_config c = {256, 128, 1e-10, 0};
   if (cfg) c = *cfg;
   if (c.root_max <= 0) c.root_max = 4096;
-  if (c.leaf < 16 || c.leaf > BM_FDS_GJ_MAX || n < 2 * c.leaf || n > 65536 || (n % c.leaf) != 0) return BM_E_ARG;
+  if (c.leaf < 16 || c.leaf > BM_FDS_LEAF_MAX || n < 2 * c.leaf || n > 65536 || (n % c.leaf) != 0) return BM_E_ARG;
   const int p = n / c.leaf;
   if (p & (p - 1)) return BM_E_ARG;
   if (c.n_proxy < 8 || !(c.tol > 0.0) || !(c.tol < 1.0)) return BM_E_ARG;
