@@ -378,10 +378,11 @@ int bm_fds_cpqr_scatter(hipStream_t s, int nprob, const bm_qr_prob *pr, bm_qr_st
 // written once per GJ_BS pivots instead of once per pivot.  Row interchanges are
 // recorded and undone on the columns at the end.  Orders up to GJ_RPT * GJ_NT.
 // ---------------------------------------------------------------------------
-#define GJ_NT 256
+#define GJ_NT 512
 #define GJ_BS 16   // pivots per block
 #define GJ_CH 64   // columns per chunk of the block's update
-#define GJ_RPT 2   // rows per thread
+#define GJ_RPT 1   // rows per thread
+#define GJ_CU 2    // columns of the block's update whose loads are in flight together
 __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d, int *info) {
   const bm_inv_desc D = d[blockIdx.x];
   const int n = D.n;
@@ -504,18 +505,29 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
         Tc[t][cc] = (t < bw && c < n) ? A[kb + t + (long)c * ld] : cmk(0, 0);
       }
       __syncthreads();
+      // GJ_CU columns at a time: their loads first (a column of the panel, or beyond
+      // the matrix, is skipped), then the products, then the stores
       const int cend = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
-      for (int cc = 0; cc < cend; ++cc) {
-        const int c = c0 + cc;
-        if (c >= kb && c < kb + bw) continue;
+      for (int cb = 0; cb < cend; cb += GJ_CU) {
 #pragma unroll
         for (int u = 0; u < GJ_RPT; ++u) {
           const int i = tid + GJ_NT * u;
-          if (i < n) {
-            cplx acc = (i >= kb && i < kb + bw) ? cmk(0, 0) : A[i + (long)c * ld];
+          const bool rowr = i >= kb && i < kb + bw;
+          cplx acc[GJ_CU];
 #pragma unroll
-            for (int t = 0; t < GJ_BS; ++t) acc = cfms(acc, pn[u][t], Tc[t][cc]);
-            A[i + (long)c * ld] = acc;
+          for (int q = 0; q < GJ_CU; ++q) {
+            const int c = c0 + cb + q;
+            const bool live = i < n && cb + q < cend && !(c >= kb && c < kb + bw);
+            acc[q] = (live && !rowr) ? A[i + (long)c * ld] : cmk(0, 0);
+          }
+#pragma unroll
+          for (int t = 0; t < GJ_BS; ++t)
+#pragma unroll
+            for (int q = 0; q < GJ_CU; ++q) acc[q] = cfms(acc[q], pn[u][t], Tc[t][cb + q]);
+#pragma unroll
+          for (int q = 0; q < GJ_CU; ++q) {
+            const int c = c0 + cb + q;
+            if (i < n && cb + q < cend && !(c >= kb && c < kb + bw)) A[i + (long)c * ld] = acc[q];
           }
         }
       }
