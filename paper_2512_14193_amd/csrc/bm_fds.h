@@ -62,7 +62,7 @@ int bm_fds_cpqr_step(hipStream_t s, int nwg, const bm_qr_prob *pr, const int *wg
 int bm_fds_cpqr_finish(hipStream_t s, int nprob, const bm_qr_prob *pr, const cplx *work, bm_qr_state st, cplx *r11,
                        cplx *r12, int max_c, int kmax_small);
 int bm_fds_cpqr_scatter(hipStream_t s, int nprob, const bm_qr_prob *pr, bm_qr_state st, const cplx *r12, int max_c);
-int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev);
+int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev, int *piv_ws);
 // Y = X[idx, :] (inverse = 0) or X[idx, :] = Y (inverse = 1), m rows, nr columns
 int bm_fds_rows(hipStream_t s, int m, int nr, const int *idx, cplx *X, long ldx, cplx *Y, long ldy, int inverse);
 int bm_fds_perm_identity(hipStream_t s, int n, const int32_t *perm, cplx *A, long ld);

@@ -313,14 +313,15 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
   if (int rc = run_copies(f, cp)) return rc;
   if (!small.empty()) {
     bm_inv_desc *dd = nullptr;
-    int *info = nullptr;
+    int *info = nullptr, *pivw = nullptr;
     tmp_list tl;
     bool ok = tmp_get(f, tl, (void **)&dd, sizeof(bm_inv_desc) * small.size()) &&
-              tmp_get(f, tl, (void **)&info, sizeof(int) * small.size());
+              tmp_get(f, tl, (void **)&info, sizeof(int) * small.size()) &&
+              tmp_get(f, tl, (void **)&pivw, sizeof(int) * small.size() * nmax_small);
     int rc = ok ? BM_OK : BM_E_NOMEM;
     if (ok && hipMemcpy(dd, small.data(), sizeof(bm_inv_desc) * small.size(), hipMemcpyHostToDevice) != hipSuccess)
       rc = BM_E_HIP;
-    if (!rc) rc = bm_fds_gj_inverse(s, (int)small.size(), dd, nmax_small, info);
+    if (!rc) rc = bm_fds_gj_inverse(s, (int)small.size(), dd, nmax_small, info, pivw);
     std::vector<int> hi(small.size(), 0);
     if (!rc && (hipStreamSynchronize(s) != hipSuccess ||
                 hipMemcpy(hi.data(), info, sizeof(int) * small.size(), hipMemcpyDeviceToHost) != hipSuccess))

@@ -376,13 +376,142 @@ int bm_fds_cpqr_scatter(hipStream_t s, int nprob, const bm_qr_prob *pr, bm_qr_st
 // P = the eliminated panel; every other column x receives it at once after the
 // block's row interchanges, x <- x - E_R x_R + P x_R.  So the matrix is read and
 // written once per GJ_BS pivots instead of once per pivot.  Row interchanges are
-// recorded and undone on the columns at the end.  Orders up to GJ_RPT * GJ_NT.
+// recorded and undone on the columns at the end.  Orders up to GJ_NT.
 // ---------------------------------------------------------------------------
-#define GJ_NT 512
+#define GJ_NT 512  // threads: one row each (orders up to GJ_NT)
 #define GJ_BS 16   // pivots per block
 #define GJ_CH 64   // columns per chunk of the block's update
-#define GJ_RPT 1   // rows per thread
 #define GJ_CU 2    // columns of the block's update whose loads are in flight together
+#define GJ_SPLIT_MAX 32  // up to this many blocks in a call: one launch per block step
+
+// The block's panel (columns kb .. kb + bw - 1 of A) into pan (column c at pan + c n)
+// and eliminated there; the pivot rows go to piv[kb ..], the first zero pivot to zinfo.
+__device__ void gj_panel(cplx *A, long ld, int n, int kb, int bw, cplx *pan, int *piv, cplx *rowj, cplx *s_ip,
+                         double *wv, int *wi, int &zinfo) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < bw * n; idx += GJ_NT) {
+    const int c = idx / n, i = idx - c * n;
+    pan[c * n + i] = A[i + (long)(kb + c) * ld];
+  }
+  __syncthreads();
+  for (int jj = 0; jj < bw; ++jj) {
+    const int j = kb + jj;
+    // pivot: largest |Re| + |Im| among rows j .. n - 1 of panel column jj (NaNs
+    // never win), the smallest row on ties
+    double bv = -1.0;
+    int bi = n;
+    if (tid >= j && tid < n) {
+      const cplx v = pan[jj * n + tid];
+      const double a = fabs(v.x) + fabs(v.y);
+      if (a > bv) {
+        bv = a;
+        bi = tid;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = bv;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    double pv = wv[0];
+    int p = wi[0];
+#pragma unroll
+    for (int w = 1; w < GJ_NT / 64; ++w)
+      if (wv[w] > pv || (wv[w] == pv && wi[w] < p)) {
+        pv = wv[w];
+        p = wi[w];
+      }
+    const bool zero = !(pv > 0.0);
+    if (p >= n) p = j;  // a column of NaNs: no interchange
+    if (tid == 0) {
+      piv[j] = p;
+      if (zero && zinfo == 0) zinfo = j + 1;
+    }
+    if (p != j && tid < bw) {
+      const cplx t = pan[tid * n + j];
+      pan[tid * n + j] = pan[tid * n + p];
+      pan[tid * n + p] = t;
+    }
+    __syncthreads();
+    if (tid == 0) *s_ip = zero ? cmk(0, 0) : crecip(pan[jj * n + j]);
+    __syncthreads();
+    if (tid < bw) {
+      cplx v = (tid == jj) ? cmk(1.0, 0.0) : pan[tid * n + j];
+      v = cmul(v, *s_ip);
+      rowj[tid] = v;
+      pan[tid * n + j] = v;
+    }
+    __syncthreads();
+    if (tid < n && tid != j) {
+      const cplx f = pan[jj * n + tid];
+      pan[jj * n + tid] = cmk(0, 0);
+      for (int c = 0; c < bw; ++c) pan[c * n + tid] = cfms(pan[c * n + tid], f, rowj[c]);
+    }
+    __syncthreads();
+  }
+}
+
+// The block's row interchanges, in order, on the columns ca, ca + step, ... < cb outside
+// the panel (each column by one thread, so its order needs no barrier).
+__device__ void gj_swaps(cplx *A, long ld, int kb, int bw, const int *piv, int ca, int cb, int step) {
+  for (int c = ca; c < cb; c += step) {
+    if (c >= kb && c < kb + bw) continue;
+    for (int jj = 0; jj < bw; ++jj) {
+      const int j = kb + jj, p = piv[j];
+      if (p != j) {
+        const cplx t = A[j + (long)c * ld];
+        A[j + (long)c * ld] = A[p + (long)c * ld];
+        A[p + (long)c * ld] = t;
+      }
+    }
+  }
+}
+
+// The block's transformation x <- x - E_R x_R + P x_R on the columns c0 .. c0 + cn - 1
+// outside the panel (after the interchanges), this thread's row of -P in pn.
+__device__ void gj_chunk(cplx *A, long ld, int n, int kb, int bw, const cplx (&pn)[GJ_BS], cplx (*Tc)[GJ_CH], int c0,
+                         int cn) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < GJ_BS * GJ_CH; idx += GJ_NT) {
+    const int t = idx % GJ_BS, cc = idx / GJ_BS, c = c0 + cc;
+    Tc[t][cc] = (t < bw && cc < cn) ? A[kb + t + (long)c * ld] : cmk(0, 0);
+  }
+  __syncthreads();
+  // GJ_CU columns at a time: their loads first (a column of the panel, or beyond the
+  // chunk, is skipped), then the products, then the stores
+  const int i = tid;
+  const bool rowr = i >= kb && i < kb + bw;
+  for (int cb = 0; cb < cn; cb += GJ_CU) {
+    cplx acc[GJ_CU];
+#pragma unroll
+    for (int q = 0; q < GJ_CU; ++q) {
+      const int c = c0 + cb + q;
+      const bool live = i < n && cb + q < cn && !(c >= kb && c < kb + bw);
+      acc[q] = (live && !rowr) ? A[i + (long)c * ld] : cmk(0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < GJ_BS; ++t)
+#pragma unroll
+      for (int q = 0; q < GJ_CU; ++q) acc[q] = cfms(acc[q], pn[t], Tc[t][cb + q]);
+#pragma unroll
+    for (int q = 0; q < GJ_CU; ++q) {
+      const int c = c0 + cb + q;
+      if (i < n && cb + q < cn && !(c >= kb && c < kb + bw)) A[i + (long)c * ld] = acc[q];
+    }
+  }
+  __syncthreads();
+}
+
+// One workgroup per matrix, every block step inside (many matrices in a call).
 __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d, int *info) {
   const bm_inv_desc D = d[blockIdx.x];
   const int n = D.n;
@@ -396,143 +525,18 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
   __shared__ cplx s_ip;
   __shared__ double wv[GJ_NT / 64];
   __shared__ int wi[GJ_NT / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   int zinfo = 0;
   for (int kb = 0; kb < n; kb += GJ_BS) {
     const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS;
-    for (int idx = tid; idx < bw * n; idx += GJ_NT) {
-      const int c = idx / n, i = idx - c * n;
-      pan[c * n + i] = A[i + (long)(kb + c) * ld];
-    }
+    gj_panel(A, ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
+    gj_swaps(A, ld, kb, bw, piv, tid, n, GJ_NT);
+    // this thread's row of -P (x + P t as x - (-P) t: exact negation)
+    cplx pn[GJ_BS];
+#pragma unroll
+    for (int t = 0; t < GJ_BS; ++t) pn[t] = (tid < n && t < bw) ? cneg(pan[t * n + tid]) : cmk(0, 0);
     __syncthreads();
-    for (int jj = 0; jj < bw; ++jj) {
-      const int j = kb + jj;
-      // pivot: largest |Re| + |Im| among rows j .. n - 1 of panel column jj (NaNs
-      // never win), the smallest row on ties
-      double bv = -1.0;
-      int bi = n;
-#pragma unroll
-      for (int u = 0; u < GJ_RPT; ++u) {
-        const int i = tid + GJ_NT * u;
-        if (i >= j && i < n) {
-          const cplx v = pan[jj * n + i];
-          const double a = fabs(v.x) + fabs(v.y);
-          if (a > bv) {
-            bv = a;
-            bi = i;
-          }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        wv[wave] = bv;
-        wi[wave] = bi;
-      }
-      __syncthreads();
-      double pv = wv[0];
-      int p = wi[0];
-#pragma unroll
-      for (int w = 1; w < GJ_NT / 64; ++w)
-        if (wv[w] > pv || (wv[w] == pv && wi[w] < p)) {
-          pv = wv[w];
-          p = wi[w];
-        }
-      const bool zero = !(pv > 0.0);
-      if (p >= n) p = j;  // a column of NaNs: no interchange
-      if (tid == 0) {
-        piv[j] = p;
-        if (zero && zinfo == 0) zinfo = j + 1;
-      }
-      if (p != j && tid < bw) {
-        const cplx t = pan[tid * n + j];
-        pan[tid * n + j] = pan[tid * n + p];
-        pan[tid * n + p] = t;
-      }
-      __syncthreads();
-      if (tid == 0) s_ip = zero ? cmk(0, 0) : crecip(pan[jj * n + j]);
-      __syncthreads();
-      if (tid < bw) {
-        cplx v = (tid == jj) ? cmk(1.0, 0.0) : pan[tid * n + j];
-        v = cmul(v, s_ip);
-        rowj[tid] = v;
-        pan[tid * n + j] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < GJ_RPT; ++u) {
-        const int i = tid + GJ_NT * u;
-        if (i < n && i != j) {
-          const cplx f = pan[jj * n + i];
-          pan[jj * n + i] = cmk(0, 0);
-          for (int c = 0; c < bw; ++c) pan[c * n + i] = cfms(pan[c * n + i], f, rowj[c]);
-        }
-      }
-      __syncthreads();
-    }
-    // the block's interchanges on the other columns, in order (each thread owns its
-    // columns, so the order within a column is kept without barriers)
-    for (int c = tid; c < n; c += GJ_NT) {
-      if (c >= kb && c < kb + bw) continue;
-      for (int jj = 0; jj < bw; ++jj) {
-        const int j = kb + jj, p = piv[j];
-        if (p != j) {
-          const cplx t = A[j + (long)c * ld];
-          A[j + (long)c * ld] = A[p + (long)c * ld];
-          A[p + (long)c * ld] = t;
-        }
-      }
-    }
-    // this thread's rows of -P in registers (x + P t as x - (-P) t: exact negation)
-    cplx pn[GJ_RPT][GJ_BS];
-#pragma unroll
-    for (int u = 0; u < GJ_RPT; ++u) {
-      const int i = tid + GJ_NT * u;
-#pragma unroll
-      for (int t = 0; t < GJ_BS; ++t) pn[u][t] = (i < n && t < bw) ? cneg(pan[t * n + i]) : cmk(0, 0);
-    }
-    __syncthreads();
-    for (int c0 = 0; c0 < n; c0 += GJ_CH) {
-      for (int idx = tid; idx < GJ_BS * GJ_CH; idx += GJ_NT) {
-        const int t = idx % GJ_BS, cc = idx / GJ_BS, c = c0 + cc;
-        Tc[t][cc] = (t < bw && c < n) ? A[kb + t + (long)c * ld] : cmk(0, 0);
-      }
-      __syncthreads();
-      // GJ_CU columns at a time: their loads first (a column of the panel, or beyond
-      // the matrix, is skipped), then the products, then the stores
-      const int cend = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
-      for (int cb = 0; cb < cend; cb += GJ_CU) {
-#pragma unroll
-        for (int u = 0; u < GJ_RPT; ++u) {
-          const int i = tid + GJ_NT * u;
-          const bool rowr = i >= kb && i < kb + bw;
-          cplx acc[GJ_CU];
-#pragma unroll
-          for (int q = 0; q < GJ_CU; ++q) {
-            const int c = c0 + cb + q;
-            const bool live = i < n && cb + q < cend && !(c >= kb && c < kb + bw);
-            acc[q] = (live && !rowr) ? A[i + (long)c * ld] : cmk(0, 0);
-          }
-#pragma unroll
-          for (int t = 0; t < GJ_BS; ++t)
-#pragma unroll
-            for (int q = 0; q < GJ_CU; ++q) acc[q] = cfms(acc[q], pn[u][t], Tc[t][cb + q]);
-#pragma unroll
-          for (int q = 0; q < GJ_CU; ++q) {
-            const int c = c0 + cb + q;
-            if (i < n && cb + q < cend && !(c >= kb && c < kb + bw)) A[i + (long)c * ld] = acc[q];
-          }
-        }
-      }
-      __syncthreads();
-    }
+    for (int c0 = 0; c0 < n; c0 += GJ_CH) gj_chunk(A, ld, n, kb, bw, pn, Tc, c0, (n - c0 < GJ_CH) ? n - c0 : GJ_CH);
     for (int idx = tid; idx < bw * n; idx += GJ_NT) {
       const int c = idx / n, i = idx - c * n;
       A[i + (long)(kb + c) * ld] = pan[c * n + i];
@@ -553,12 +557,87 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
   }
 }
 
-int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev) {
+// Few matrices in a call: one launch per block step for the panels (one workgroup
+// per matrix: the eliminated panel back to A, its pivot rows to piv), one for the
+// update (one workgroup per chunk of GJ_CH columns of each matrix), then one for
+// the final column interchanges (one thread per row), so that the updates of a
+// few large blocks spread over many CUs.  The same arithmetic in the same order as
+// gj_inverse_kernel.
+__global__ __launch_bounds__(GJ_NT) void gj_panel_kernel(const bm_inv_desc *d, int *info, int *piv_ws, int max_n,
+                                                          int kb) {
+  const bm_inv_desc D = d[blockIdx.x];
+  const int n = D.n;
+  if (kb >= n) return;
+  extern __shared__ char smem[];
+  cplx *pan = (cplx *)smem;
+  __shared__ cplx rowj[GJ_BS];
+  __shared__ cplx s_ip;
+  __shared__ double wv[GJ_NT / 64];
+  __shared__ int wi[GJ_NT / 64];
+  int *piv = piv_ws + (size_t)blockIdx.x * max_n;
+  const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS;
+  int zinfo = 0;
+  gj_panel(D.A, D.ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
+  for (int idx = threadIdx.x; idx < bw * n; idx += GJ_NT) {
+    const int c = idx / n, i = idx - c * n;
+    D.A[i + (long)(kb + c) * D.ld] = pan[c * n + i];
+  }
+  if (threadIdx.x == 0) {
+    if (kb == 0) info[blockIdx.x] = 0;
+    if (zinfo && info[blockIdx.x] == 0) info[blockIdx.x] = zinfo;
+  }
+}
+
+__global__ __launch_bounds__(GJ_NT) void gj_update_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n, int kb) {
+  const bm_inv_desc D = d[blockIdx.y];
+  const int n = D.n, c0 = blockIdx.x * GJ_CH;
+  if (kb >= n || c0 >= n) return;
+  __shared__ cplx Tc[GJ_BS][GJ_CH];
+  const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS, cn = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
+  const int *piv = piv_ws + (size_t)blockIdx.y * max_n;
+  const int tid = threadIdx.x;
+  if (tid < cn) gj_swaps(D.A, D.ld, kb, bw, piv, c0 + tid, c0 + tid + 1, 1);
+  cplx pn[GJ_BS];
+#pragma unroll
+  for (int t = 0; t < GJ_BS; ++t) pn[t] = (tid < n && t < bw) ? cneg(D.A[tid + (long)(kb + t) * D.ld]) : cmk(0, 0);
+  __syncthreads();
+  gj_chunk(D.A, D.ld, n, kb, bw, pn, Tc, c0, cn);
+}
+
+__global__ __launch_bounds__(GJ_NT) void gj_unswap_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n) {
+  const bm_inv_desc D = d[blockIdx.x];
+  const int n = D.n, i = threadIdx.x;
+  const int *piv = piv_ws + (size_t)blockIdx.x * max_n;
+  if (i >= n) return;
+  for (int j = n - 1; j >= 0; --j) {
+    const int p = piv[j];
+    if (p != j) {
+      const cplx t = D.A[i + (long)j * D.ld];
+      D.A[i + (long)j * D.ld] = D.A[i + (long)p * D.ld];
+      D.A[i + (long)p * D.ld] = t;
+    }
+  }
+}
+
+int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev, int *piv_ws) {
   if (count <= 0) return BM_OK;
-  if (max_n < 1 || max_n > GJ_RPT * GJ_NT) return BM_E_ARG;
+  if (max_n < 1 || max_n > GJ_NT) return BM_E_ARG;
+  if (piv_ws && count <= GJ_SPLIT_MAX) {
+    const size_t lds = sizeof(cplx) * GJ_BS * (size_t)max_n;
+    BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(sizeof(cplx) * GJ_BS * GJ_NT)));
+    const int nch = (max_n + GJ_CH - 1) / GJ_CH;
+    for (int kb = 0; kb < max_n; kb += GJ_BS) {
+      hipLaunchKernelGGL(gj_panel_kernel, dim3(count), dim3(GJ_NT), lds, s, d_dev, info_dev, piv_ws, max_n, kb);
+      hipLaunchKernelGGL(gj_update_kernel, dim3(nch, count), dim3(GJ_NT), 0, s, d_dev, (const int *)piv_ws, max_n, kb);
+    }
+    hipLaunchKernelGGL(gj_unswap_kernel, dim3(count), dim3(GJ_NT), 0, s, d_dev, (const int *)piv_ws, max_n);
+    BM_HIP_TRY(hipGetLastError());
+    return BM_OK;
+  }
   const size_t lds = (sizeof(cplx) * GJ_BS + sizeof(int)) * (size_t)max_n;
   BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)((sizeof(cplx) * GJ_BS + sizeof(int)) * GJ_RPT * GJ_NT)));
+                                 (int)((sizeof(cplx) * GJ_BS + sizeof(int)) * GJ_NT)));
   hipLaunchKernelGGL(gj_inverse_kernel, dim3(count), dim3(GJ_NT), lds, s, d_dev, info_dev);
   BM_HIP_TRY(hipGetLastError());
   return BM_OK;
