@@ -28,7 +28,7 @@
 
 #include "bm_fds.h"
 
-#define BM_FDS_GJ_MAX 512      // explicit inverses up to this order by one workgroup each
+#define BM_FDS_GJ_MAX 512      // explicit inverses up to this order by Gauss-Jordan
 #define BM_FDS_LEAF_MAX 320    // leaf cells of at most this many nodes
 #define BM_FDS_BACKSUB_MAX 128 // interpolation solves up to this rank per thread
 #define BM_FDS_RCHUNK 32       // right-hand sides per solve pass
@@ -291,6 +291,36 @@ struct inv_job {
   int n;
 };
 
+#define BM_FDS_GJ_REFINE_MIN 321  // Gauss-Jordan inverses of this order and above get a Newton-Schulz step
+
+int refine_inverses(bm_fds *f, const std::vector<inv_job> &jobs) {
+  std::vector<bm_copy_desc> cp;
+  std::vector<bm_gemm_desc> g1, g2;
+  tmp_list tl;
+  for (const auto &j : jobs) {
+    if (j.n < BM_FDS_GJ_REFINE_MIN || j.n > BM_FDS_GJ_MAX || j.Ainv == j.A) continue;
+    cplx *X0 = nullptr, *T = nullptr;
+    const size_t nn = (size_t)j.n * j.n;
+    if (!tmp_get(f, tl, (void **)&X0, sizeof(cplx) * nn) || !tmp_get(f, tl, (void **)&T, sizeof(cplx) * nn)) {
+      (void)hipStreamSynchronize(f->stream);
+      tmp_put_all(f, tl);
+      return BM_E_NOMEM;
+    }
+    cp.push_back(copyd(j.Ainv, j.n, X0, j.n, j.n, j.n));
+    g1.push_back(gemm(j.n, j.n, j.n, ONE, j.A, j.n, X0, j.n, ZERO, T, j.n));
+    g2.push_back(gemm(j.n, j.n, j.n, MONE, X0, j.n, T, j.n, cmk(2.0, 0.0), j.Ainv, j.n));
+  }
+  int rc = BM_OK;
+  if (!cp.empty()) {
+    rc = run_copies(f, cp);
+    if (!rc) rc = run_gemms(f, g1);
+    if (!rc) rc = run_gemms(f, g2);
+  }
+  (void)hipStreamSynchronize(f->stream);
+  tmp_put_all(f, tl);
+  return rc;
+}
+
 int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
   hipStream_t s = f->stream;
   std::vector<bm_inv_desc> small;
@@ -335,6 +365,10 @@ int invert(bm_fds *f, const std::vector<inv_job> &jobs) {
                                small[q].n, hi[q]);
         return BM_E_DEVICE;  // an exactly singular block
       }
+    // Gauss-Jordan loses accuracy on the larger, worse-conditioned blocks of the
+    // upper levels: there one Newton-Schulz step X <- 2X - X A X (the error of X
+    // squared) with the original block, T = A X0 and X = -X0 T + 2 X, X0 a copy of X
+    if (int rc2 = refine_inverses(f, jobs)) return rc2;
   }
   if (nmax_big > 0) {
     bm_getrf_ws *w = bm_getrf_ws_create(nmax_big);
