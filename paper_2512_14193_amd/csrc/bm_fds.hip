@@ -28,7 +28,7 @@
 
 #include "bm_fds.h"
 
-#define BM_FDS_GJ_MAX 512      // explicit inverses up to this order by Gauss-Jordan
+#define BM_FDS_GJ_MAX 1024     // explicit inverses up to this order by Gauss-Jordan
 #define BM_FDS_LEAF_MAX 320    // leaf cells of at most this many nodes
 #define BM_FDS_BACKSUB_MAX 128 // interpolation solves up to this rank per thread
 #define BM_FDS_RCHUNK 32       // right-hand sides per solve pass

@@ -376,20 +376,23 @@ int bm_fds_cpqr_scatter(hipStream_t s, int nprob, const bm_qr_prob *pr, bm_qr_st
 // P = the eliminated panel; every other column x receives it at once after the
 // block's row interchanges, x <- x - E_R x_R + P x_R.  So the matrix is read and
 // written once per GJ_BS pivots instead of once per pivot.  Row interchanges are
-// recorded and undone on the columns at the end.  Orders up to GJ_NT.
+// recorded and undone on the columns at the end.  Orders up to GJ_NT2.
 // ---------------------------------------------------------------------------
-#define GJ_NT 512  // threads: one row each (orders up to GJ_NT)
-#define GJ_BS 16   // pivots per block
+#define GJ_NT 512  // threads of the one-workgroup kernel: one row each (orders up to GJ_NT)
+#define GJ_BS 16   // its pivots per block
+#define GJ_NT2 1024  // the split path above GJ_NT: threads (rows) and pivots per block
+#define GJ_BS2 8
 #define GJ_CH 64   // columns per chunk of the block's update
 #define GJ_CU 2    // columns of the block's update whose loads are in flight together
 #define GJ_SPLIT_MAX 32  // up to this many blocks in a call: one launch per block step
 
 // The block's panel (columns kb .. kb + bw - 1 of A) into pan (column c at pan + c n)
 // and eliminated there; the pivot rows go to piv[kb ..], the first zero pivot to zinfo.
+template <int NT, int BS>
 __device__ void gj_panel(cplx *A, long ld, int n, int kb, int bw, cplx *pan, int *piv, cplx *rowj, cplx *s_ip,
                          double *wv, int *wi, int &zinfo) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < bw * n; idx += GJ_NT) {
+  for (int idx = tid; idx < bw * n; idx += NT) {
     const int c = idx / n, i = idx - c * n;
     pan[c * n + i] = A[i + (long)(kb + c) * ld];
   }
@@ -425,7 +428,7 @@ __device__ void gj_panel(cplx *A, long ld, int n, int kb, int bw, cplx *pan, int
     double pv = wv[0];
     int p = wi[0];
 #pragma unroll
-    for (int w = 1; w < GJ_NT / 64; ++w)
+    for (int w = 1; w < NT / 64; ++w)
       if (wv[w] > pv || (wv[w] == pv && wi[w] < p)) {
         pv = wv[w];
         p = wi[w];
@@ -462,6 +465,7 @@ __device__ void gj_panel(cplx *A, long ld, int n, int kb, int bw, cplx *pan, int
 
 // The block's row interchanges, in order, on the columns ca, ca + step, ... < cb outside
 // the panel (each column by one thread, so its order needs no barrier).
+template <int NT, int BS>
 __device__ void gj_swaps(cplx *A, long ld, int kb, int bw, const int *piv, int ca, int cb, int step) {
   for (int c = ca; c < cb; c += step) {
     if (c >= kb && c < kb + bw) continue;
@@ -478,11 +482,12 @@ __device__ void gj_swaps(cplx *A, long ld, int kb, int bw, const int *piv, int c
 
 // The block's transformation x <- x - E_R x_R + P x_R on the columns c0 .. c0 + cn - 1
 // outside the panel (after the interchanges), this thread's row of -P in pn.
-__device__ void gj_chunk(cplx *A, long ld, int n, int kb, int bw, const cplx (&pn)[GJ_BS], cplx (*Tc)[GJ_CH], int c0,
+template <int NT, int BS>
+__device__ void gj_chunk(cplx *A, long ld, int n, int kb, int bw, const cplx (&pn)[BS], cplx (*Tc)[GJ_CH], int c0,
                          int cn) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < GJ_BS * GJ_CH; idx += GJ_NT) {
-    const int t = idx % GJ_BS, cc = idx / GJ_BS, c = c0 + cc;
+  for (int idx = tid; idx < BS * GJ_CH; idx += NT) {
+    const int t = idx % BS, cc = idx / BS, c = c0 + cc;
     Tc[t][cc] = (t < bw && cc < cn) ? A[kb + t + (long)c * ld] : cmk(0, 0);
   }
   __syncthreads();
@@ -499,7 +504,7 @@ __device__ void gj_chunk(cplx *A, long ld, int n, int kb, int bw, const cplx (&p
       acc[q] = (live && !rowr) ? A[i + (long)c * ld] : cmk(0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < GJ_BS; ++t)
+    for (int t = 0; t < BS; ++t)
 #pragma unroll
       for (int q = 0; q < GJ_CU; ++q) acc[q] = cfms(acc[q], pn[t], Tc[t][cb + q]);
 #pragma unroll
@@ -529,14 +534,14 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
   int zinfo = 0;
   for (int kb = 0; kb < n; kb += GJ_BS) {
     const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS;
-    gj_panel(A, ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
-    gj_swaps(A, ld, kb, bw, piv, tid, n, GJ_NT);
+    gj_panel<GJ_NT, GJ_BS>(A, ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
+    gj_swaps<GJ_NT, GJ_BS>(A, ld, kb, bw, piv, tid, n, GJ_NT);
     // this thread's row of -P (x + P t as x - (-P) t: exact negation)
     cplx pn[GJ_BS];
 #pragma unroll
     for (int t = 0; t < GJ_BS; ++t) pn[t] = (tid < n && t < bw) ? cneg(pan[t * n + tid]) : cmk(0, 0);
     __syncthreads();
-    for (int c0 = 0; c0 < n; c0 += GJ_CH) gj_chunk(A, ld, n, kb, bw, pn, Tc, c0, (n - c0 < GJ_CH) ? n - c0 : GJ_CH);
+    for (int c0 = 0; c0 < n; c0 += GJ_CH) gj_chunk<GJ_NT, GJ_BS>(A, ld, n, kb, bw, pn, Tc, c0, (n - c0 < GJ_CH) ? n - c0 : GJ_CH);
     for (int idx = tid; idx < bw * n; idx += GJ_NT) {
       const int c = idx / n, i = idx - c * n;
       A[i + (long)(kb + c) * ld] = pan[c * n + i];
@@ -563,22 +568,23 @@ __global__ __launch_bounds__(GJ_NT) void gj_inverse_kernel(const bm_inv_desc *d,
 // the final column interchanges (one thread per row), so that the updates of a
 // few large blocks spread over many CUs.  The same arithmetic in the same order as
 // gj_inverse_kernel.
-__global__ __launch_bounds__(GJ_NT) void gj_panel_kernel(const bm_inv_desc *d, int *info, int *piv_ws, int max_n,
+template <int NT, int BS>
+__global__ __launch_bounds__(NT) void gj_panel_kernel(const bm_inv_desc *d, int *info, int *piv_ws, int max_n,
                                                           int kb) {
   const bm_inv_desc D = d[blockIdx.x];
   const int n = D.n;
   if (kb >= n) return;
   extern __shared__ char smem[];
   cplx *pan = (cplx *)smem;
-  __shared__ cplx rowj[GJ_BS];
+  __shared__ cplx rowj[BS];
   __shared__ cplx s_ip;
-  __shared__ double wv[GJ_NT / 64];
-  __shared__ int wi[GJ_NT / 64];
+  __shared__ double wv[NT / 64];
+  __shared__ int wi[NT / 64];
   int *piv = piv_ws + (size_t)blockIdx.x * max_n;
-  const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS;
+  const int bw = (n - kb < BS) ? n - kb : BS;
   int zinfo = 0;
-  gj_panel(D.A, D.ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
-  for (int idx = threadIdx.x; idx < bw * n; idx += GJ_NT) {
+  gj_panel<NT, BS>(D.A, D.ld, n, kb, bw, pan, piv, rowj, &s_ip, wv, wi, zinfo);
+  for (int idx = threadIdx.x; idx < bw * n; idx += NT) {
     const int c = idx / n, i = idx - c * n;
     D.A[i + (long)(kb + c) * D.ld] = pan[c * n + i];
   }
@@ -588,23 +594,25 @@ __global__ __launch_bounds__(GJ_NT) void gj_panel_kernel(const bm_inv_desc *d, i
   }
 }
 
-__global__ __launch_bounds__(GJ_NT) void gj_update_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n, int kb) {
+template <int NT, int BS>
+__global__ __launch_bounds__(NT) void gj_update_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n, int kb) {
   const bm_inv_desc D = d[blockIdx.y];
   const int n = D.n, c0 = blockIdx.x * GJ_CH;
   if (kb >= n || c0 >= n) return;
-  __shared__ cplx Tc[GJ_BS][GJ_CH];
-  const int bw = (n - kb < GJ_BS) ? n - kb : GJ_BS, cn = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
+  __shared__ cplx Tc[BS][GJ_CH];
+  const int bw = (n - kb < BS) ? n - kb : BS, cn = (n - c0 < GJ_CH) ? n - c0 : GJ_CH;
   const int *piv = piv_ws + (size_t)blockIdx.y * max_n;
   const int tid = threadIdx.x;
-  if (tid < cn) gj_swaps(D.A, D.ld, kb, bw, piv, c0 + tid, c0 + tid + 1, 1);
-  cplx pn[GJ_BS];
+  if (tid < cn) gj_swaps<NT, BS>(D.A, D.ld, kb, bw, piv, c0 + tid, c0 + tid + 1, 1);
+  cplx pn[BS];
 #pragma unroll
-  for (int t = 0; t < GJ_BS; ++t) pn[t] = (tid < n && t < bw) ? cneg(D.A[tid + (long)(kb + t) * D.ld]) : cmk(0, 0);
+  for (int t = 0; t < BS; ++t) pn[t] = (tid < n && t < bw) ? cneg(D.A[tid + (long)(kb + t) * D.ld]) : cmk(0, 0);
   __syncthreads();
-  gj_chunk(D.A, D.ld, n, kb, bw, pn, Tc, c0, cn);
+  gj_chunk<NT, BS>(D.A, D.ld, n, kb, bw, pn, Tc, c0, cn);
 }
 
-__global__ __launch_bounds__(GJ_NT) void gj_unswap_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n) {
+template <int NT, int BS>
+__global__ __launch_bounds__(NT) void gj_unswap_kernel(const bm_inv_desc *d, const int *piv_ws, int max_n) {
   const bm_inv_desc D = d[blockIdx.x];
   const int n = D.n, i = threadIdx.x;
   const int *piv = piv_ws + (size_t)blockIdx.x * max_n;
@@ -619,22 +627,27 @@ __global__ __launch_bounds__(GJ_NT) void gj_unswap_kernel(const bm_inv_desc *d, 
   }
 }
 
+template <int NT, int BS>
+static int gj_split(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev, int *piv_ws) {
+  const size_t lds = sizeof(cplx) * BS * (size_t)max_n;
+  BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_panel_kernel<NT, BS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(sizeof(cplx) * BS * NT)));
+  const int nch = (max_n + GJ_CH - 1) / GJ_CH;
+  for (int kb = 0; kb < max_n; kb += BS) {
+    hipLaunchKernelGGL((gj_panel_kernel<NT, BS>), dim3(count), dim3(NT), lds, s, d_dev, info_dev, piv_ws, max_n, kb);
+    hipLaunchKernelGGL((gj_update_kernel<NT, BS>), dim3(nch, count), dim3(NT), 0, s, d_dev, (const int *)piv_ws,
+                       max_n, kb);
+  }
+  hipLaunchKernelGGL((gj_unswap_kernel<NT, BS>), dim3(count), dim3(NT), 0, s, d_dev, (const int *)piv_ws, max_n);
+  BM_HIP_TRY(hipGetLastError());
+  return BM_OK;
+}
+
 int bm_fds_gj_inverse(hipStream_t s, int count, const bm_inv_desc *d_dev, int max_n, int *info_dev, int *piv_ws) {
   if (count <= 0) return BM_OK;
-  if (max_n < 1 || max_n > GJ_NT) return BM_E_ARG;
-  if (piv_ws && count <= GJ_SPLIT_MAX) {
-    const size_t lds = sizeof(cplx) * GJ_BS * (size_t)max_n;
-    BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(sizeof(cplx) * GJ_BS * GJ_NT)));
-    const int nch = (max_n + GJ_CH - 1) / GJ_CH;
-    for (int kb = 0; kb < max_n; kb += GJ_BS) {
-      hipLaunchKernelGGL(gj_panel_kernel, dim3(count), dim3(GJ_NT), lds, s, d_dev, info_dev, piv_ws, max_n, kb);
-      hipLaunchKernelGGL(gj_update_kernel, dim3(nch, count), dim3(GJ_NT), 0, s, d_dev, (const int *)piv_ws, max_n, kb);
-    }
-    hipLaunchKernelGGL(gj_unswap_kernel, dim3(count), dim3(GJ_NT), 0, s, d_dev, (const int *)piv_ws, max_n);
-    BM_HIP_TRY(hipGetLastError());
-    return BM_OK;
-  }
+  if (max_n < 1 || max_n > GJ_NT2 || (max_n > GJ_NT && !piv_ws)) return BM_E_ARG;
+  if (max_n > GJ_NT) return gj_split<GJ_NT2, GJ_BS2>(s, count, d_dev, max_n, info_dev, piv_ws);
+  if (piv_ws && count <= GJ_SPLIT_MAX) return gj_split<GJ_NT, GJ_BS>(s, count, d_dev, max_n, info_dev, piv_ws);
   const size_t lds = (sizeof(cplx) * GJ_BS + sizeof(int)) * (size_t)max_n;
   BM_HIP_TRY(hipFuncSetAttribute((const void *)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)((sizeof(cplx) * GJ_BS + sizeof(int)) * GJ_NT)));
