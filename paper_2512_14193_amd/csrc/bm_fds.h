@@ -5,6 +5,7 @@
 
 // rows of a column-pivoted QR target held in LDS by the step kernel
 #define BM_FDS_QR_MAX_ROWS 8192
+#define BM_FDS_QR_CW 32  // columns of a QR problem per workgroup
 
 // One column-pivoted QR problem (device array of these).
 struct bm_qr_prob {

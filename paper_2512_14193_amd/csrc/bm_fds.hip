@@ -570,7 +570,7 @@ int compress_level(bm_fds *f, std::vector<fds_cell> &cells) {
     P.kmin = 0;
     P.kcap = std::min(q.M, q.C);
     P.wg0 = nwg;
-    P.wgs = std::max(1, (q.C + 63) / 64);
+    P.wgs = std::max(1, (q.C + BM_FDS_QR_CW - 1) / BM_FDS_QR_CW);
     work_elems += (long)q.M * q.C;
     ncol += q.C;
     npiv += P.kcap;

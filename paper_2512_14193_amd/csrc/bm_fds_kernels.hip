@@ -23,8 +23,8 @@
 // that a launch reads what the previous one wrote: each workgroup's best column
 // (value, index) and the problem's step counter.
 // ---------------------------------------------------------------------------
-#define QR_NT 256
-#define QR_CW 64  // columns per workgroup
+#define QR_NT 1024
+#define QR_CW BM_FDS_QR_CW  // columns per workgroup
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
