@@ -1462,7 +1462,9 @@ static int sp_plan(int n, int k, int ncu, int gs, size_t w_cap, sp_seg *seg, int
         bt = t;
       }
     }
-    if (nseg == SP_MAXSEG - 1) {  // the last segment takes the rest
+    // the last segment takes the rest; so does a segment that would leave a single
+    // block, which alone would need a catch-up step for every panel before it
+    if (nseg == SP_MAXSEG - 1 || (B - f - best == 1 && nseg >= 2)) {
       best = B - f;
       bks = sp_ksplit(tb * best, gs, k, w_cap);
       bt = sp_time(tb * best, bks, gs, k, per_k1);
