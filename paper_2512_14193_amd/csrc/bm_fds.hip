@@ -80,6 +80,13 @@ struct bm_fds {
   int root_max = 4096;       // order up to which a level's compressed system is the root
   int top = 1;               // the level whose cells make up the root
   std::vector<long> root_off;  // offset of each top-level cell's skeletons in the root
+  // a root above the Gauss-Jordan limit: its LU in place of its block, kept for the
+  // solve (two triangular solves per pass instead of the product with an inverse)
+  bool root_lu = false;
+  bm_getrf_ws *root_ws = nullptr;
+  int root_ws_n = 0;
+  int32_t *root_ipiv = nullptr, *root_perm = nullptr;
+  cplx *root_dinv = nullptr;
   // scratch reused by the solve
   std::vector<bm_gemm_desc> hg;
   bm_gemm_desc *dg = nullptr;
@@ -1042,6 +1049,35 @@ int factor_all(bm_fds *f) {
   // root: the dense compressed system of the top level's cells
   fds_cell &root = f->lv[0][0];
   f->root_n = root.m;
+  f->root_lu = root.m > BM_FDS_GJ_MAX;
+  if (f->root_lu) {
+    const int m = root.m;
+    if (f->root_ws && f->root_ws_n < m) {
+      bm_getrf_ws_destroy(f->root_ws);
+      f->root_ws = nullptr;
+    }
+    if (!f->root_ws) {
+      f->root_ws = bm_getrf_ws_create(m);
+      if (!f->root_ws) return BM_E_NOMEM;
+      f->root_ws_n = m;
+    }
+    const size_t nblk = (size_t)(m + BM_DIAG_NB - 1) / BM_DIAG_NB;
+    if (int rc = dmalloc(f, &f->root_ipiv, (size_t)m)) return rc;
+    if (int rc = dmalloc(f, &f->root_perm, (size_t)m)) return rc;
+    if (int rc = dmalloc(f, &f->root_dinv, nblk * BM_DINV_TILES * BM_DIAG_NB * BM_DIAG_NB)) return rc;
+    hipStream_t s = f->stream;
+    if (int rc = bm_getrf_run(s, m, root.Abar, m, f->root_ipiv, f->dev_err, f->root_ws, 0)) return rc;
+    if (int rc = bm_launch_diag_inverses(s, m, root.Abar, m, f->root_dinv)) return rc;
+    if (int rc = bm_launch_perm(s, f->root_ws, m, f->root_perm)) return rc;
+    int32_t h[2] = {0, 0};
+    BM_HIP_TRY(hipStreamSynchronize(s));
+    BM_HIP_TRY(hipMemcpy(h, f->dev_err, sizeof(h), hipMemcpyDeviceToHost));
+    if (h[0] || h[1]) {
+      if (verbose()) fprintf(stderr, "[bm_fds] root LU: error flag %d, zero pivot %d\n", h[0], h[1]);
+      return BM_E_DEVICE;  // a bounded wait expired, or an exactly singular root
+    }
+    return BM_OK;
+  }
   if (int rc = dmalloc(f, &root.Ainv, (size_t)root.m * root.m)) return rc;
   inv_job j;
   j.A = root.Abar;
@@ -1120,7 +1156,13 @@ int solve_chunk(bm_fds *f, int nr, const cplx *B, long ldb, cplx *X, long ldx) {
     if (int rc = run_gemms(f, h2)) return rc;
   }
   // root
-  {
+  if (f->root_lu) {
+    const int m = root.m;
+    if (int rc = bm_launch_gather(s, m, nr, f->root_perm, root.fb, m, root.xb, m)) return rc;
+    if (int rc = bm_trsv_reset(s, f->root_ws, m)) return rc;
+    if (int rc = bm_launch_trsv(s, f->root_ws, 1, m, root.Abar, m, f->root_dinv, root.xb, m, nr, f->dev_err)) return rc;
+    if (int rc = bm_launch_trsv(s, f->root_ws, 0, m, root.Abar, m, f->root_dinv, root.xb, m, nr, f->dev_err)) return rc;
+  } else {
     std::vector<bm_gemm_desc> g{gemm(root.m, nr, root.m, ONE, root.Ainv, root.m, root.fb, root.m, ZERO, root.xb,
                                      root.m)};
     if (int rc = run_gemms(f, g)) return rc;
@@ -1209,6 +1251,7 @@ void bm_fds_destroy(bm_fds *f) {
   (void)hipStreamSynchronize(f->stream);
   free_factor_memory(f);
   release_spare(f, LONG_MAX);
+  if (f->root_ws) bm_getrf_ws_destroy(f->root_ws);
   for (void *p : f->mem_fixed) (void)hipFree(p);
   if (f->dg) (void)hipFree(f->dg);
   if (f->dc) (void)hipFree(f->dc);
@@ -1265,6 +1308,11 @@ int bm_fds_solve(bm_fds *f, int32_t nrhs, const void *B, int64_t ldb, void *X, i
     const int nr = std::min(BM_FDS_RCHUNK, nrhs - r0);
     if (int rc = solve_chunk(f, nr, (const cplx *)B + (size_t)r0 * ldb, ldb, (cplx *)X + (size_t)r0 * ldx, ldx))
       return rc;
+  }
+  if (f->root_lu && nrhs > 0) {  // the root's triangular solves wait (bounded) for each other's blocks
+    int32_t h = 0;
+    BM_HIP_TRY(hipMemcpy(&h, f->dev_err, sizeof(h), hipMemcpyDeviceToHost));
+    if (h) return BM_E_DEVICE;
   }
   return BM_OK;
 }
