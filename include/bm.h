@@ -543,13 +543,19 @@ typedef struct {
  * BM_E_HIP. */
 int bm_fds_create(int32_t n, const bm_fds_config *cfg, void *hip_stream, bm_fds **out);
 /* Compress and factor the mixed system for this geometry and these parameters (as
- * bm_assemble).  Synchronous (the tree's index lists live on the host).  Errors:
- * BM_E_ARG (as bm_assemble, a wavenumber below the sector, a proxy target of more
- * than 8192 rows), BM_E_NOMEM, BM_E_HIP, BM_E_DEVICE (an exactly singular block). */
+ * bm_assemble).  Synchronous (the tree's index lists live on the host).  Device
+ * buffers are kept between factorisations and handed out again by size: the previous
+ * factors become spares for this call, which frees the spares it did not take and
+ * keeps its own temporary buffers (the largest: the leaves' QR workspace) for the
+ * next call; so between calls the solver holds its factors plus those temporaries.
+ * Errors: BM_E_ARG (as bm_assemble, a wavenumber below the sector, a proxy target of
+ * more than 8192 rows), BM_E_NOMEM, BM_E_HIP, BM_E_DEVICE (an exactly singular block,
+ * or a bounded wait of the root's factorisation expired). */
 int bm_fds_factor(bm_fds *f, const bm_geometry *geometry, const bm_params *params);
 /* X = A^{-1} B for nrhs right-hand sides (3N x nrhs, column-major, ld >= 3N, X not
  * aliasing B), through the compressed factorisation.  Synchronous.
- * Errors: BM_E_STATE before bm_fds_factor, BM_E_ARG. */
+ * Errors: BM_E_STATE before bm_fds_factor, BM_E_ARG, BM_E_DEVICE (a bounded wait of
+ * the root's triangular solves expired). */
 int bm_fds_solve(bm_fds *f, int32_t nrhs, const void *B, int64_t ldb, void *X, int64_t ldx);
 /* Plane-wave right-hand sides and far field, as bm_rhs_plane_wave and bm_far_field. */
 int bm_fds_rhs_plane_wave(bm_fds *f, int32_t nrhs, const double *theta_inc, void *B, int64_t ldb);
@@ -558,7 +564,8 @@ int bm_fds_far_field(bm_fds *f, int32_t nrhs, const void *X, int64_t ldx, int32_
 /* Host outputs: the number of levels L; for every level l = 0..L (l = L the leaves)
  * the sum and the largest number of skeletons of its cells (skel_sum, skel_max: host
  * arrays of at least L + 1 entries; level 0 holds 0); the order of the dense root
- * system; the device bytes held.  Errors: BM_E_STATE before bm_fds_factor. */
+ * system; the device bytes of the factors (the kept temporaries not counted).
+ * Errors: BM_E_STATE before bm_fds_factor. */
 int bm_fds_info(bm_fds *f, int32_t *levels, int32_t *skel_sum, int32_t *skel_max, int32_t *root_n,
                 int64_t *bytes);
 /* Release the solver and its device memory (after synchronising its stream). */
