@@ -211,3 +211,32 @@ def test_fds_fullsize_residual_on_sampled_rows(ellipse65536):
     ratio = np.abs(r) / np.linalg.norm(Bh, axis=0)[None, :]
     print(f"[fds] full size: max |r_i| / ||b|| = {ratio.max():.3e}", flush=True)
     assert ratio.max() <= 1e-8, ratio.max()
+
+
+def test_fds_refactor_reuses_buffers_bitwise():
+    """A handle factored again (other wavenumbers: other ranks, some buffer sizes
+    differ) and then at the first ones: its device buffers come from the previous
+    factorisation where the sizes match, which must not change a bit of the result:
+    each solve equals that of a fresh handle factored once at the same parameters."""
+    bnd = I.ellipse(1024, 10.0, 1.0)
+    ph1 = I.Physics.from_wavenumbers(6.0, 9.0)
+    ph2 = I.Physics.from_wavenumbers(9.0 + 0.2j, 13.5 + 0.3j)
+    rhs = to_dev(I.probing_rhs(3 * 1024, 3, 21))
+    g = geo(bnd)
+
+    def fresh(ph):
+        f = B.FDS(1024, leaf=64, n_proxy=64, tol=1e-10)
+        f.factor(g, ph)
+        X = to_np(f.solve(rhs))
+        info = f.info()
+        f.close()
+        return X, info
+
+    X1, i1 = fresh(ph1)
+    X2, i2 = fresh(ph2)
+    assert i1["skeletons_sum"] != i2["skeletons_sum"]  # the two factorisations differ in their sizes
+    h = B.FDS(1024, leaf=64, n_proxy=64, tol=1e-10)
+    for ph, Xref in ((ph1, X1), (ph2, X2), (ph1, X1), (ph1, X1)):
+        h.factor(g, ph)
+        assert np.array_equal(to_np(h.solve(rhs)), Xref)
+    h.close()
