@@ -449,7 +449,9 @@ typedef struct {
   double t_submit;           /* host steady (monotonic) clock, seconds: submission */
   double t_start;            /* ... the request's work was enqueued on the device */
   double t_done;             /* ... the server saw the request's work complete    */
-  double device_ms;          /* device time of the request's work (HIP events)    */
+  double device_ms;          /* device time of the request's work (HIP events); for
+                                a size above concurrent_max_n it includes the wait,
+                                after its assembly, for the other lanes' work     */
   int32_t batched;           /* requests factored together with it (itself counted;
                                 1: alone), see config.batch_max                    */
 } bm_request_result;

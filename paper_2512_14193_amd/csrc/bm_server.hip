@@ -5,10 +5,10 @@
 // enqueues each one's work on a lane (assembly, factorisation, solve, error-flag
 // readback, two timing events) and polls the completion events of the requests
 // in flight.  Requests with N <= concurrent_max_n run side by side on different
-// lanes; a larger request is fenced on the device against every other lane (it
-// waits for the work already enqueued there), so that it assembles and forms its
-// Schur complement alone; later requests wait for that, not for its LU, which
-// runs beside them.  The host enqueues up to max_inflight requests per lane
+// lanes; a larger request is fenced on the device against every other lane
+// after its assembly (it then waits for the work already enqueued there), so that
+// it forms its Schur complement alone; later requests wait for that, not for its
+// LU, which runs beside them.  The host enqueues up to max_inflight requests per lane
 // ahead, so the device never waits for the host.  (The lanes' streams only run
 // side by side if the process has enough hardware queues: GPU_MAX_HW_QUEUES.)
 //
@@ -280,9 +280,13 @@ int enqueue(bm_server *s, srv_request *rq) {
   srv_handle *h = rq->h;
   const hipStream_t st = s->lanes[rq->lane].stream;
   const int64_t rows = 3 * (int64_t)r.n;
-  if (int rc = fence(s, rq)) return rc;
-  BM_HIP_TRY(hipEventRecord(s->ev_start[rq->slot], st));
   const bool reuse = r.reuse_key != 0 && h->factored && same_params(h->prm, r.params);
+  // a large request's assembly (vector work on its own buffers) runs beside the
+  // other lanes' work; its product, LU and solve wait for them
+  const bool late_fence = !reuse && !is_small(s, r.n);
+  if (!late_fence)
+    if (int rc = fence(s, rq)) return rc;
+  BM_HIP_TRY(hipEventRecord(s->ev_start[rq->slot], st));
   int rc = BM_OK;
   if (reuse) {
     rc = bm_solve(h->p, r.nrhs, r.B, r.ldb, r.X, r.ldx);
@@ -291,6 +295,8 @@ int enqueue(bm_server *s, srv_request *rq) {
     h->factored = false;
     rc = bm_assemble(h->p, &r.geometry, &r.params);
     if (rc) return rc;
+    if (late_fence)
+      if (int rc2 = fence(s, rq)) return rc2;
     const bool want_graph = r.n <= s->graph_max_n && !h->graph_failed;
     if (want_graph && h->gexec && h->graph_nrhs != r.nrhs) {
       (void)hipGraphExecDestroy(h->gexec);  // captured for another block width
