@@ -315,9 +315,9 @@ int enqueue(bm_server *s, srv_request *rq) {
                                   r.nrhs, hipMemcpyDeviceToDevice, st));
       rq->res.graph = 1;
     } else {
-      // a large request holds the device alone only while it assembles and forms
-      // U33; the small requests after it start beside its LU (the panels of the
-      // lanes together stay within half the CUs, see bm_server_create)
+      // a large request holds the device alone only while it forms U33; the small
+      // requests after it start beside its LU (the panels of the lanes together
+      // stay within half the CUs, see bm_server_create)
       const bool big = !is_small(s, r.n) && s->lanes.size() > 1;
       if (big) h->p->after_schur = s->big_fence;
       rc = bm_block_lu(h->p, nullptr);
