@@ -77,10 +77,11 @@ def contour_mix():
 
 @pytest.mark.parametrize("graph_max_n,lanes,concurrent_max_n,batch_max",
                          [(0, 1, 1024, 1), (256, 4, 1024, 1), (0, 4, 1024, 1), (256, 3, 128, 1), (0, 2, 512, 4),
-                          (128, 3, 512, 2)])
+                          (128, 3, 512, 2), (0, 3, 128, 2)])
 def test_alone_equals_mix_equals_direct(graph_max_n, lanes, concurrent_max_n, batch_max):
     """lanes > 1: requests with N <= concurrent_max_n run concurrently, larger
-    ones (N = 192, 256 when concurrent_max_n = 128) are fenced to run alone.  With
+    ones (N = 192, 256 when concurrent_max_n = 128) are fenced to run alone after
+    their assembly (eagerly, or through a replayed graph when graph_max_n covers them).  With
     batch_max > 1, queued requests of one N are factored together (up to four at
     N = 128, two at N = 192 and 256 with a lane share of eight panel workgroups);
     every result is still bitwise the direct one."""
